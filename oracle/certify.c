@@ -1,0 +1,161 @@
+/*
+ * Max-flow/min-cut certificate checker.  TEST INFRASTRUCTURE ONLY (see
+ * oracle.c).  It verifies, at any problem size and in O(n), that a solver's
+ * final state is a maximum preflow and that the reported surface is the
+ * inclusion-minimal minimum cut:
+ *
+ *   - capacity and sign bounds of every arc (Eq. 2);
+ *   - the excess of every node equals inflow minus outflow (Eq. 8) and is
+ *     non-negative, so the state is a preflow;
+ *   - the surface is delta-smooth (Section 1.2, proper-ordered columns);
+ *   - the set R reachable in the residual graph from every node with
+ *     positive excess does not contain the sink and its column heights equal
+ *     the surface.  Then no residual arc leaves R, the flow value equals the
+ *     capacity of the cut (R, complement) (Theorem 1.1), and R is contained
+ *     in every minimum cut, i.e. it is the minimal one.
+ *
+ * The arc set checked is the one the solver stores: the down arc
+ * (p,z)->(p,z-1) for z >= 1, and for each 4-neighbour q of p the lateral arc
+ * (p,z)->(q,z-delta) when z > delta, plus (p,0)->(q,0).  The omitted arcs
+ * (p,z)->(q,0) for 1 <= z <= delta are implied by (p,z)->(p,0)->(q,0), so
+ * the closed sets, the cut capacities and the max-flow value are those of
+ * the full graph of oracle.c.  Flows are stored per arc at the arc's tail.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int64_t flow;
+    int64_t cut;
+    int64_t energy;
+    int64_t bad_capacity;
+    int64_t bad_conservation;
+    int64_t bad_smooth;
+    int64_t bad_reach;
+    int32_t status;
+    int32_t pad;
+} cert_result;
+
+static int lat_arc_exists(int64_t z, int64_t delta) { return z == 0 || z > delta; }
+static int64_t lat_target(int64_t z, int64_t delta) { return z == 0 ? 0 : z - delta; }
+
+int certify_preflow(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_,
+                    int32_t delta_, const int32_t *excess, const int32_t *sink_res,
+                    const int32_t *flow_down, const int32_t *flow_lat,
+                    const int32_t *surface, cert_result *out)
+{
+    memset(out, 0, sizeof(*out));
+    const int64_t nx = nx_, ny = ny_, K = K_, delta = delta_;
+    if (nx < 1 || ny < 1 || K < 1 || delta < 0) return out->status = -1;
+    const int64_t N = nx * ny * K, P = nx * ny;
+    static const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+
+    int64_t B = INT64_MIN;
+    for (int64_t p = 0; p < P; ++p)
+        if (cost[p * K] > B) B = cost[p * K];
+    B += 1;
+
+    int64_t *net = calloc((size_t)N, sizeof(int64_t));
+    uint8_t *mark = calloc((size_t)N, 1);
+    int64_t *queue = malloc((size_t)N * sizeof(int64_t));
+    if (!net || !mark || !queue) {
+        free(net); free(mark); free(queue);
+        return out->status = -2;
+    }
+
+    /* Arc flows: bounds, and net inflow per node. */
+    for (int64_t x = 0; x < nx; ++x)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t z = 0; z < K; ++z) {
+                int64_t v = (x * ny + y) * K + z;
+                int64_t fd = flow_down[v];
+                if (fd < 0 || (z == 0 && fd != 0)) out->bad_capacity++;
+                if (z > 0) { net[v] -= fd; net[v - 1] += fd; }
+                for (int k = 0; k < 4; ++k) {
+                    int64_t f = flow_lat[(int64_t)k * N + v];
+                    int64_t qx = x + dx[k], qy = y + dy[k];
+                    int in = qx >= 0 && qx < nx && qy >= 0 && qy < ny;
+                    if (!in || !lat_arc_exists(z, delta)) {
+                        if (f != 0) out->bad_capacity++;
+                        continue;
+                    }
+                    if (f < 0) out->bad_capacity++;
+                    int64_t u = (qx * ny + qy) * K + lat_target(z, delta);
+                    net[v] -= f; net[u] += f;
+                }
+            }
+
+    /* Terminal arcs: the source arcs are saturated (the solver never returns
+     * flow to s), the sink arc keeps residual sink_res. */
+    for (int64_t v = 0; v < N; ++v) {
+        int64_t z = v % K;
+        int64_t w = z == 0 ? (int64_t)cost[v] - B : (int64_t)cost[v] - cost[v - 1];
+        int64_t src = w < 0 ? -w : 0, snk = w > 0 ? w : 0;
+        int64_t r = sink_res[v];
+        if (r < 0 || r > snk) out->bad_capacity++;
+        out->flow += snk - r;
+        int64_t e = excess[v];
+        if (e < 0) out->bad_capacity++;
+        if (e != src - (snk - r) + net[v]) out->bad_conservation++;
+    }
+
+    /* Smoothness, energy and cut capacity of the surface. */
+    for (int64_t x = 0; x < nx; ++x)
+        for (int64_t y = 0; y < ny; ++y) {
+            int64_t p = x * ny + y, h = surface[p];
+            if (h < 0 || h >= K) { out->bad_smooth++; continue; }
+            out->energy += cost[p * K + h];
+            for (int k = 0; k < 4; ++k) {
+                int64_t qx = x + dx[k], qy = y + dy[k];
+                if (qx < 0 || qx >= nx || qy < 0 || qy >= ny) continue;
+                int64_t hq = surface[qx * ny + qy];
+                if (hq - h > delta || h - hq > delta) out->bad_smooth++;
+            }
+            for (int64_t z = 0; z < K; ++z) {
+                int64_t v = p * K + z;
+                int64_t w = z == 0 ? (int64_t)cost[v] - B : (int64_t)cost[v] - cost[v - 1];
+                if (z <= h && w > 0) out->cut += w;
+                if (z > h && w < 0) out->cut += -w;
+            }
+        }
+
+    /* Residual reach from all nodes with positive excess. */
+    int64_t qh = 0, qt = 0;
+    for (int64_t v = 0; v < N; ++v)
+        if (excess[v] > 0) { mark[v] = 1; queue[qt++] = v; }
+    int reached_sink = 0;
+#define VISIT(u) do { if (!mark[u]) { mark[u] = 1; queue[qt++] = (u); } } while (0)
+    while (qh < qt) {
+        int64_t v = queue[qh++];
+        int64_t z = v % K, p = v / K, x = p / ny, y = p % ny;
+        if (sink_res[v] > 0) reached_sink = 1;
+        if (z > 0) VISIT(v - 1);                               /* down, infinite */
+        if (z + 1 < K && flow_down[v + 1] > 0) VISIT(v + 1);  /* reverse of down */
+        for (int k = 0; k < 4; ++k) {
+            int64_t qx = x + dx[k], qy = y + dy[k];
+            if (qx < 0 || qx >= nx || qy < 0 || qy >= ny) continue;
+            int64_t q = qx * ny + qy;
+            if (lat_arc_exists(z, delta)) VISIT(q * K + lat_target(z, delta));
+            /* Reverse residual of q's arc in the opposite direction that
+             * lands on v: its tail is (q, z + delta), or (q, 0) when z = 0. */
+            int kk = k ^ 1;
+            int64_t zt = z == 0 ? 0 : z + delta;
+            if (zt < K && lat_arc_exists(zt, delta) && lat_target(zt, delta) == z) {
+                int64_t u = q * K + zt;
+                if (flow_lat[(int64_t)kk * N + u] > 0) VISIT(u);
+            }
+        }
+    }
+#undef VISIT
+    if (reached_sink) out->bad_reach++;
+    for (int64_t p = 0; p < P; ++p) {
+        int64_t top = -1;
+        for (int64_t z = 0; z < K; ++z)
+            if (mark[p * K + z]) top = z;
+        if (top != surface[p]) out->bad_reach++;
+    }
+
+    free(net); free(mark); free(queue);
+    return 0;
+}

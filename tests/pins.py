@@ -1,0 +1,262 @@
+"""Independent references that pin the CPU oracle to the mathematics.
+
+None of these shares code with the oracle or with the GPU library:
+  - brute force over every delta-smooth surface of a tiny volume (the
+    definition of the optimal net surface, Section 1.2 and Eq. 1);
+  - an exact dynamic program along a single row of columns;
+  - the closed form of the max-flow value from the optimal energy;
+  - library max-flow routines (scipy, networkx) on the explicit graph.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def neighbours(nx, ny):
+    """Unordered 4-neighbour column pairs of an nx x ny grid, flat indices."""
+    out = []
+    for x in range(nx):
+        for y in range(ny):
+            if x + 1 < nx:
+                out.append((x * ny + y, (x + 1) * ny + y))
+            if y + 1 < ny:
+                out.append((x * ny + y, x * ny + y + 1))
+    return out
+
+
+def brute_force(cost: np.ndarray, delta: int):
+    """E*, the pointwise-lowest and pointwise-highest optimal surfaces.
+
+    Enumerates all K^(nx*ny) height maps, keeps the delta-smooth ones and
+    takes the minimum of sum_p c(p, h(p)).  The optimal surfaces form a
+    lattice under pointwise min/max, so the pointwise min (max) over all
+    optimal surfaces is itself optimal.
+    """
+    nx, ny, K = cost.shape
+    P = nx * ny
+    c = cost.reshape(P, K).astype(np.int64)
+    H = np.array(list(itertools.product(range(K), repeat=P)), dtype=np.int64)
+    ok = np.ones(len(H), dtype=bool)
+    for a, b in neighbours(nx, ny):
+        ok &= np.abs(H[:, a] - H[:, b]) <= delta
+    H = H[ok]
+    E = c[np.arange(P)[None, :], H].sum(axis=1)
+    best = E.min()
+    opt = H[E == best]
+    return int(best), opt.min(axis=0).reshape(nx, ny), opt.max(axis=0).reshape(nx, ny)
+
+
+def _window_min(a: np.ndarray, delta: int) -> np.ndarray:
+    """out[z] = min(a[z - delta .. z + delta]) clipped to the array."""
+    K = a.shape[0]
+    out = a.copy()
+    for s in range(1, delta + 1):
+        if s >= K:
+            break
+        out[:-s] = np.minimum(out[:-s], a[s:])
+        out[s:] = np.minimum(out[s:], a[:-s])
+    return out
+
+
+def row_dp(cost: np.ndarray, delta: int):
+    """Exact optimum for a single row of columns (cost shape (n, K)).
+
+    Forward and backward min-plus recurrences over the chain of columns:
+    Fw[x][z] = c(x,z) + min_{|z'-z|<=delta} Fw[x-1][z'] and the mirror
+    image Bw.  The best surface through (x, z) costs Fw + Bw - c; the lowest
+    (highest) z attaining E* at x is h_min(x) (h_max(x)).
+    """
+    c = cost.astype(np.int64)
+    n, K = c.shape
+    Fw = np.empty_like(c)
+    Bw = np.empty_like(c)
+    Fw[0] = c[0]
+    for x in range(1, n):
+        Fw[x] = c[x] + _window_min(Fw[x - 1], delta)
+    Bw[n - 1] = c[n - 1]
+    for x in range(n - 2, -1, -1):
+        Bw[x] = c[x] + _window_min(Bw[x + 1], delta)
+    best = int(Fw[n - 1].min())
+    through = Fw + Bw - c
+    hit = through == best
+    hmin = np.argmax(hit, axis=1)
+    hmax = K - 1 - np.argmax(hit[:, ::-1], axis=1)
+    return best, hmin.astype(np.int32), hmax.astype(np.int32)
+
+
+def flow_closed_form(cost: np.ndarray, energy: int) -> int:
+    """Max-flow value from the optimal energy.
+
+    With B > max_p c(p,0) the minimum cut is a delta-smooth surface whose
+    capacity is W^- + sum_{z <= h(p)} w(p,z) = E(h) - sum_p c(p,0)
+    + sum_p sum_{z>=1} max(0, c(p,z-1) - c(p,z)), independent of B.
+    """
+    c = cost.astype(np.int64)
+    drops = np.maximum(0, c[:, :, :-1] - c[:, :, 1:]).sum()
+    return int(energy - c[:, :, 0].sum() + drops)
+
+
+def explicit_arcs(cost: np.ndarray, delta: int, inf: int):
+    """(tail, head, capacity) triples of G(c, delta), s = N, t = N + 1."""
+    nx, ny, K = cost.shape
+    c = cost.astype(np.int64)
+    N = nx * ny * K
+    s, t = N, N + 1
+    B = int(c[:, :, 0].max()) + 1
+    arcs = []
+    idx = lambda x, y, z: (x * ny + y) * K + z
+    for x in range(nx):
+        for y in range(ny):
+            for z in range(K):
+                v = idx(x, y, z)
+                w = int(c[x, y, 0]) - B if z == 0 else int(c[x, y, z] - c[x, y, z - 1])
+                if w < 0:
+                    arcs.append((s, v, -w))
+                elif w > 0:
+                    arcs.append((v, t, w))
+                if z > 0:
+                    arcs.append((v, idx(x, y, z - 1), inf))
+                for qx, qy in ((x + 1, y), (x - 1, y), (x, y + 1), (x, y - 1)):
+                    if 0 <= qx < nx and 0 <= qy < ny:
+                        arcs.append((v, idx(qx, qy, max(0, z - delta)), inf))
+    return arcs, s, t, N + 2
+
+
+def scipy_flow(cost: np.ndarray, delta: int) -> int:
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import maximum_flow
+
+    arcs, s, t, n = explicit_arcs(cost, delta, inf=1 << 28)
+    a = np.array(arcs, dtype=np.int64)
+    m = sp.csr_array((a[:, 2].astype(np.int32), (a[:, 0], a[:, 1])), shape=(n, n))
+    return int(maximum_flow(m, s, t).flow_value)
+
+
+def networkx_flow(cost: np.ndarray, delta: int) -> int:
+    import networkx as nx_
+
+    arcs, s, t, n = explicit_arcs(cost, delta, inf=-1)
+    g = nx_.DiGraph()
+    g.add_nodes_from(range(n))
+    for u, v, cap in arcs:
+        if cap < 0:
+            g.add_edge(u, v)          # no capacity attribute = infinite
+        else:
+            g.add_edge(u, v, capacity=cap)
+    return int(nx_.maximum_flow_value(g, s, t))
+
+
+def reduced_preflow(cost: np.ndarray, delta: int):
+    """A maximum preflow of the reduced column graph by textbook FIFO
+    push-relabel (Section 2.1), in plain Python loops for tiny volumes.
+
+    The reduced graph keeps the down arcs and, per 4-neighbour q, the
+    lateral arcs (p,z) -> (q, z - delta) for z > delta plus (p,0) -> (q,0);
+    source arcs start saturated and excess is never returned to s (a node
+    whose label reaches n has no path to t and stops).  Returns the solver
+    storage arrays (excess, sink residual, down flow, lateral flows in
+    +x,-x,+y,-y order) and the flow value.
+    """
+    from collections import deque
+
+    nx, ny, K = cost.shape
+    c = cost.astype(np.int64)
+    N = nx * ny * K
+    t = N
+    B = int(c[:, :, 0].max()) + 1
+    idx = lambda x, y, z: (x * ny + y) * K + z
+    # arcs: [tail, head, cap(-1 = inf), flow, kind, slot]
+    arcs = []
+    out = [[] for _ in range(N)]
+    inn = [[] for _ in range(N + 1)]
+    e = np.zeros(N, dtype=np.int64)
+    dirs = ((1, 0), (-1, 0), (0, 1), (0, -1))
+
+    def add(u, v, cap, kind):
+        arcs.append([u, v, cap, 0, kind])
+        out[u].append(len(arcs) - 1)
+        inn[v].append(len(arcs) - 1)
+
+    for x in range(nx):
+        for y in range(ny):
+            for z in range(K):
+                v = idx(x, y, z)
+                w = int(c[x, y, 0]) - B if z == 0 else int(c[x, y, z] - c[x, y, z - 1])
+                if w < 0:
+                    e[v] = -w
+                if w > 0:
+                    add(v, t, w, ("t",))
+                if z > 0:
+                    add(v, v - 1, -1, ("d",))
+                for k, (ddx, ddy) in enumerate(dirs):
+                    qx, qy = x + ddx, y + ddy
+                    if 0 <= qx < nx and 0 <= qy < ny and (z == 0 or z > delta):
+                        add(v, idx(qx, qy, 0 if z == 0 else z - delta), -1, ("l", k))
+
+    n = N + 2
+    d = [0] * N
+    q = deque(v for v in range(N) if e[v] > 0)
+    inq = set(q)
+    while q:
+        u = q.popleft()
+        inq.discard(u)
+        while e[u] > 0 and d[u] < n:
+            pushed = False
+            # residual arcs out of u: forward arcs with room, reverse of arcs into u
+            for a in out[u]:
+                tail, head, cap, f, _ = arcs[a]
+                r = (1 << 62) if cap < 0 else cap - f
+                dh = 0 if head == t else d[head]
+                if r > 0 and d[u] == dh + 1:
+                    amt = min(e[u], r)
+                    arcs[a][3] += amt
+                    e[u] -= amt
+                    if head != t:
+                        e[head] += amt
+                        if head not in inq:
+                            q.append(head); inq.add(head)
+                    pushed = True
+                    if e[u] == 0:
+                        break
+            if e[u] > 0:
+                for a in inn[u]:
+                    tail, head, cap, f, _ = arcs[a]
+                    if f > 0 and d[u] == d[tail] + 1:
+                        amt = min(e[u], f)
+                        arcs[a][3] -= amt
+                        e[u] -= amt
+                        e[tail] += amt
+                        if tail not in inq:
+                            q.append(tail); inq.add(tail)
+                        pushed = True
+                        if e[u] == 0:
+                            break
+            if e[u] > 0 and not pushed:
+                best = n
+                for a in out[u]:
+                    tail, head, cap, f, _ = arcs[a]
+                    if cap < 0 or cap - f > 0:
+                        best = min(best, 1 if head == t else d[head] + 1)
+                for a in inn[u]:
+                    tail, head, cap, f, _ = arcs[a]
+                    if f > 0:
+                        best = min(best, d[tail] + 1)
+                d[u] = best
+
+    ts = np.zeros(N, dtype=np.int64)
+    fd = np.zeros(N, dtype=np.int64)
+    fl = np.zeros((4, N), dtype=np.int64)
+    flow = 0
+    for tail, head, cap, f, kind in arcs:
+        if kind[0] == "t":
+            ts[tail] = cap - f
+            flow += f
+        elif kind[0] == "d":
+            fd[tail] = f
+        else:
+            fl[kind[1], tail] = f
+    sh = (nx, ny, K)
+    return (e.reshape(sh).astype(np.int32), ts.reshape(sh).astype(np.int32),
+            fd.reshape(sh).astype(np.int32), fl.reshape((4,) + sh).astype(np.int32), flow)

@@ -1,0 +1,171 @@
+"""Pins of the CPU oracle (no GPU): the oracle against brute force, an exact
+row DP, closed forms, library max-flow routines and its own invariants."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from paper_2601_17026_amd import synth
+
+
+def _check_invariants(cost, delta, r):
+    nx, ny, K = cost.shape
+    assert r.conservation_ok and r.capacity_ok          # Eq. 2-4 on the final flow
+    assert r.smin_in_smax                                # minimal cut inside maximal cut
+    assert r.flow == r.cut                               # Theorem 1.1
+    assert r.flow == pins.flow_closed_form(cost, r.energy)
+    assert r.energy == r.energy_hmax                     # both extreme cuts are optimal
+    for h in (r.hmin, r.hmax):
+        assert h.min() >= 0 and h.max() < K
+        assert np.abs(np.diff(h.astype(np.int64), axis=0)).max(initial=0) <= delta
+        assert np.abs(np.diff(h.astype(np.int64), axis=1)).max(initial=0) <= delta
+    assert (r.hmin <= r.hmax).all()
+    E = np.take_along_axis(cost.astype(np.int64), r.hmin[:, :, None].astype(np.int64), 2).sum()
+    assert E == r.energy
+
+
+TINY = [(1, 1, 5), (1, 3, 4), (3, 1, 4), (2, 2, 4), (2, 3, 3), (3, 2, 4), (1, 6, 3), (2, 3, 4)]
+
+
+@pytest.mark.parametrize("shape", TINY)
+@pytest.mark.parametrize("delta", [0, 1, 2, 4])
+@pytest.mark.parametrize("lohi", [(-20, 20), (0, 3), (0, 1000)])
+def test_brute_force(shape, delta, lohi):
+    for seed in range(3):
+        c = synth.random_cost(*shape, *lohi, seed=hash((shape, delta, lohi, seed)) % 2**31)
+        r = oracle.solve(c, delta)
+        E, hmin, hmax = pins.brute_force(c, delta)
+        assert r.energy == E
+        np.testing.assert_array_equal(r.hmin, hmin)
+        np.testing.assert_array_equal(r.hmax, hmax)
+        _check_invariants(c, delta, r)
+
+
+@pytest.mark.parametrize("n,K,delta", [(64, 32, 1), (48, 20, 0), (40, 16, 3), (33, 7, 2), (5, 64, 5)])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_row_dp(n, K, delta, axis):
+    for seed in range(2):
+        row = synth.random_cost(n, 1, K, 0, 50, seed=1000 * n + 7 * K + seed)[:, 0, :]
+        c = row[:, None, :] if axis == 0 else row[None, :, :]
+        r = oracle.solve(np.ascontiguousarray(c), delta)
+        E, hmin, hmax = pins.row_dp(row, delta)
+        assert r.energy == E
+        np.testing.assert_array_equal(r.hmin.reshape(-1), hmin)
+        np.testing.assert_array_equal(r.hmax.reshape(-1), hmax)
+        _check_invariants(np.ascontiguousarray(c), delta, r)
+
+
+def test_row_dp_agrees_with_brute_force():
+    # the DP pin is itself pinned to brute force
+    for seed in range(20):
+        row = synth.random_cost(6, 1, 4, -5, 5, seed=seed)[:, 0, :]
+        for delta in (0, 1, 2):
+            a = pins.row_dp(row, delta)
+            b = pins.brute_force(row[:, None, :], delta)
+            assert a[0] == b[0]
+            np.testing.assert_array_equal(a[1], b[1].reshape(-1))
+            np.testing.assert_array_equal(a[2], b[2].reshape(-1))
+
+
+def test_unconstrained_columns():
+    # delta >= K-1: every column independently takes its lowest/highest argmin
+    c = synth.random_cost(7, 5, 9, 0, 6, seed=11)
+    r = oracle.solve(c, 8)
+    np.testing.assert_array_equal(r.hmin, np.argmin(c, axis=2))
+    np.testing.assert_array_equal(r.hmax, 8 - np.argmin(c[:, :, ::-1], axis=2))
+    assert r.energy == c.min(axis=2).sum()
+
+
+def test_flat_surface_delta0():
+    # delta = 0: the surface is flat at the argmin of the summed column costs
+    c = synth.random_cost(4, 6, 11, -9, 9, seed=12)
+    r = oracle.solve(c, 0)
+    tot = c.astype(np.int64).sum(axis=(0, 1))
+    assert (r.hmin == np.argmin(tot)).all()
+    assert (r.hmax == 10 - np.argmin(tot[::-1])).all()
+    assert r.energy == tot.min()
+
+
+def test_non_decreasing_columns():
+    # costs non-decreasing up every column: h = 0 is optimal and no flow moves
+    c = np.sort(synth.random_cost(5, 4, 8, 0, 40, seed=13), axis=2)
+    c[:, :, 0] -= 1   # make the bottom the strict unique minimum
+    r = oracle.solve(np.ascontiguousarray(c), 1)
+    assert (r.hmin == 0).all() and (r.hmax == 0).all()
+    assert r.flow == 0
+
+
+def test_planted_surface():
+    # noise-free planted surface with slope <= delta is recovered exactly
+    rng = np.random.default_rng(14)
+    nx, ny, K, delta = 9, 7, 20, 2
+    h = np.zeros((nx, ny), dtype=np.int64)
+    h[0, 0] = 10
+    for x in range(nx):
+        for y in range(ny):
+            if x == 0 and y == 0:
+                continue
+            ref = h[x - 1, y] if x > 0 else h[x, y - 1]
+            lo, hi = ref - 2, ref + 2
+            if x > 0 and y > 0:
+                lo, hi = max(lo, h[x, y - 1] - 2), min(hi, h[x, y - 1] + 2)
+            h[x, y] = np.clip(rng.integers(lo, hi + 1), 0, K - 1)
+    c = rng.integers(1, 100, size=(nx, ny, K)).astype(np.int32)
+    np.put_along_axis(c, h[:, :, None], 0, axis=2)
+    r = oracle.solve(c, delta)
+    np.testing.assert_array_equal(r.hmin, h)
+    np.testing.assert_array_equal(r.hmax, h)
+    assert r.energy == 0
+    _check_invariants(c, delta, r)
+
+
+@pytest.mark.parametrize("shape,delta", [((3, 4, 6), 1), ((4, 3, 5), 0), ((2, 5, 7), 2), ((3, 3, 8), 3)])
+def test_library_maxflow(shape, delta):
+    for seed in range(2):
+        c = synth.random_cost(*shape, -30, 60, seed=77 + seed)
+        r = oracle.solve(c, delta)
+        assert r.flow == pins.scipy_flow(c, delta)
+        assert r.flow == pins.networkx_flow(c, delta)
+
+
+def test_small_workload_invariants():
+    c, delta = synth.config_small()
+    r = oracle.solve(c, delta)
+    _check_invariants(c, delta, r)
+
+
+@pytest.mark.parametrize("shape,delta", [((2, 3, 5), 1), ((3, 3, 6), 2), ((1, 4, 7), 0), ((4, 2, 6), 3)])
+def test_certificate_accepts_reduced_preflow(shape, delta):
+    # An independent push-relabel on the reduced arc set yields the same flow
+    # value as the oracle on the full graph, and the certificate checker
+    # accepts its final state together with the oracle's minimal surface.
+    for seed in range(3):
+        c = synth.random_cost(*shape, -25, 25, seed=500 + seed)
+        r = oracle.solve(c, delta)
+        e, ts, fd, fl, flow = pins.reduced_preflow(c, delta)
+        assert flow == r.flow
+        cert = oracle.certify(c, delta, e, ts, fd, fl, r.hmin)
+        assert cert.ok, cert
+        assert cert.flow == r.flow and cert.energy == r.energy
+
+
+def test_certificate_rejects_mistakes():
+    c = synth.random_cost(3, 3, 6, -25, 25, seed=600)
+    delta = 1
+    r = oracle.solve(c, delta)
+    e, ts, fd, fl, flow = pins.reduced_preflow(c, delta)
+    assert oracle.certify(c, delta, e, ts, fd, fl, r.hmin).ok
+    # a different surface
+    h2 = r.hmin.copy(); h2[1, 1] += 1
+    assert not oracle.certify(c, delta, e, ts, fd, fl, h2).ok
+    # a flow that breaks conservation
+    fd2 = fd.copy(); fd2[0, 0, 3] += 1
+    assert oracle.certify(c, delta, e, ts, fd2, fl, r.hmin).bad_conservation > 0
+    # the zero flow is a preflow but not a maximum one
+    N0 = np.zeros_like(e)
+    B = int(c[:, :, 0].max()) + 1
+    w = np.concatenate([c[:, :, :1].astype(np.int64) - B, np.diff(c.astype(np.int64), axis=2)], axis=2)
+    e0 = np.maximum(0, -w).astype(np.int32)
+    ts0 = np.maximum(0, w).astype(np.int32)
+    z = oracle.certify(c, delta, e0, ts0, N0, np.zeros_like(fl), r.hmin)
+    assert z.bad_conservation == 0 and not z.ok
