@@ -1,0 +1,119 @@
+/*
+ * smf -- exact surface max-flow on MI355X (gfx950).
+ *
+ * Solves the optimal delta-smooth net surface of an int32 cost volume as an
+ * exact s-t minimum cut (Section 1.2: multi-column proper-ordered graph whose
+ * node weights become terminal arc capacities; Section 1.3: max-flow / min-cut,
+ * Eqs. 2-7, Theorem 1.1) with a push-relabel method (Section 2.1) run as
+ * hand-written HIP kernels.
+ *
+ * The graph G(c, delta) of a cost volume c[x][y][z] (nx * ny columns of K
+ * nodes, z fastest in memory):
+ *   B = max_p c(p,0) + 1;  w(p,0) = c(p,0) - B;  w(p,z) = c(p,z) - c(p,z-1);
+ *   s -> v with capacity -w(v) if w(v) < 0;  v -> t with capacity w(v) if
+ *   w(v) > 0;  (p,z) -> (p,z-1) infinite (z >= 1);  (p,z) -> (q, max(0,
+ *   z - delta)) infinite for each 4-neighbour column q inside the grid.
+ * Results:
+ *   - the max-flow value F (Eq. 5), as int64;
+ *   - the surface h(p) = max{z : (p,z) in S_min}, where S_min is the source
+ *     side of the inclusion-minimal minimum cut.  h is the pointwise-lowest
+ *     surface minimising E(h) = sum_p c(p, h(p)) subject to
+ *     |h(p) - h(q)| <= delta for 4-neighbours (Eq. 1 with a hard prior);
+ *   - E* = E(h).
+ *
+ * Conventions for every entry point:
+ *   - "device pointer" means memory the caller allocated on the current HIP
+ *     device; the caller keeps ownership.  Volumes are contiguous
+ *     [nx][ny][K] int32 (z fastest), surfaces contiguous [nx][ny] int32.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   - Every int-returning call returns SMF_OK (0) or a negative SMF_ERR_*
+ *     code; smf_last_error() then describes the failure (thread-local).
+ *   - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef SMF_H
+#define SMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SMF_OK = 0,
+    SMF_ERR_ARG = -1,           /* bad argument (NULL, size, shape mismatch) */
+    SMF_ERR_NOMEM = -2,         /* device or host allocation failed */
+    SMF_ERR_RANGE = -3,         /* |cost| >= 2^30, nx*ny*K >= 2^31, or an int32
+                                   excess/flow counter would overflow */
+    SMF_ERR_NOT_CONVERGED = -4, /* sweep cap reached before termination */
+    SMF_ERR_HIP = -5,           /* a HIP runtime call failed */
+    SMF_ERR_NOT_SOLVED = -6     /* result requested before a successful solve */
+};
+
+typedef struct smf_handle smf_handle;
+
+/* Allocates all solver state for one nx x ny x K volume with smoothness
+ * bound delta (Section 1.2, the "edge interval") on the current device:
+ * 32 bytes per node plus O(nx*ny).  Returns NULL on failure (see
+ * smf_last_error).  Requires nx, ny, K >= 1, delta >= 0, nx*ny*K < 2^31. */
+smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t delta);
+
+/* Releases the handle and its device memory.  NULL is allowed. */
+void smf_destroy(smf_handle *h);
+
+/* Solves the volume `cost_dev` (device pointer, [nx][ny][K] int32, every
+ * value in (-2^30, 2^30)).  Work is enqueued on `stream`; the call drives
+ * the iteration from the host and returns when the result is complete, so
+ * on SMF_OK the flow value, energy and surface are ready.  The cost buffer
+ * is only read. */
+int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream);
+
+/* Max-flow value F of the last successful solve (host int64 out). */
+int smf_flow_value(const smf_handle *h, int64_t *out);
+
+/* Optimal energy E* = sum_p c(p, h(p)) of the last successful solve. */
+int smf_energy(const smf_handle *h, int64_t *out);
+
+/* Copies the minimal-cut surface h (values in [0, K-1]) of the last
+ * successful solve into `out_dev` (device pointer, [nx][ny] int32),
+ * enqueued on `stream`. */
+int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream);
+
+/* Copies the final preflow of the last successful solve into caller device
+ * buffers, each [nx][ny][K] int32 (z fastest) except `flow_lat_dev`, which
+ * is [4][nx][ny][K] in neighbour order +x, -x, +y, -y:
+ *   excess_dev   -- excess e(v) >= 0 left at each node;
+ *   sink_res_dev -- residual capacity of v -> t;
+ *   flow_down_dev-- flow on (p,z) -> (p,z-1) (0 at z = 0);
+ *   flow_lat_dev -- flow on (p,z) -> (q, z - delta), stored for z > delta,
+ *                   and on (p,0) -> (q,0); 0 for absent arcs.  The solver
+ *                   omits the arcs (p,z) -> (q,0) for 1 <= z <= delta, which
+ *                   are implied by (p,z) -> (p,0) -> (q,0) and change no cut.
+ * Source arcs are saturated and never carry flow back.  For certificates and
+ * debugging; enqueued on `stream`. */
+int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res_dev,
+                     int32_t *flow_down_dev, int32_t *flow_lat_dev, void *stream);
+
+/* Tuning and limits.  Keys:
+ *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1)
+ *   "max_sweeps"      -- sweep cap before SMF_ERR_NOT_CONVERGED (>= 1)
+ *   "poll_every"      -- sweeps between host termination checks (>= 1)
+ *   "bfs_poll_every"  -- BFS passes between host convergence checks (>= 1)
+ * Returns SMF_ERR_ARG for an unknown key or an out-of-range value. */
+int smf_set_param(smf_handle *h, const char *key, int64_t value);
+
+/* Counters of the last solve.  Keys: "sweeps", "global_relabels",
+ * "bfs_passes", "mincut_passes", "gap_relabels". */
+int smf_get_stat(const smf_handle *h, const char *key, int64_t *out);
+
+/* Static text for a status code. */
+const char *smf_status_string(int status);
+
+/* Description of the last failure on this host thread ("" if none). */
+const char *smf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMF_H */

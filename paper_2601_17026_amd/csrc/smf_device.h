@@ -1,0 +1,70 @@
+// Device-side layout and helpers shared by the solver kernels.
+//
+// Node state is stored level-major ("z slowest"): node (p, z) with column
+// p = x*ny + y lives at index z*P + p, P = nx*ny.  A thread that owns column
+// p walks z and every step of a wave touches 64 consecutive columns, so all
+// per-node loads and stores are coalesced, the column-direction carries stay
+// in registers, and the lateral neighbours (p +- 1, p +- ny) of a wave are
+// again contiguous runs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smf {
+
+constexpr int kInf = 0x40000000;       // label of a node that cannot reach t
+constexpr int kErrCostRange = 1;       // a cost outside (-2^30, 2^30)
+constexpr int kErrOverflow = 2;        // an int32 excess or flow would overflow
+
+struct Geom {
+    int nx, ny, K, delta;
+    int P;      // columns
+    int N;      // nodes (< 2^31)
+    int lab_cap; // labels >= lab_cap are unreachable (N + 1, at most kInf)
+};
+
+// Per-node solver state; each array holds N int32 in level-major order.
+struct State {
+    int *e;    // excess
+    int *d;    // distance label (lower bound of the residual distance to t)
+    int *ts;   // residual capacity of v -> t
+    int *fd;   // flow on (p,z) -> (p,z-1)
+    int *fl;   // 4 x N: flow on (p,z) -> (q, zt(z)), q = p + (+x, -x, +y, -y)
+};
+
+// Device-resident counters and flags of one solve.
+struct Scratch {
+    int bmax;            // max_p c(p, 0)
+    int err;             // kErr* bits
+    int changed;         // a BFS / min-cut pass changed something
+    int active;          // active nodes after the last relabel phase
+    long long flow;      // sum of flow into t
+    long long energy;    // sum_p c(p, h(p))
+    long long pad[2];
+};
+
+// Lateral arcs kept by the solver: (p,z) -> (q, z - delta) for z > delta,
+// and (p,0) -> (q,0).  The arcs (p,z) -> (q,0), 1 <= z <= delta, are implied
+// by (p,z) -> (p,0) -> (q,0) and change no closed set, hence no cut.
+__device__ __forceinline__ bool lat_arc(int z, int delta) { return z == 0 || z > delta; }
+__device__ __forceinline__ int lat_head(int z, int delta) { return z == 0 ? 0 : z - delta; }
+// Height of the tail of the lateral arc that ends at height z (or -1 when
+// no kept arc ends there within a column of K nodes).
+__device__ __forceinline__ int lat_tail(int z, int delta, int K)
+{
+    int zt = z == 0 ? 0 : z + delta;
+    return zt < K ? zt : -1;
+}
+
+// Neighbour column in direction k (0:+x, 1:-x, 2:+y, 3:-y), or -1.
+__device__ __forceinline__ int nbr(const Geom &g, int x, int y, int p, int k)
+{
+    switch (k) {
+    case 0: return x + 1 < g.nx ? p + g.ny : -1;
+    case 1: return x > 0 ? p - g.ny : -1;
+    case 2: return y + 1 < g.ny ? p + 1 : -1;
+    default: return y > 0 ? p - 1 : -1;
+    }
+}
+
+}  // namespace smf

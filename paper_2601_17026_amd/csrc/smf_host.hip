@@ -1,0 +1,300 @@
+// Host driver and C-ABI of the exact surface max-flow (include/smf.h).
+//
+// One handle owns the level-major node state of one volume (32 bytes per
+// node) plus a small device scratch block and a pinned host mirror of it.
+// smf_solve enqueues the build, the initial global relabel and then sweeps
+// of push and relabel phases on the caller's stream; the host polls the
+// device's active-node counter every `poll_every` sweeps (the only
+// device-to-host traffic of the loop) and runs a global relabel every
+// `relabel_period` sweeps.  Termination: no node with excess and a finite
+// label remains (Section 3.2.4 decides this with flags and locks across
+// threads; here it is one counter written by the relabel phase).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/smf.h"
+#include "smf_device.h"
+
+namespace smf {
+void launch_init_scratch(Scratch *s, hipStream_t st);
+void launch_set_int(int *p, int v, hipStream_t st);
+void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st);
+void launch_bfs_reset(const Geom &g, const State &sv, hipStream_t st);
+void launch_bfs_pass(const Geom &g, const State &sv, Scratch *s, hipStream_t st);
+void launch_push(const Geom &g, const State &sv, Scratch *s, bool down, hipStream_t st);
+void launch_relabel(const Geom &g, const State &sv, Scratch *s, hipStream_t st);
+void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
+void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
+void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
+                   hipStream_t st);
+void launch_export(const Geom &g, const State &sv, int *e, int *ts, int *fd, int *fl,
+                   hipStream_t st);
+}  // namespace smf
+
+using namespace smf;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                     \
+    do {                                                                                  \
+        hipError_t err_ = (call);                                                         \
+        if (err_ != hipSuccess)                                                           \
+            return fail(SMF_ERR_HIP, std::string(#call ": ") + hipGetErrorString(err_)); \
+    } while (0)
+
+struct smf_handle {
+    Geom g{};
+    int device = 0;
+    int *state = nullptr;      // 8 * N int32
+    int *H = nullptr;          // P int32 surface
+    Scratch *scr = nullptr;    // device scratch
+    Scratch *host = nullptr;   // pinned mirror
+    State st{};
+    // parameters
+    int64_t relabel_period = 6;
+    int64_t max_sweeps = 2000000;
+    int64_t poll_every = 1;
+    int64_t bfs_poll_every = 1;
+    // results and counters of the last solve
+    bool solved = false;
+    int64_t flow = 0, energy = 0;
+    int64_t sweeps = 0, global_relabels = 0, bfs_passes = 0, mincut_passes = 0, gap_relabels = 0;
+};
+
+static void release(smf_handle *h)
+{
+    if (!h) return;
+    if (h->state) (void)hipFree(h->state);
+    if (h->H) (void)hipFree(h->H);
+    if (h->scr) (void)hipFree(h->scr);
+    if (h->host) (void)hipHostFree(h->host);
+    delete h;
+}
+
+extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t delta)
+{
+    g_last_error.clear();
+    if (nx < 1 || ny < 1 || K < 1 || delta < 0) {
+        fail(SMF_ERR_ARG, "smf_create: need nx, ny, K >= 1 and delta >= 0");
+        return nullptr;
+    }
+    long long N = (long long)nx * ny * K;
+    if (N >= (1LL << 31) || 4 * N >= (1LL << 62)) {
+        fail(SMF_ERR_RANGE, "smf_create: nx*ny*K must be below 2^31");
+        return nullptr;
+    }
+    smf_handle *h = new (std::nothrow) smf_handle;
+    if (!h) {
+        fail(SMF_ERR_NOMEM, "smf_create: host allocation failed");
+        return nullptr;
+    }
+    h->g.nx = nx; h->g.ny = ny; h->g.K = K; h->g.delta = delta;
+    h->g.P = nx * ny;
+    h->g.N = (int)N;
+    h->g.lab_cap = N + 1 < kInf ? (int)(N + 1) : kInf;
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipMalloc((void **)&h->state, sizeof(int) * 8 * (size_t)N) != hipSuccess ||
+        hipMalloc((void **)&h->H, sizeof(int) * (size_t)h->g.P) != hipSuccess ||
+        hipMalloc((void **)&h->scr, sizeof(Scratch)) != hipSuccess ||
+        hipHostMalloc((void **)&h->host, sizeof(Scratch), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        release(h);
+        fail(SMF_ERR_NOMEM, "smf_create: device allocation of " +
+                                std::to_string(32.0 * N / (1 << 20)) + " MiB failed");
+        return nullptr;
+    }
+    int *b = h->state;
+    size_t n = (size_t)N;
+    h->st.e = b;
+    h->st.d = b + n;
+    h->st.ts = b + 2 * n;
+    h->st.fd = b + 3 * n;
+    h->st.fl = b + 4 * n;
+    return h;
+}
+
+extern "C" void smf_destroy(smf_handle *h) { release(h); }
+
+// Copies the scratch block to the pinned mirror and waits for the stream.
+static int sync_scratch(smf_handle *h, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(h->host, h->scr, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h->host->err & kErrCostRange)
+        return fail(SMF_ERR_RANGE, "smf_solve: a cost lies outside (-2^30, 2^30)");
+    if (h->host->err & kErrOverflow)
+        return fail(SMF_ERR_RANGE, "smf_solve: an int32 excess or flow counter overflowed");
+    return SMF_OK;
+}
+
+// Exact global relabel: reset all labels, then column passes of the
+// reverse breadth-first search until a pass changes nothing.
+static int global_relabel(smf_handle *h, hipStream_t s)
+{
+    launch_bfs_reset(h->g, h->st, s);
+    int64_t passes = 0;
+    for (;;) {
+        for (int64_t i = 0; i < h->bfs_poll_every; ++i) {
+            launch_set_int(&h->scr->changed, 0, s);
+            launch_bfs_pass(h->g, h->st, h->scr, s);
+            h->bfs_passes++;
+            passes++;
+        }
+        int rc = sync_scratch(h, s);
+        if (rc) return rc;
+        if (!h->host->changed) break;
+        // labels only decrease from kInf towards the exact distances: a
+        // pass count beyond N + 2 means a defect, not a slow search
+        if (passes > (int64_t)h->g.N + 2 + h->bfs_poll_every)
+            return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: breadth-first search did not settle");
+    }
+    h->global_relabels++;
+    return SMF_OK;
+}
+
+extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
+{
+    g_last_error.clear();
+    if (!h || !cost_dev) return fail(SMF_ERR_ARG, "smf_solve: NULL handle or cost");
+    hipStream_t s = (hipStream_t)stream;
+    h->solved = false;
+    h->sweeps = h->global_relabels = h->bfs_passes = h->mincut_passes = h->gap_relabels = 0;
+    HIP_TRY(hipSetDevice(h->device));
+
+    launch_init_scratch(h->scr, s);
+    launch_build(cost_dev, h->g, h->st, h->scr, s);
+    HIP_TRY(hipGetLastError());
+    int rc = sync_scratch(h, s);
+    if (rc) return rc;
+    rc = global_relabel(h, s);
+    if (rc) return rc;
+
+    bool done = false;
+    while (!done) {
+        if (h->sweeps >= h->max_sweeps)
+            return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: sweep cap reached");
+        for (int64_t i = 0; i < h->poll_every; ++i) {
+            if (h->sweeps > 0 && h->sweeps % h->relabel_period == 0) {
+                rc = global_relabel(h, s);
+                if (rc) return rc;
+            }
+            launch_push(h->g, h->st, h->scr, (h->sweeps & 1) == 0, s);
+            launch_set_int(&h->scr->active, 0, s);
+            launch_relabel(h->g, h->st, h->scr, s);
+            h->sweeps++;
+        }
+        HIP_TRY(hipGetLastError());
+        rc = sync_scratch(h, s);
+        if (rc) return rc;
+        done = h->host->active == 0;
+    }
+
+    launch_mincut_init(h->g, h->st, h->H, s);
+    for (;;) {
+        launch_set_int(&h->scr->changed, 0, s);
+        launch_mincut_pass(h->g, h->st, h->H, h->scr, s);
+        h->mincut_passes++;
+        rc = sync_scratch(h, s);
+        if (rc) return rc;
+        if (!h->host->changed) break;
+        if (h->mincut_passes > (int64_t)h->g.N + 2)
+            return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: minimum-cut search did not settle");
+    }
+    launch_finish(cost_dev, h->g, h->st, h->H, h->scr, s);
+    HIP_TRY(hipGetLastError());
+    rc = sync_scratch(h, s);
+    if (rc) return rc;
+    h->flow = h->host->flow;
+    h->energy = h->host->energy;
+    h->solved = true;
+    return SMF_OK;
+}
+
+extern "C" int smf_flow_value(const smf_handle *h, int64_t *out)
+{
+    if (!h || !out) return fail(SMF_ERR_ARG, "smf_flow_value: NULL argument");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_flow_value: no successful solve");
+    *out = h->flow;
+    return SMF_OK;
+}
+
+extern "C" int smf_energy(const smf_handle *h, int64_t *out)
+{
+    if (!h || !out) return fail(SMF_ERR_ARG, "smf_energy: NULL argument");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_energy: no successful solve");
+    *out = h->energy;
+    return SMF_OK;
+}
+
+extern "C" int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream)
+{
+    if (!h || !out_dev) return fail(SMF_ERR_ARG, "smf_surface: NULL argument");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_surface: no successful solve");
+    HIP_TRY(hipMemcpyAsync(out_dev, h->H, sizeof(int) * (size_t)h->g.P, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return SMF_OK;
+}
+
+extern "C" int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res_dev,
+                                int32_t *flow_down_dev, int32_t *flow_lat_dev, void *stream)
+{
+    if (!h || !excess_dev || !sink_res_dev || !flow_down_dev || !flow_lat_dev)
+        return fail(SMF_ERR_ARG, "smf_export_state: NULL argument");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_export_state: no successful solve");
+    launch_export(h->g, h->st, excess_dev, sink_res_dev, flow_down_dev, flow_lat_dev,
+                  (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return SMF_OK;
+}
+
+extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
+{
+    if (!h || !key) return fail(SMF_ERR_ARG, "smf_set_param: NULL argument");
+    int64_t *slot = nullptr;
+    if (!strcmp(key, "relabel_period")) slot = &h->relabel_period;
+    else if (!strcmp(key, "max_sweeps")) slot = &h->max_sweeps;
+    else if (!strcmp(key, "poll_every")) slot = &h->poll_every;
+    else if (!strcmp(key, "bfs_poll_every")) slot = &h->bfs_poll_every;
+    if (!slot) return fail(SMF_ERR_ARG, std::string("smf_set_param: unknown key ") + key);
+    if (value < 1) return fail(SMF_ERR_ARG, std::string("smf_set_param: ") + key + " must be >= 1");
+    *slot = value;
+    return SMF_OK;
+}
+
+extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
+{
+    if (!h || !key || !out) return fail(SMF_ERR_ARG, "smf_get_stat: NULL argument");
+    if (!strcmp(key, "sweeps")) *out = h->sweeps;
+    else if (!strcmp(key, "global_relabels")) *out = h->global_relabels;
+    else if (!strcmp(key, "bfs_passes")) *out = h->bfs_passes;
+    else if (!strcmp(key, "mincut_passes")) *out = h->mincut_passes;
+    else if (!strcmp(key, "gap_relabels")) *out = h->gap_relabels;
+    else return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown key ") + key);
+    return SMF_OK;
+}
+
+extern "C" const char *smf_status_string(int status)
+{
+    switch (status) {
+    case SMF_OK: return "ok";
+    case SMF_ERR_ARG: return "invalid argument";
+    case SMF_ERR_NOMEM: return "out of memory";
+    case SMF_ERR_RANGE: return "value out of int32 range";
+    case SMF_ERR_NOT_CONVERGED: return "not converged within the sweep cap";
+    case SMF_ERR_HIP: return "HIP runtime error";
+    case SMF_ERR_NOT_SOLVED: return "no successful solve";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *smf_last_error(void) { return g_last_error.c_str(); }

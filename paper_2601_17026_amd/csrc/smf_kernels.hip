@@ -1,0 +1,469 @@
+// HIP kernels of the exact surface max-flow (gfx950).
+//
+// Method: push-relabel (Section 2.1) on the implicit column graph of
+// Section 1.2, with global relabelling by a reverse breadth-first search
+// from the sink (Section 2.1, "global relabeling"; Section 3.2.2) and the
+// minimum cut read out as the residual reach set (Section 1.3, Eq. 6,
+// Theorem 1.1).  Storage is implicit (Section 3.2.3): no edge lists, only
+// per-node excess, label, sink residual and the flows of the five outgoing
+// infinite arcs.
+//
+// Labels.  A valid labelling here satisfies d(u) <= d(w) + len(u, w) for
+// every residual arc, with len = 0 for the always-residual down arcs
+// (p,z) -> (p,z-1) and len = 1 for every other arc (sink arcs included,
+// d(t) = 0).  Down arcs never lie on a cycle of length-0 arcs, so pushes
+// along them cannot circulate, and d(v) remains a lower bound of the
+// weighted residual distance to t: a node whose label exceeds N cannot reach
+// t.  Zero-length down arcs let excess fall down a whole column in one
+// sweep and make the breadth-first search count only column changes and
+// upward moves.
+//
+// Concurrency.  A sweep is two launches: a push phase with all labels fixed,
+// then a relabel phase with all flows fixed.  In the push phase a thread owns
+// one column; an arc and its reverse can never both be admissible under
+// fixed labels, so every flow counter has a single writer per phase, and
+// only excess counters of other columns are updated with atomics.  In the
+// relabel phase labels only grow, so reading a neighbour's old or new label
+// both keep the labelling valid.
+#include "smf_device.h"
+#include <limits.h>
+
+namespace smf {
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum64(long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ void add_excess(int *e, int w, long long a, int &err)
+{
+    if (a > INT_MAX) { err = 1; a = INT_MAX; }
+    int old = atomicAdd(e + w, (int)a);
+    if ((long long)old + a > INT_MAX) err = 1;
+}
+
+__device__ __forceinline__ int add_flow(int f, long long a, int &err)
+{
+    long long r = (long long)f + a;
+    if (r > INT_MAX) { err = 1; r = INT_MAX; }
+    return (int)r;
+}
+
+__global__ void k_init_scratch(Scratch *s)
+{
+    s->bmax = INT_MIN;
+    s->err = 0;
+    s->changed = 0;
+    s->active = 0;
+    s->flow = 0;
+    s->energy = 0;
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+__global__ void k_fill(int *a, int n, int v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// B - 1 = max_p c(p, 0): the bottom shift that makes every bottom node a
+// source node (w(p,0) < 0), so that the empty cut never wins.
+__global__ void k_bottom_max(const int *__restrict__ cost, int P, int K, Scratch *s)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int v = p < P ? cost[(long long)p * K] : INT_MIN;
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) atomicMax(&s->bmax, v);
+}
+
+// Graph build: node weights w (Section 1.2), source arcs pre-saturated into
+// the excess (Section 2.1 initialisation), sink residuals, zero flows and
+// labels set to "unknown" for the first breadth-first search.  A 64-column
+// x 64-level tile is transposed through LDS from the caller's z-fastest
+// layout to the level-major state layout.
+__global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geom g, State st,
+                                               Scratch *s)
+{
+    __shared__ int tile[64][65];
+    __shared__ int below[64];
+    const int p0 = blockIdx.x * 64, z0 = blockIdx.y * 64;
+    const int tid = threadIdx.x;
+    int bad = 0;
+    for (int i = 0; i < 16; ++i) {
+        int l = tid + 256 * i, pc = l >> 6, zc = l & 63;
+        int p = p0 + pc, z = z0 + zc;
+        int c = 0;
+        if (p < g.P && z < g.K) {
+            c = cost[(long long)p * g.K + z];
+            if (c <= -(1 << 30) || c >= (1 << 30)) bad = 1;
+        }
+        tile[pc][zc] = c;
+    }
+    if (tid < 64) {
+        int p = p0 + tid;
+        below[tid] = (z0 > 0 && p < g.P) ? cost[(long long)p * g.K + z0 - 1] : 0;
+    }
+    __syncthreads();
+    const int B = s->bmax + 1;
+    long long ts_sum = 0;
+    for (int i = 0; i < 16; ++i) {
+        int l = tid + 256 * i, zc = l >> 6, pc = l & 63;
+        int p = p0 + pc, z = z0 + zc;
+        if (p >= g.P || z >= g.K) continue;
+        int c = tile[pc][zc];
+        int cb = zc > 0 ? tile[pc][zc - 1] : below[pc];
+        int w = z == 0 ? c - B : c - cb;
+        int v = z * g.P + p;
+        st.e[v] = w < 0 ? -w : 0;
+        st.ts[v] = w > 0 ? w : 0;
+        ts_sum += w > 0 ? w : 0;
+        st.d[v] = kInf;
+        st.fd[v] = 0;
+        for (int k = 0; k < 4; ++k) st.fl[(size_t)k * g.N + v] = 0;
+    }
+    ts_sum = wave_sum64(ts_sum);
+    if ((tid & 63) == 0 && ts_sum) atomicAdd((unsigned long long *)&s->flow, (unsigned long long)ts_sum);
+    if (bad) atomicOr(&s->err, kErrCostRange);
+}
+
+// One pass of the reverse breadth-first search from t, in column form: a
+// thread takes its column up (length-0 down arcs and the sink and lateral
+// terms) and then down (length-1 reverse arcs of down arcs with flow).
+// Repeated until no label changes, it yields the exact weighted residual
+// distances (kInf where t is unreachable): the global relabelling.
+__global__ __launch_bounds__(256) void k_bfs_pass(Geom g, State st, Scratch *s)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.P) return;
+    const int P = g.P, K = g.K, N = g.N, dl = g.delta;
+    int x = p / g.ny, y = p - x * g.ny;
+    int q[4];
+    for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
+    int changed = 0, prev = kInf;
+    for (int z = 0; z < K; ++z) {
+        int u = z * P + p;
+        int du = st.d[u];
+        int b = min(du, prev);
+        if (st.ts[u] > 0) b = min(b, 1);
+        if (lat_arc(z, dl)) {
+            int zh = lat_head(z, dl) * P;
+            for (int k = 0; k < 4; ++k)
+                if (q[k] >= 0) b = min(b, st.d[zh + q[k]] + 1);
+        }
+        int zt = lat_tail(z, dl, K);
+        if (zt >= 0) {
+            for (int k = 0; k < 4; ++k) {
+                if (q[k] < 0) continue;
+                int w = zt * P + q[k];
+                if (st.fl[(size_t)(k ^ 1) * N + w] > 0) b = min(b, st.d[w] + 1);
+            }
+        }
+        b = min(b, kInf);
+        if (b < du) {
+            st.d[u] = b;
+            changed = 1;
+        }
+        prev = b;
+    }
+    int nxt = prev;
+    for (int z = K - 2; z >= 0; --z) {
+        int u = z * P + p;
+        int du = st.d[u];
+        if (st.fd[u + P] > 0 && nxt + 1 < du) {
+            du = nxt + 1;
+            st.d[u] = du;
+            changed = 1;
+        }
+        nxt = du;
+    }
+    if (changed) s->changed = 1;
+}
+
+// Push phase of one sweep (labels fixed).  The thread owning column p walks
+// it top-down (kDown) or bottom-up; each node with excess pushes along
+// admissible arcs d(u) = d(w) + len(u, w): to t, down the column, along
+// reverse lateral arcs (cancelling flow first), along forward lateral arcs,
+// and up along reverse down arcs.  Excess moving in the walking direction
+// is carried in a register and handled at the next node of the same walk.
+template <bool kDown>
+__global__ __launch_bounds__(256) void k_push(Geom g, State st, Scratch *s)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.P) return;
+    const int P = g.P, K = g.K, N = g.N, dl = g.delta;
+    int x = p / g.ny, y = p - x * g.ny;
+    int q[4];
+    for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
+    int err = 0;
+    long long carry = 0;
+    for (int i = 0; i < K; ++i) {
+        const int z = kDown ? K - 1 - i : i;
+        const int u = z * P + p;
+        long long ex = carry;
+        carry = 0;
+        const int eu = st.e[u];
+        if (eu <= 0 && ex == 0) continue;
+        const int du = st.d[u];
+        if (du >= kInf) {
+            if (ex) add_excess(st.e, u, ex, err);   // not reached: carries follow admissible arcs
+            continue;
+        }
+        if (eu > 0) ex += atomicExch(st.e + u, 0);
+        if (du == 1) {
+            int r = st.ts[u];
+            if (r > 0) {
+                int a = (int)min<long long>(ex, r);
+                st.ts[u] = r - a;
+                ex -= a;
+            }
+        }
+        if (ex > 0 && z > 0 && st.d[u - P] == du) {
+            st.fd[u] = add_flow(st.fd[u], ex, err);
+            if (kDown) carry = ex;
+            else add_excess(st.e, u - P, ex, err);
+            ex = 0;
+        }
+        if (ex > 0) {
+            int zt = lat_tail(z, dl, K);
+            if (zt >= 0) {
+                for (int k = 0; k < 4 && ex > 0; ++k) {
+                    if (q[k] < 0) continue;
+                    int w = zt * P + q[k];
+                    int *fp = st.fl + (size_t)(k ^ 1) * N + w;
+                    int f = *fp;
+                    if (f > 0 && st.d[w] + 1 == du) {
+                        int a = (int)min<long long>(ex, f);
+                        *fp = f - a;
+                        add_excess(st.e, w, a, err);
+                        ex -= a;
+                    }
+                }
+            }
+        }
+        if (ex > 0 && lat_arc(z, dl)) {
+            int zh = lat_head(z, dl) * P;
+            for (int k = 0; k < 4; ++k) {
+                if (q[k] < 0) continue;
+                int w = zh + q[k];
+                if (st.d[w] + 1 == du) {
+                    st.fl[(size_t)k * N + u] = add_flow(st.fl[(size_t)k * N + u], ex, err);
+                    add_excess(st.e, w, ex, err);
+                    ex = 0;
+                    break;
+                }
+            }
+        }
+        if (ex > 0 && z + 1 < K) {
+            int w = u + P;
+            int f = st.fd[w];
+            if (f > 0 && st.d[w] + 1 == du) {
+                int a = (int)min<long long>(ex, f);
+                st.fd[w] = f - a;
+                if (kDown) add_excess(st.e, w, a, err);
+                else carry = a;
+                ex -= a;
+            }
+        }
+        if (ex > 0) add_excess(st.e, u, ex, err);
+    }
+    if (err) atomicOr(&s->err, kErrOverflow);
+}
+
+// Relabel phase of one sweep (flows fixed): every node with excess, a finite
+// label and no admissible arc takes d(u) = min over residual arcs of
+// d(w) + len(u, w) (kInf when that exceeds every possible distance).  Also
+// counts the nodes that stay active.
+__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Scratch *s)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int cnt = 0;
+    if (p < g.P) {
+        const int P = g.P, K = g.K, N = g.N, dl = g.delta;
+        int x = p / g.ny, y = p - x * g.ny;
+        int q[4];
+        for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
+        int prev = kInf;
+        for (int z = 0; z < K; ++z) {
+            const int u = z * P + p;
+            int du = st.d[u];
+            if (du < kInf && st.e[u] > 0) {
+                int b = prev;
+                if (st.ts[u] > 0) b = min(b, 1);
+                if (z + 1 < K && st.fd[u + P] > 0) b = min(b, st.d[u + P] + 1);
+                if (lat_arc(z, dl)) {
+                    int zh = lat_head(z, dl) * P;
+                    for (int k = 0; k < 4; ++k)
+                        if (q[k] >= 0) b = min(b, st.d[zh + q[k]] + 1);
+                }
+                int zt = lat_tail(z, dl, K);
+                if (zt >= 0) {
+                    for (int k = 0; k < 4; ++k) {
+                        if (q[k] < 0) continue;
+                        int w = zt * P + q[k];
+                        if (st.fl[(size_t)(k ^ 1) * N + w] > 0) b = min(b, st.d[w] + 1);
+                    }
+                }
+                if (b > du) {
+                    du = b >= g.lab_cap ? kInf : b;
+                    st.d[u] = du;
+                }
+                if (du < kInf) ++cnt;
+            }
+            prev = du;
+        }
+    }
+    cnt = wave_sum(cnt);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&s->active, cnt);
+}
+
+// Minimum cut: S_min is the set reached in the residual graph from the
+// nodes that keep excess (the source arcs are saturated).  Down arcs are
+// always residual, so S_min meets every column in a prefix {0..h(p)}; the
+// passes below raise h to the fixed point of the residual arcs.
+__global__ __launch_bounds__(256) void k_mincut_init(Geom g, State st, int *H)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.P) return;
+    int h = -1;
+    for (int z = 0; z < g.K; ++z)
+        if (st.e[z * g.P + p] > 0) h = z;
+    H[p] = h;
+}
+
+__global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, Scratch *s)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.P) return;
+    const int P = g.P, K = g.K, N = g.N, dl = g.delta;
+    int x = p / g.ny, y = p - x * g.ny;
+    const int h0 = H[p];
+    int h = h0;
+    for (int k = 0; k < 4; ++k) {
+        int qq = nbr(g, x, y, p, k);
+        if (qq < 0) continue;
+        int hq = H[qq];
+        if (hq < 0) continue;
+        // forward lateral arcs of q's reached prefix land at heights <= hq - delta (or 0)
+        h = max(h, hq > dl ? hq - dl : 0);
+        // reverse residual of p's own lateral arcs into q's reached prefix
+        int top = min(K - 1, hq + dl);
+        for (int z = top; z > h; --z) {
+            if (lat_arc(z, dl) && st.fl[(size_t)k * N + z * P + p] > 0) { h = z; break; }
+        }
+    }
+    // reverse residual of down arcs with flow: (p,h) -> (p,h+1)
+    while (h >= 0 && h + 1 < K && st.fd[(h + 1) * P + p] > 0) ++h;
+    if (h != h0) {
+        H[p] = h;
+        s->changed = 1;
+    }
+}
+
+// Flow value F = sum_v (w+(v) - ts(v)) and energy E = sum_p c(p, h(p)).
+__global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Geom g, State st,
+                                                const int *H, Scratch *s)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    long long r = 0, en = 0;
+    if (p < g.P) {
+        for (int z = 0; z < g.K; ++z) r += st.ts[z * g.P + p];
+        int h = H[p];
+        if (h >= 0) en = cost[(long long)p * g.K + h];
+    }
+    r = wave_sum64(r);
+    en = wave_sum64(en);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long *)&s->flow, (unsigned long long)(-r));
+        atomicAdd((unsigned long long *)&s->energy, (unsigned long long)en);
+    }
+}
+
+// Level-major state -> caller's z-fastest layout.
+__global__ void k_export(Geom g, State st, int *e, int *ts, int *fd, int *fl)
+{
+    long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= g.N) return;
+    int p = (int)(o / g.K), z = (int)(o - (long long)p * g.K);
+    int v = z * g.P + p;
+    e[o] = st.e[v];
+    ts[o] = st.ts[v];
+    fd[o] = st.fd[v];
+    for (int k = 0; k < 4; ++k) fl[(long long)k * g.N + o] = st.fl[(long long)k * g.N + v];
+}
+
+// ---- launchers --------------------------------------------------------------
+
+static inline unsigned cols_blocks(const Geom &g) { return (unsigned)((g.P + 255) / 256); }
+
+void launch_init_scratch(Scratch *s, hipStream_t st) { hipLaunchKernelGGL(k_init_scratch, 1, 1, 0, st, s); }
+void launch_set_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_set_int, 1, 1, 0, st, p, v); }
+
+void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bottom_max, dim3(cols_blocks(g)), dim3(256), 0, st, cost, g.P, g.K, s);
+    dim3 grid((g.P + 63) / 64, (g.K + 63) / 64);
+    hipLaunchKernelGGL(k_build, grid, dim3(256), 0, st, cost, g, sv, s);
+}
+
+void launch_bfs_reset(const Geom &g, const State &sv, hipStream_t st)
+{
+    unsigned blocks = (unsigned)(((long long)g.N + 255) / 256);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, sv.d, g.N, kInf);
+}
+
+void launch_bfs_pass(const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bfs_pass, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+}
+
+void launch_push(const Geom &g, const State &sv, Scratch *s, bool down, hipStream_t st)
+{
+    if (down)
+        hipLaunchKernelGGL(k_push<true>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+    else
+        hipLaunchKernelGGL(k_push<false>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+}
+
+void launch_relabel(const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_relabel, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+}
+
+void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mincut_init, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, H);
+}
+
+void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mincut_pass, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, H, s);
+}
+
+void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finish, dim3(cols_blocks(g)), dim3(256), 0, st, cost, g, sv, H, s);
+}
+
+void launch_export(const Geom &g, const State &sv, int *e, int *ts, int *fd, int *fl,
+                   hipStream_t st)
+{
+    unsigned blocks = (unsigned)(((long long)g.N + 255) / 256);
+    hipLaunchKernelGGL(k_export, dim3(blocks), dim3(256), 0, st, g, sv, e, ts, fd, fl);
+}
+
+}  // namespace smf

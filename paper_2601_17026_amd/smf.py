@@ -1,0 +1,161 @@
+"""Python binding of the C-ABI library `_libsmf.so` (declared in include/smf.h).
+
+Argument marshalling only: torch tensors provide device memory and streams,
+every step of the solve runs in the library's HIP kernels.  Importing this
+module loads the library and raises if it is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_libsmf.so")
+
+OK = 0
+ERR_ARG = -1
+ERR_NOMEM = -2
+ERR_RANGE = -3
+ERR_NOT_CONVERGED = -4
+ERR_HIP = -5
+ERR_NOT_SOLVED = -6
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "or python paper_2601_17026_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+
+_lib.smf_create.argtypes = [_I32, _I32, _I32, _I32]
+_lib.smf_create.restype = _P
+_lib.smf_destroy.argtypes = [_P]
+_lib.smf_destroy.restype = None
+_lib.smf_solve.argtypes = [_P, _P, _P]
+_lib.smf_flow_value.argtypes = [_P, _PI64]
+_lib.smf_energy.argtypes = [_P, _PI64]
+_lib.smf_surface.argtypes = [_P, _P, _P]
+_lib.smf_export_state.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.smf_set_param.argtypes = [_P, ctypes.c_char_p, _I64]
+_lib.smf_get_stat.argtypes = [_P, ctypes.c_char_p, _PI64]
+_lib.smf_status_string.argtypes = [ctypes.c_int]
+_lib.smf_status_string.restype = ctypes.c_char_p
+_lib.smf_last_error.argtypes = []
+_lib.smf_last_error.restype = ctypes.c_char_p
+for _name in ("smf_solve", "smf_flow_value", "smf_energy", "smf_surface",
+              "smf_export_state", "smf_set_param", "smf_get_stat"):
+    getattr(_lib, _name).restype = ctypes.c_int
+
+EXPORTED = ("smf_create", "smf_destroy", "smf_solve", "smf_flow_value", "smf_energy",
+            "smf_surface", "smf_export_state", "smf_set_param", "smf_get_stat",
+            "smf_status_string", "smf_last_error")
+
+
+class SmfError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.smf_last_error().decode() or _lib.smf_status_string(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise SmfError(status, where)
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_i32(t: torch.Tensor, shape, name: str) -> torch.Tensor:
+    if t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous int32 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class Solver:
+    """One solver handle for nx x ny x K volumes with smoothness bound delta."""
+
+    def __init__(self, nx: int, ny: int, K: int, delta: int):
+        self.shape = (int(nx), int(ny), int(K))
+        self.delta = int(delta)
+        h = _lib.smf_create(int(nx), int(ny), int(K), int(delta))
+        if not h:
+            raise SmfError(ERR_NOMEM, "smf_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.smf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_param(self, key: str, value: int) -> None:
+        _check(_lib.smf_set_param(self._h, key.encode(), int(value)), f"smf_set_param({key})")
+
+    def stat(self, key: str) -> int:
+        out = ctypes.c_int64()
+        _check(_lib.smf_get_stat(self._h, key.encode(), ctypes.byref(out)), f"smf_get_stat({key})")
+        return out.value
+
+    def stats(self) -> dict:
+        return {k: self.stat(k) for k in
+                ("sweeps", "global_relabels", "bfs_passes", "mincut_passes", "gap_relabels")}
+
+    def solve(self, cost: torch.Tensor, stream=None) -> None:
+        _dev_i32(cost, self.shape, "cost")
+        _check(_lib.smf_solve(self._h, cost.data_ptr(), _stream_ptr(stream)), "smf_solve")
+
+    def flow_value(self) -> int:
+        out = ctypes.c_int64()
+        _check(_lib.smf_flow_value(self._h, ctypes.byref(out)), "smf_flow_value")
+        return out.value
+
+    def energy(self) -> int:
+        out = ctypes.c_int64()
+        _check(_lib.smf_energy(self._h, ctypes.byref(out)), "smf_energy")
+        return out.value
+
+    def surface(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        nx, ny, _ = self.shape
+        if out is None:
+            out = torch.empty((nx, ny), dtype=torch.int32, device="cuda")
+        _dev_i32(out, (nx, ny), "out")
+        _check(_lib.smf_surface(self._h, out.data_ptr(), _stream_ptr(stream)), "smf_surface")
+        return out
+
+    def export_state(self, stream=None):
+        """Final preflow as (excess, sink_res, flow_down, flow_lat) device tensors."""
+        nx, ny, K = self.shape
+        e = torch.empty((nx, ny, K), dtype=torch.int32, device="cuda")
+        ts = torch.empty_like(e)
+        fd = torch.empty_like(e)
+        fl = torch.empty((4, nx, ny, K), dtype=torch.int32, device="cuda")
+        _check(_lib.smf_export_state(self._h, e.data_ptr(), ts.data_ptr(), fd.data_ptr(),
+                                     fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
+        return e, ts, fd, fl
+
+
+def solve(cost: torch.Tensor, delta: int, stream=None):
+    """Solves one (nx, ny, K) int32 CUDA volume; returns (flow, energy, surface)."""
+    with Solver(*cost.shape, delta) as s:
+        s.solve(cost, stream)
+        surf = s.surface(stream=stream)
+        return s.flow_value(), s.energy(), surf
