@@ -1,0 +1,195 @@
+"""Benchmark: Mvoxels/s to the exact max-flow value and minimal-cut surface.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+One step is one complete solve (graph build, push-relabel with global
+relabels, minimum-cut surface, flow value and energy) of the seismic-scale
+volume: 512 x 512 columns x K = 384 nodes, delta = 2, five nested synthetic
+horizons with sigma 0.4, costs in [0, 1023] and 10% random fault columns.
+The cost volume is resident in HBM before the timed region starts.  Prints
+one JSON line.  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+# Algorithmic bytes per node moved by one launch of each kernel class: the
+# state words the kernel must read (and, for the build, write) for every
+# node of the volume, not counting re-reads of neighbours' words.
+BYTES_PER_NODE = {
+    "build": 4 + 32,           # cost in, 8 state words out
+    "bfs_reset": 4,            # label write
+    "bfs": 4 + 4 + 4 + 16,     # label, sink residual, down flow, 4 lateral flows
+    "push": 8,                 # excess + label scan (active nodes add more)
+    "relabel": 8,              # label + excess scan (active nodes add more)
+    "mincut": 4,               # excess scan / per-column flow probes
+    "finish": 4,               # sink residual reduction
+}
+KERNEL_OF_CLASS = {"bfs": "k_bfs_pass", "push": "k_push", "relabel": "k_relabel",
+                   "build": "k_build", "bfs_reset": "k_fill", "mincut": "k_mincut_pass",
+                   "finish": "k_finish"}
+
+WORKLOAD = ("seismic 512x512x384 delta=2: five nested synthetic horizons, sigma 0.4, "
+            "costs 0..1023, 10% uniform-random fault columns")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-crop", type=int, default=48,
+                    help="columns per side of the oracle's CPU sample")
+    return ap.parse_args()
+
+
+def kernel_source_sha() -> str:
+    path = os.path.join(ROOT, "paper_2601_17026_amd", "csrc", "smf_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get("kernels", {}).get(kernel)
+    if not ent or rec.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cost, delta, crop):
+    import numpy as np
+
+    import oracle
+
+    sub = np.ascontiguousarray(cost[:crop, :crop])
+    t = time.perf_counter()
+    oracle.solve(sub, delta)
+    dt = time.perf_counter() - t
+    return {
+        "value": round(sub.size / dt / 1e6, 4),
+        "unit": "Mvoxels/s",
+        "cores": 1,
+        "kind": "oracle",
+        "seconds": round(dt, 2),
+        "sample": f"x<{crop}, y<{crop} crop ({crop}x{crop}x{cost.shape[2]}) of the same "
+                  f"volume, delta={delta}; single-threaded Dinic (oracle/oracle.c)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the volume is solved whole on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2601_17026_amd import smf, synth
+
+    cost, delta = synth.config_seismic()
+    nx, ny, K = cost.shape
+    V = cost.size
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    c = torch.from_numpy(cost).to(dev)
+    stream = torch.cuda.current_stream()
+    solver = smf.Solver(nx, ny, K, delta)
+    for _ in range(args.warmup):
+        solver.solve(c, stream)
+
+    solver.set_param("kernel_timing", 1)
+    classes = list(BYTES_PER_NODE)
+    tot_ns = {k: 0 for k in classes}
+    tot_n = {k: 0 for k in classes}
+    sweeps = relabels = passes = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(c, stream)
+        for k in classes:
+            tot_ns[k] += solver.stat(f"time_ns.{k}")
+            tot_n[k] += solver.stat(f"launches.{k}")
+        sweeps += solver.stat("sweeps")
+        relabels += solver.stat("global_relabels")
+        passes += solver.stat("bfs_passes")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    flow, energy = solver.flow_value(), solver.energy()
+    surf = solver.surface(stream=stream)
+    torch.cuda.synchronize()
+    surface_sha = hashlib.sha256(surf.cpu().numpy().tobytes()).hexdigest()
+    solver.close()
+
+    ms = 1e3 * elapsed / args.steps
+    value = V * args.steps / elapsed / 1e6
+
+    dom = max(classes, key=lambda k: tot_ns[k])
+    avg_ns = tot_ns[dom] / max(1, tot_n[dom])
+    alg = BYTES_PER_NODE[dom] * V
+    achieved = alg / avg_ns   # bytes/ns = GB/s
+    traffic = stored_traffic(KERNEL_OF_CLASS[dom])
+    roof = {
+        "bound": "hbm",
+        "kernel": KERNEL_OF_CLASS[dom],
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": alg,
+        "avg_launch_us": round(avg_ns / 1e3, 2),
+        "launches": tot_n[dom],
+    }
+    kernels = {k: {"ms_per_step": round(tot_ns[k] / 1e6 / args.steps, 3),
+                   "launches_per_step": tot_n[k] / args.steps,
+                   "avg_us": round(tot_ns[k] / max(1, tot_n[k]) / 1e3, 2),
+                   "GBps_alg": round(BYTES_PER_NODE[k] * V / (tot_ns[k] / max(1, tot_n[k])), 1)
+                   if tot_n[k] else None}
+               for k in classes}
+
+    out = {
+        "metric": "Mvoxels/s to exact maxflow+surface",
+        "value": round(value, 3),
+        "unit": "Mvoxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 2),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "nx": nx, "ny": ny, "K": K, "delta": delta,
+                   "voxels": V, "mode": "plain"},
+        "roofline": roof,
+        "result": {"flow": flow, "energy": energy, "surface_sha256": surface_sha},
+        "per_step": {"sweeps": sweeps / args.steps, "global_relabels": relabels / args.steps,
+                     "bfs_passes": passes / args.steps},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cost, delta, args.cpu_crop)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

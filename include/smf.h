@@ -99,11 +99,15 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *   "max_sweeps"      -- sweep cap before SMF_ERR_NOT_CONVERGED (>= 1)
  *   "poll_every"      -- sweeps between host termination checks (>= 1)
  *   "bfs_poll_every"  -- BFS passes between host convergence checks (>= 1)
+ *   "kernel_timing"   -- 1: bracket every kernel launch of a solve with HIP
+ *                        events on the solve stream (for benchmarks); 0: off
  * Returns SMF_ERR_ARG for an unknown key or an out-of-range value. */
 int smf_set_param(smf_handle *h, const char *key, int64_t value);
 
 /* Counters of the last solve.  Keys: "sweeps", "global_relabels",
- * "bfs_passes", "mincut_passes", "gap_relabels". */
+ * "bfs_passes", "mincut_passes", "gap_relabels", and with kernel_timing on,
+ * "time_ns.<class>" (summed event time) and "launches.<class>" for the
+ * kernel classes build, bfs_reset, bfs, push, relabel, mincut, finish. */
 int smf_get_stat(const smf_handle *h, const char *key, int64_t *out);
 
 /* Static text for a status code. */

@@ -41,6 +41,7 @@ struct Scratch {
     long long flow;      // sum of flow into t
     long long energy;    // sum_p c(p, h(p))
     long long pad[2];
+    int lvl_changed[64]; // BFS level L labelled something: slot L % 64
 };
 
 // Lateral arcs kept by the solver: (p,z) -> (q, z - delta) for z > delta,

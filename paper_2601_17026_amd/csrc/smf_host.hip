@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/smf.h"
 #include "smf_device.h"
@@ -23,8 +24,10 @@ namespace smf {
 void launch_init_scratch(Scratch *s, hipStream_t st);
 void launch_set_int(int *p, int v, hipStream_t st);
 void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st);
-void launch_bfs_reset(const Geom &g, const State &sv, hipStream_t st);
-void launch_bfs_pass(const Geom &g, const State &sv, Scratch *s, hipStream_t st);
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, Scratch *s, hipStream_t st);
+void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
+                      int *Tout, int *LFout, Scratch *s, hipStream_t st);
+void launch_fill(int *a, int n, int v, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, Scratch *s, bool down, hipStream_t st);
 void launch_relabel(const Geom &g, const State &sv, Scratch *s, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
@@ -52,11 +55,83 @@ static int fail(int code, const std::string &msg)
             return fail(SMF_ERR_HIP, std::string(#call ": ") + hipGetErrorString(err_)); \
     } while (0)
 
+// Optional per-kernel timing with HIP events recorded on the solve stream
+// around every launch of a kernel class; read back at the host sync points.
+enum KClass { KC_BUILD, KC_BFS_RESET, KC_BFS, KC_PUSH, KC_RELABEL, KC_MINCUT, KC_FINISH, KC_COUNT };
+static const char *const kKClassName[KC_COUNT] = {"build", "bfs_reset", "bfs", "push", "relabel",
+                                                  "mincut", "finish"};
+
+struct KernelTimer {
+    bool on = false;
+    struct Pending { int kc; hipEvent_t a, b; };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    double ns[KC_COUNT] = {};
+    int64_t launches[KC_COUNT] = {};
+
+    hipEvent_t take()
+    {
+        if (pool.empty()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    void reset()
+    {
+        for (int i = 0; i < KC_COUNT; ++i) { ns[i] = 0; launches[i] = 0; }
+    }
+    // Called after the stream has been synchronised.
+    void collect()
+    {
+        for (auto &p : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                ns[p.kc] += 1e6 * (double)ms;
+                launches[p.kc] += 1;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+    ~KernelTimer()
+    {
+        for (auto &p : pending) { pool.push_back(p.a); pool.push_back(p.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// RAII bracket: records a start event before and an end event after the
+// launches made in its scope.
+struct TimedScope {
+    KernelTimer &t;
+    int kc;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    TimedScope(KernelTimer &t_, int kc_, hipStream_t s_) : t(t_), kc(kc_), s(s_)
+    {
+        if (t.on && (a = t.take())) (void)hipEventRecord(a, s);
+    }
+    ~TimedScope()
+    {
+        if (!a) return;
+        hipEvent_t b = t.take();
+        if (!b) { t.pool.push_back(a); return; }
+        (void)hipEventRecord(b, s);
+        t.pending.push_back({kc, a, b});
+    }
+};
+
 struct smf_handle {
     Geom g{};
     int device = 0;
     int *state = nullptr;      // 8 * N int32
     int *H = nullptr;          // P int32 surface
+    int *bfs = nullptr;        // 10 * P int32: two per-column BFS records (T, LF[4])
     Scratch *scr = nullptr;    // device scratch
     Scratch *host = nullptr;   // pinned mirror
     State st{};
@@ -64,11 +139,12 @@ struct smf_handle {
     int64_t relabel_period = 6;
     int64_t max_sweeps = 2000000;
     int64_t poll_every = 1;
-    int64_t bfs_poll_every = 1;
+    int64_t bfs_poll_every = 8;
     // results and counters of the last solve
     bool solved = false;
     int64_t flow = 0, energy = 0;
     int64_t sweeps = 0, global_relabels = 0, bfs_passes = 0, mincut_passes = 0, gap_relabels = 0;
+    KernelTimer timer;
 };
 
 static void release(smf_handle *h)
@@ -76,6 +152,7 @@ static void release(smf_handle *h)
     if (!h) return;
     if (h->state) (void)hipFree(h->state);
     if (h->H) (void)hipFree(h->H);
+    if (h->bfs) (void)hipFree(h->bfs);
     if (h->scr) (void)hipFree(h->scr);
     if (h->host) (void)hipHostFree(h->host);
     delete h;
@@ -105,6 +182,7 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
     if (hipGetDevice(&h->device) != hipSuccess ||
         hipMalloc((void **)&h->state, sizeof(int) * 8 * (size_t)N) != hipSuccess ||
         hipMalloc((void **)&h->H, sizeof(int) * (size_t)h->g.P) != hipSuccess ||
+        hipMalloc((void **)&h->bfs, sizeof(int) * 10 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->scr, sizeof(Scratch)) != hipSuccess ||
         hipHostMalloc((void **)&h->host, sizeof(Scratch), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -130,6 +208,7 @@ static int sync_scratch(smf_handle *h, hipStream_t s)
 {
     HIP_TRY(hipMemcpyAsync(h->host, h->scr, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    h->timer.collect();
     if (h->host->err & kErrCostRange)
         return fail(SMF_ERR_RANGE, "smf_solve: a cost lies outside (-2^30, 2^30)");
     if (h->host->err & kErrOverflow)
@@ -137,25 +216,34 @@ static int sync_scratch(smf_handle *h, hipStream_t s)
     return SMF_OK;
 }
 
-// Exact global relabel: reset all labels, then column passes of the
-// reverse breadth-first search until a pass changes nothing.
+// Exact global relabel: level 1 from the sink arcs, then one launch per BFS
+// level until a level labels nothing; the host checks every bfs_poll_every
+// levels (levels after the last productive one are no-ops).
 static int global_relabel(smf_handle *h, hipStream_t s)
 {
-    launch_bfs_reset(h->g, h->st, s);
-    int64_t passes = 0;
+    const int P = h->g.P;
+    int *T[2] = {h->bfs, h->bfs + 5 * (size_t)P};
+    int *LF[2] = {h->bfs + P, h->bfs + 6 * (size_t)P};
+    {
+        TimedScope ts(h->timer, KC_BFS_RESET, s);
+        launch_bfs_init(h->g, h->st, T[1], LF[1], h->scr, s);   // level 1 lives in buffer 1
+    }
+    int L = 1;
     for (;;) {
-        for (int64_t i = 0; i < h->bfs_poll_every; ++i) {
-            launch_set_int(&h->scr->changed, 0, s);
-            launch_bfs_pass(h->g, h->st, h->scr, s);
+        for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L) {
+            {
+                TimedScope ts(h->timer, KC_BFS, s);
+                launch_bfs_level(h->g, h->st, L, T[L & 1], LF[L & 1], T[(L + 1) & 1],
+                                 LF[(L + 1) & 1], h->scr, s);
+            }
             h->bfs_passes++;
-            passes++;
         }
+        HIP_TRY(hipGetLastError());
         int rc = sync_scratch(h, s);
         if (rc) return rc;
-        if (!h->host->changed) break;
-        // labels only decrease from kInf towards the exact distances: a
-        // pass count beyond N + 2 means a defect, not a slow search
-        if (passes > (int64_t)h->g.N + 2 + h->bfs_poll_every)
+        if (!h->host->lvl_changed[(L - 1) & 63]) break;   // the last level launched
+        // every productive level lowers at least one threshold by >= 1
+        if ((int64_t)L > (int64_t)h->g.N + 2 + h->bfs_poll_every)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: breadth-first search did not settle");
     }
     h->global_relabels++;
@@ -171,8 +259,12 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     h->sweeps = h->global_relabels = h->bfs_passes = h->mincut_passes = h->gap_relabels = 0;
     HIP_TRY(hipSetDevice(h->device));
 
+    h->timer.reset();
     launch_init_scratch(h->scr, s);
-    launch_build(cost_dev, h->g, h->st, h->scr, s);
+    {
+        TimedScope ts(h->timer, KC_BUILD, s);
+        launch_build(cost_dev, h->g, h->st, h->scr, s);
+    }
     HIP_TRY(hipGetLastError());
     int rc = sync_scratch(h, s);
     if (rc) return rc;
@@ -188,9 +280,15 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
                 rc = global_relabel(h, s);
                 if (rc) return rc;
             }
-            launch_push(h->g, h->st, h->scr, (h->sweeps & 1) == 0, s);
+            {
+                TimedScope ts(h->timer, KC_PUSH, s);
+                launch_push(h->g, h->st, h->scr, (h->sweeps & 1) == 0, s);
+            }
             launch_set_int(&h->scr->active, 0, s);
-            launch_relabel(h->g, h->st, h->scr, s);
+            {
+                TimedScope ts(h->timer, KC_RELABEL, s);
+                launch_relabel(h->g, h->st, h->scr, s);
+            }
             h->sweeps++;
         }
         HIP_TRY(hipGetLastError());
@@ -199,10 +297,16 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
         done = h->host->active == 0;
     }
 
-    launch_mincut_init(h->g, h->st, h->H, s);
+    {
+        TimedScope ts(h->timer, KC_MINCUT, s);
+        launch_mincut_init(h->g, h->st, h->H, s);
+    }
     for (;;) {
         launch_set_int(&h->scr->changed, 0, s);
-        launch_mincut_pass(h->g, h->st, h->H, h->scr, s);
+        {
+            TimedScope ts(h->timer, KC_MINCUT, s);
+            launch_mincut_pass(h->g, h->st, h->H, h->scr, s);
+        }
         h->mincut_passes++;
         rc = sync_scratch(h, s);
         if (rc) return rc;
@@ -210,7 +314,10 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
         if (h->mincut_passes > (int64_t)h->g.N + 2)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: minimum-cut search did not settle");
     }
-    launch_finish(cost_dev, h->g, h->st, h->H, h->scr, s);
+    {
+        TimedScope ts(h->timer, KC_FINISH, s);
+        launch_finish(cost_dev, h->g, h->st, h->H, h->scr, s);
+    }
     HIP_TRY(hipGetLastError());
     rc = sync_scratch(h, s);
     if (rc) return rc;
@@ -265,6 +372,11 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     else if (!strcmp(key, "max_sweeps")) slot = &h->max_sweeps;
     else if (!strcmp(key, "poll_every")) slot = &h->poll_every;
     else if (!strcmp(key, "bfs_poll_every")) slot = &h->bfs_poll_every;
+    else if (!strcmp(key, "kernel_timing")) {
+        if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: kernel_timing is 0 or 1");
+        h->timer.on = value == 1;
+        return SMF_OK;
+    }
     if (!slot) return fail(SMF_ERR_ARG, std::string("smf_set_param: unknown key ") + key);
     if (value < 1) return fail(SMF_ERR_ARG, std::string("smf_set_param: ") + key + " must be >= 1");
     *slot = value;
@@ -279,6 +391,15 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
     else if (!strcmp(key, "bfs_passes")) *out = h->bfs_passes;
     else if (!strcmp(key, "mincut_passes")) *out = h->mincut_passes;
     else if (!strcmp(key, "gap_relabels")) *out = h->gap_relabels;
+    else if (!strncmp(key, "time_ns.", 8) || !strncmp(key, "launches.", 9)) {
+        bool t = key[0] == 't';
+        const char *name = key + (t ? 8 : 9);
+        int kc = -1;
+        for (int i = 0; i < KC_COUNT; ++i)
+            if (!strcmp(name, kKClassName[i])) kc = i;
+        if (kc < 0) return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown kernel class in ") + key);
+        *out = t ? (int64_t)h->timer.ns[kc] : h->timer.launches[kc];
+    }
     else return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown key ") + key);
     return SMF_OK;
 }

@@ -140,57 +140,130 @@ __global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geo
     if (bad) atomicOr(&s->err, kErrCostRange);
 }
 
-// One pass of the reverse breadth-first search from t, in column form: a
-// thread takes its column up (length-0 down arcs and the sink and lateral
-// terms) and then down (length-1 reverse arcs of down arcs with flow).
-// Repeated until no label changes, it yields the exact weighted residual
-// distances (kInf where t is unreachable): the global relabelling.
-__global__ __launch_bounds__(256) void k_bfs_pass(Geom g, State st, Scratch *s)
+// Loads are issued a chunk of kCh levels at a time so that a thread keeps
+// many independent loads in flight instead of one level's worth.
+constexpr int kCh = 8;
+
+// ---- global relabel: level-synchronous reverse breadth-first search -------
+//
+// Exact weighted residual distances to t (Section 2.1 global relabelling;
+// the level-by-level order of Section 3.2.2 / Algorithm 3).  Because the
+// down arc (p,z) -> (p,z-1) is always residual with length 0, an exact label
+// never increases down a column: d(p,z) <= d(p,z-1).  So the set of nodes at
+// distance <= L meets column p in a suffix [T_L(p), K), and one BFS level is
+// a min-plus update of the per-column thresholds:
+//   T_{L+1}(p) = min( T_L(p),
+//       lowest z with a lateral arc into q's labelled suffix:
+//           0 if T_L(q) = 0, else T_L(q) + delta (when < K);
+//       lowest z with a reverse lateral arc into it: the head height of the
+//           lowest arc (q,z') -> (p, .) with flow > 0 and z' >= T_L(q);
+//       T_L(p) - 1 if the down arc into (p, T_L(p)) carries flow ),
+// and the labels d = L+1 are written once, on [T_{L+1}(p), T_L(p)).  Level 1
+// is the suffix above the lowest node with a residual sink arc.  The whole
+// search reads and writes every node O(1) times; each level touches only
+// nx*ny thresholds plus the nodes it labels.
+//
+// Per-column BFS record, double-buffered by level parity:
+//   T[p]      threshold T_L(p) (K when no node of the column is labelled);
+//   LF[k][p]  lowest z' >= T_L(p) whose lateral arc in direction k carries
+//             flow (K if none) -- the reverse-arc term seen by neighbour k.
+
+__device__ __forceinline__ int lat_head_of(int zp, int dl) { return zp == 0 ? 0 : zp - dl; }
+
+__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, Scratch *s)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) s->lvl_changed[1] = 0;
+    if (p >= g.P) return;
+    const int P = g.P, K = g.K, N = g.N;
+    int t1 = K;
+    int lf[4] = {K, K, K, K};
+    for (int z0 = 0; z0 < K; z0 += kCh) {
+        int tsv[kCh], fv[4][kCh];
+#pragma unroll
+        for (int j = 0; j < kCh; ++j) {
+            const int z = z0 + j;
+            tsv[j] = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) fv[k][j] = 0;
+            if (z >= K) continue;
+            const int u = z * P + p;
+            tsv[j] = st.ts[u];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) fv[k][j] = st.fl[(size_t)k * N + u];
+        }
+#pragma unroll
+        for (int j = 0; j < kCh; ++j) {
+            const int z = z0 + j;
+            if (z >= K) break;
+            if (t1 == K && tsv[j] > 0) t1 = z;
+            const bool lab = t1 < K;
+            st.d[z * P + p] = lab ? 1 : kInf;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (lab && lf[k] == K && fv[k][j] > 0) lf[k] = z;
+        }
+    }
+    T[p] = t1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) LF[k * P + p] = lf[k];
+}
+
+// Level L -> L+1.  Reads the level-L records (Tin, LFin), writes level L+1.
+__global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
+                                                   const int *__restrict__ LFin, int *__restrict__ Tout,
+                                                   int *__restrict__ LFout, Scratch *s)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // the flag of the next level is cleared here; stream order puts this
+    // before every write of level L+1
+    if (p == 0) s->lvl_changed[(L + 1) & 63] = 0;
     if (p >= g.P) return;
     const int P = g.P, K = g.K, N = g.N, dl = g.delta;
     int x = p / g.ny, y = p - x * g.ny;
-    int q[4];
-    for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
-    int changed = 0, prev = kInf;
-    for (int z = 0; z < K; ++z) {
-        int u = z * P + p;
-        int du = st.d[u];
-        int b = min(du, prev);
-        if (st.ts[u] > 0) b = min(b, 1);
-        if (lat_arc(z, dl)) {
-            int zh = lat_head(z, dl) * P;
-            for (int k = 0; k < 4; ++k)
-                if (q[k] >= 0) b = min(b, st.d[zh + q[k]] + 1);
-        }
-        int zt = lat_tail(z, dl, K);
-        if (zt >= 0) {
-            for (int k = 0; k < 4; ++k) {
-                if (q[k] < 0) continue;
-                int w = zt * P + q[k];
-                if (st.fl[(size_t)(k ^ 1) * N + w] > 0) b = min(b, st.d[w] + 1);
+    const int T = Tin[p];
+    int cand = T;
+    for (int k = 0; k < 4; ++k) {
+        const int q = nbr(g, x, y, p, k);
+        if (q < 0) continue;
+        const int tq = Tin[q];
+        if (tq == 0) cand = 0;
+        else if (tq + dl < K) cand = min(cand, tq + dl);
+        const int lq = LFin[(k ^ 1) * P + q];
+        if (lq < K) cand = min(cand, lat_head_of(lq, dl));
+    }
+    if (T >= 1 && T < K && st.fd[T * P + p] > 0) cand = min(cand, T - 1);
+    int lf[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lf[k] = LFin[k * P + p];
+    if (cand < T) {
+        const int lab = L + 1;
+        // label the newly reached nodes and extend the flow scans downwards;
+        // walking from the top of the new range keeps the lowest hit
+        for (int z0 = T - 1; z0 >= cand; z0 -= kCh) {
+            int fv[4][kCh];
+#pragma unroll
+            for (int j = 0; j < kCh; ++j) {
+                const int z = z0 - j;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    fv[k][j] = z >= cand ? st.fl[(size_t)k * N + z * P + p] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kCh; ++j) {
+                const int z = z0 - j;
+                if (z < cand) break;
+                st.d[z * P + p] = lab;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (fv[k][j] > 0) lf[k] = z;
             }
         }
-        b = min(b, kInf);
-        if (b < du) {
-            st.d[u] = b;
-            changed = 1;
-        }
-        prev = b;
+        s->lvl_changed[L & 63] = 1;
     }
-    int nxt = prev;
-    for (int z = K - 2; z >= 0; --z) {
-        int u = z * P + p;
-        int du = st.d[u];
-        if (st.fd[u + P] > 0 && nxt + 1 < du) {
-            du = nxt + 1;
-            st.d[u] = du;
-            changed = 1;
-        }
-        nxt = du;
-    }
-    if (changed) s->changed = 1;
+    Tout[p] = cand;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
 }
 
 // Push phase of one sweep (labels fixed).  The thread owning column p walks
@@ -210,14 +283,28 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Scratch *s)
     for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
     int err = 0;
     long long carry = 0;
-    for (int i = 0; i < K; ++i) {
+    for (int i0 = 0; i0 < K; i0 += kCh) {
+      int ev[kCh], dv[kCh];
+#pragma unroll
+      for (int j = 0; j < kCh; ++j) {
+          const int i = i0 + j;
+          ev[j] = 0;
+          dv[j] = kInf;
+          if (i >= K) continue;
+          const int u = (kDown ? K - 1 - i : i) * P + p;
+          ev[j] = st.e[u];
+          dv[j] = st.d[u];
+      }
+      for (int j = 0; j < kCh; ++j) {
+        const int i = i0 + j;
+        if (i >= K) break;
         const int z = kDown ? K - 1 - i : i;
         const int u = z * P + p;
         long long ex = carry;
         carry = 0;
-        const int eu = st.e[u];
+        const int eu = ev[j];
         if (eu <= 0 && ex == 0) continue;
-        const int du = st.d[u];
+        const int du = dv[j];
         if (du >= kInf) {
             if (ex) add_excess(st.e, u, ex, err);   // not reached: carries follow admissible arcs
             continue;
@@ -279,6 +366,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Scratch *s)
             }
         }
         if (ex > 0) add_excess(st.e, u, ex, err);
+      }
     }
     if (err) atomicOr(&s->err, kErrOverflow);
 }
@@ -297,10 +385,23 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Scratch *s)
         int q[4];
         for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
         int prev = kInf;
-        for (int z = 0; z < K; ++z) {
+        for (int z0 = 0; z0 < K; z0 += kCh) {
+          int ev[kCh], dv[kCh];
+#pragma unroll
+          for (int j = 0; j < kCh; ++j) {
+              const int z = z0 + j;
+              ev[j] = 0;
+              dv[j] = kInf;
+              if (z >= K) continue;
+              ev[j] = st.e[z * P + p];
+              dv[j] = st.d[z * P + p];
+          }
+          for (int j = 0; j < kCh; ++j) {
+            const int z = z0 + j;
+            if (z >= K) break;
             const int u = z * P + p;
-            int du = st.d[u];
-            if (du < kInf && st.e[u] > 0) {
+            int du = dv[j];
+            if (du < kInf && ev[j] > 0) {
                 int b = prev;
                 if (st.ts[u] > 0) b = min(b, 1);
                 if (z + 1 < K && st.fd[u + P] > 0) b = min(b, st.d[u + P] + 1);
@@ -324,6 +425,7 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Scratch *s)
                 if (du < kInf) ++cnt;
             }
             prev = du;
+          }
         }
     }
     cnt = wave_sum(cnt);
@@ -419,15 +521,21 @@ void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, h
     hipLaunchKernelGGL(k_build, grid, dim3(256), 0, st, cost, g, sv, s);
 }
 
-void launch_bfs_reset(const Geom &g, const State &sv, hipStream_t st)
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, Scratch *s, hipStream_t st)
 {
-    unsigned blocks = (unsigned)(((long long)g.N + 255) / 256);
-    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, sv.d, g.N, kInf);
+    hipLaunchKernelGGL(k_bfs_init, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, T, LF, s);
 }
 
-void launch_bfs_pass(const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
+                      int *Tout, int *LFout, Scratch *s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_pass, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+    hipLaunchKernelGGL(k_bfs_level, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, L, Tin, LFin,
+                       Tout, LFout, s);
+}
+
+void launch_fill(int *a, int n, int v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n, v);
 }
 
 void launch_push(const Geom &g, const State &sv, Scratch *s, bool down, hipStream_t st)
