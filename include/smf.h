@@ -98,7 +98,10 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1)
  *   "max_sweeps"      -- sweep cap before SMF_ERR_NOT_CONVERGED (>= 1)
  *   "poll_every"      -- sweeps between host termination checks (>= 1)
- *   "bfs_poll_every"  -- BFS passes between host convergence checks (>= 1)
+ *   "bfs_poll_every"  -- BFS levels between host convergence checks (>= 1)
+ *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
+ *                        with excess is labelled; 0: always run it to the end
+ *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
  *   "kernel_timing"   -- 1: bracket every kernel launch of a solve with HIP
  *                        events on the solve stream (for benchmarks); 0: off
  * Returns SMF_ERR_ARG for an unknown key or an out-of-range value. */

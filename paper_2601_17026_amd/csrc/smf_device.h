@@ -13,6 +13,7 @@
 namespace smf {
 
 constexpr int kInf = 0x40000000;       // label of a node that cannot reach t
+constexpr int kUnl = kInf - 1;         // not (yet) reached by the running BFS
 constexpr int kErrCostRange = 1;       // a cost outside (-2^30, 2^30)
 constexpr int kErrOverflow = 2;        // an int32 excess or flow would overflow
 
@@ -40,8 +41,11 @@ struct Scratch {
     int active;          // active nodes after the last relabel phase
     long long flow;      // sum of flow into t
     long long energy;    // sum_p c(p, h(p))
-    long long pad[2];
+    int bfs_active;      // nodes with excess and a finite label when the BFS starts
+    int bfs_labelled;    // ... of which the running BFS has labelled so far
+    int pad_i[2];
     int lvl_changed[64]; // BFS level L labelled something: slot L % 64
+    int lvl_lab[64];     // nodes with excess labelled by level L: slot L % 64
 };
 
 // Lateral arcs kept by the solver: (p,z) -> (q, z - delta) for z > delta,

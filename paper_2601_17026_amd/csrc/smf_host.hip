@@ -24,12 +24,18 @@ namespace smf {
 void launch_init_scratch(Scratch *s, hipStream_t st);
 void launch_set_int(int *p, int v, hipStream_t st);
 void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st);
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, Scratch *s, hipStream_t st);
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *chg, Scratch *s,
+                     hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      int *Tout, int *LFout, Scratch *s, hipStream_t st);
+                      const int *chg_in, int *Tout, int *LFout, int *chg_out, Scratch *s,
+                      hipStream_t st);
 void launch_fill(int *a, int n, int v, hipStream_t st);
-void launch_push(const Geom &g, const State &sv, Scratch *s, bool down, hipStream_t st);
-void launch_relabel(const Geom &g, const State &sv, Scratch *s, hipStream_t st);
+void launch_bfs_fixup(const Geom &g, const State &sv, int v, hipStream_t st);
+
+void launch_push(const Geom &g, const State &sv, const int *rlo_in, const int *rhi_in,
+                 int *rlo_out, int *rhi_out, Scratch *s, bool down, hipStream_t st);
+void launch_relabel(const Geom &g, const State &sv, int *rlo, int *rhi, int *rlo_reset,
+                    int *rhi_reset, Scratch *s, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
 void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
@@ -131,7 +137,8 @@ struct smf_handle {
     int device = 0;
     int *state = nullptr;      // 8 * N int32
     int *H = nullptr;          // P int32 surface
-    int *bfs = nullptr;        // 10 * P int32: two per-column BFS records (T, LF[4])
+    int *bfs = nullptr;        // 12 * P int32: two per-column BFS records (T, LF[4], changed)
+    int *rng = nullptr;        // 4 * P int32: two per-column work ranges (lo, hi)
     Scratch *scr = nullptr;    // device scratch
     Scratch *host = nullptr;   // pinned mirror
     State st{};
@@ -139,7 +146,10 @@ struct smf_handle {
     int64_t relabel_period = 6;
     int64_t max_sweeps = 2000000;
     int64_t poll_every = 1;
-    int64_t bfs_poll_every = 8;
+    int64_t bfs_poll_every = 16;
+    int64_t bfs_early_stop = 1;
+    int64_t verbose = 0;           // 1: progress lines on stderr
+
     // results and counters of the last solve
     bool solved = false;
     int64_t flow = 0, energy = 0;
@@ -153,6 +163,7 @@ static void release(smf_handle *h)
     if (h->state) (void)hipFree(h->state);
     if (h->H) (void)hipFree(h->H);
     if (h->bfs) (void)hipFree(h->bfs);
+    if (h->rng) (void)hipFree(h->rng);
     if (h->scr) (void)hipFree(h->scr);
     if (h->host) (void)hipHostFree(h->host);
     delete h;
@@ -182,7 +193,8 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
     if (hipGetDevice(&h->device) != hipSuccess ||
         hipMalloc((void **)&h->state, sizeof(int) * 8 * (size_t)N) != hipSuccess ||
         hipMalloc((void **)&h->H, sizeof(int) * (size_t)h->g.P) != hipSuccess ||
-        hipMalloc((void **)&h->bfs, sizeof(int) * 10 * (size_t)h->g.P) != hipSuccess ||
+        hipMalloc((void **)&h->bfs, sizeof(int) * 12 * (size_t)h->g.P) != hipSuccess ||
+        hipMalloc((void **)&h->rng, sizeof(int) * 4 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->scr, sizeof(Scratch)) != hipSuccess ||
         hipHostMalloc((void **)&h->host, sizeof(Scratch), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -216,25 +228,32 @@ static int sync_scratch(smf_handle *h, hipStream_t s)
     return SMF_OK;
 }
 
-// Exact global relabel: level 1 from the sink arcs, then one launch per BFS
-// level until a level labels nothing; the host checks every bfs_poll_every
-// levels (levels after the last productive one are no-ops).
+// Global relabel: level 1 from the sink arcs, then one launch per BFS level
+// until a level labels nothing (exact distances; unreached nodes get kInf)
+// or, with bfs_early_stop, until every node that holds excess is labelled
+// (unreached nodes then get the first unfinished level, a valid lower
+// bound).  The host checks every bfs_poll_every levels; levels launched
+// after the last productive one are no-ops.
 static int global_relabel(smf_handle *h, hipStream_t s)
 {
     const int P = h->g.P;
     int *T[2] = {h->bfs, h->bfs + 5 * (size_t)P};
     int *LF[2] = {h->bfs + P, h->bfs + 6 * (size_t)P};
+    int *CH[2] = {h->bfs + 10 * (size_t)P, h->bfs + 11 * (size_t)P};
+    launch_set_int(&h->scr->bfs_active, 0, s);
+    launch_set_int(&h->scr->bfs_labelled, 0, s);
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_init(h->g, h->st, T[1], LF[1], h->scr, s);   // level 1 lives in buffer 1
+        launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], h->scr, s);   // level 1 lives in buffer 1
     }
     int L = 1;
+    int fill = kInf;
     for (;;) {
         for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L) {
             {
                 TimedScope ts(h->timer, KC_BFS, s);
-                launch_bfs_level(h->g, h->st, L, T[L & 1], LF[L & 1], T[(L + 1) & 1],
-                                 LF[(L + 1) & 1], h->scr, s);
+                launch_bfs_level(h->g, h->st, L, T[L & 1], LF[L & 1], CH[L & 1], T[(L + 1) & 1],
+                                 LF[(L + 1) & 1], CH[(L + 1) & 1], h->scr, s);
             }
             h->bfs_passes++;
         }
@@ -242,10 +261,22 @@ static int global_relabel(smf_handle *h, hipStream_t s)
         int rc = sync_scratch(h, s);
         if (rc) return rc;
         if (!h->host->lvl_changed[(L - 1) & 63]) break;   // the last level launched
+        if (h->bfs_early_stop && h->host->bfs_labelled >= h->host->bfs_active) {
+            fill = L + 1;   // levels <= L are complete
+            break;
+        }
         // every productive level lowers at least one threshold by >= 1
         if ((int64_t)L > (int64_t)h->g.N + 2 + h->bfs_poll_every)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: breadth-first search did not settle");
     }
+    {
+        TimedScope ts(h->timer, KC_BFS_RESET, s);
+        launch_bfs_fixup(h->g, h->st, fill, s);
+    }
+    if (h->verbose)
+        fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d levels, active %d, labelled %d, %s\n",
+                (long long)h->global_relabels, (long long)h->sweeps, L - 1, h->host->bfs_active,
+                h->host->bfs_labelled, fill == kInf ? "complete" : "early stop");
     h->global_relabels++;
     return SMF_OK;
 }
@@ -271,6 +302,14 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     rc = global_relabel(h, s);
     if (rc) return rc;
 
+    // work ranges: every column may hold excess anywhere before the first sweep
+    const int P = h->g.P;
+    int *rlo[2] = {h->rng, h->rng + 2 * (size_t)P};
+    int *rhi[2] = {h->rng + P, h->rng + 3 * (size_t)P};
+    launch_fill(rlo[0], P, 0, s);
+    launch_fill(rhi[0], P, h->g.K - 1, s);
+    launch_fill(rlo[1], P, h->g.K, s);
+    launch_fill(rhi[1], P, -1, s);
     bool done = false;
     while (!done) {
         if (h->sweeps >= h->max_sweeps)
@@ -280,14 +319,15 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
                 rc = global_relabel(h, s);
                 if (rc) return rc;
             }
+            const int a = (int)(h->sweeps & 1), b = a ^ 1;
             {
                 TimedScope ts(h->timer, KC_PUSH, s);
-                launch_push(h->g, h->st, h->scr, (h->sweeps & 1) == 0, s);
+                launch_push(h->g, h->st, rlo[a], rhi[a], rlo[b], rhi[b], h->scr, a == 0, s);
             }
             launch_set_int(&h->scr->active, 0, s);
             {
                 TimedScope ts(h->timer, KC_RELABEL, s);
-                launch_relabel(h->g, h->st, h->scr, s);
+                launch_relabel(h->g, h->st, rlo[b], rhi[b], rlo[a], rhi[a], h->scr, s);
             }
             h->sweeps++;
         }
@@ -295,6 +335,7 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
         rc = sync_scratch(h, s);
         if (rc) return rc;
         done = h->host->active == 0;
+        if (h->verbose) fprintf(stderr, "smf: sweep %lld active %d\n", (long long)h->sweeps, h->host->active);
     }
 
     {
@@ -372,6 +413,16 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     else if (!strcmp(key, "max_sweeps")) slot = &h->max_sweeps;
     else if (!strcmp(key, "poll_every")) slot = &h->poll_every;
     else if (!strcmp(key, "bfs_poll_every")) slot = &h->bfs_poll_every;
+    else if (!strcmp(key, "verbose")) {
+        if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: verbose is 0 or 1");
+        h->verbose = value;
+        return SMF_OK;
+    }
+    else if (!strcmp(key, "bfs_early_stop")) {
+        if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: bfs_early_stop is 0 or 1");
+        h->bfs_early_stop = value;
+        return SMF_OK;
+    }
     else if (!strcmp(key, "kernel_timing")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: kernel_timing is 0 or 1");
         h->timer.on = value == 1;

@@ -70,6 +70,8 @@ __global__ void k_init_scratch(Scratch *s)
     s->active = 0;
     s->flow = 0;
     s->energy = 0;
+    s->bfs_active = 0;
+    s->bfs_labelled = 0;
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
@@ -92,7 +94,7 @@ __global__ void k_bottom_max(const int *__restrict__ cost, int P, int K, Scratch
 
 // Graph build: node weights w (Section 1.2), source arcs pre-saturated into
 // the excess (Section 2.1 initialisation), sink residuals, zero flows and
-// labels set to "unknown" for the first breadth-first search.  A 64-column
+// labels 0 (valid lower bounds) until the first breadth-first search.  A 64-column
 // x 64-level tile is transposed through LDS from the caller's z-fastest
 // layout to the level-major state layout.
 __global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geom g, State st,
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geo
         st.e[v] = w < 0 ? -w : 0;
         st.ts[v] = w > 0 ? w : 0;
         ts_sum += w > 0 ? w : 0;
-        st.d[v] = kInf;
+        st.d[v] = 0;   // valid lower bound until the first global relabel
         st.fd[v] = 0;
         for (int k = 0; k < 4; ++k) st.fl[(size_t)k * g.N + v] = 0;
     }
@@ -170,263 +172,393 @@ constexpr int kCh = 8;
 
 __device__ __forceinline__ int lat_head_of(int zp, int dl) { return zp == 0 ? 0 : zp - dl; }
 
-__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, Scratch *s)
+__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *chg,
+                                                  Scratch *s)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) s->lvl_changed[1] = 0;
-    if (p >= g.P) return;
-    const int P = g.P, K = g.K, N = g.N;
-    int t1 = K;
-    int lf[4] = {K, K, K, K};
-    for (int z0 = 0; z0 < K; z0 += kCh) {
-        int tsv[kCh], fv[4][kCh];
-#pragma unroll
-        for (int j = 0; j < kCh; ++j) {
-            const int z = z0 + j;
-            tsv[j] = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) fv[k][j] = 0;
-            if (z >= K) continue;
-            const int u = z * P + p;
-            tsv[j] = st.ts[u];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) fv[k][j] = st.fl[(size_t)k * N + u];
-        }
-#pragma unroll
-        for (int j = 0; j < kCh; ++j) {
-            const int z = z0 + j;
-            if (z >= K) break;
-            if (t1 == K && tsv[j] > 0) t1 = z;
-            const bool lab = t1 < K;
-            st.d[z * P + p] = lab ? 1 : kInf;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (lab && lf[k] == K && fv[k][j] > 0) lf[k] = z;
-        }
+    if (p == 0) {
+        s->lvl_changed[1] = 0;
+        s->lvl_lab[1] = 0;
     }
-    T[p] = t1;
+    int act = 0, lab_act = 0;
+    if (p < g.P) {
+        const int P = g.P, K = g.K, N = g.N;
+        int t1 = K;
+        int lf[4] = {K, K, K, K};
+        for (int z0 = 0; z0 < K; z0 += kCh) {
+            int tsv[kCh], ev[kCh], dv[kCh], fv[4][kCh];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) LF[k * P + p] = lf[k];
+            for (int j = 0; j < kCh; ++j) {
+                const int z = z0 + j;
+                tsv[j] = 0;
+                ev[j] = 0;
+                dv[j] = kInf;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fv[k][j] = 0;
+                if (z >= K) continue;
+                const int u = z * P + p;
+                tsv[j] = st.ts[u];
+                ev[j] = st.e[u];
+                dv[j] = st.d[u];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fv[k][j] = st.fl[(size_t)k * N + u];
+            }
+#pragma unroll
+            for (int j = 0; j < kCh; ++j) {
+                const int z = z0 + j;
+                if (z >= K) break;
+                if (t1 == K && tsv[j] > 0) t1 = z;
+                const bool lab = t1 < K;
+                // a node that could not reach t never can again (new residual
+                // arcs only join nodes that reach t), so kInf is kept
+                st.d[z * P + p] = lab ? 1 : (dv[j] >= kInf ? kInf : kUnl);
+                if (ev[j] > 0 && dv[j] < kInf) {
+                    ++act;
+                    if (lab) ++lab_act;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (lab && lf[k] == K && fv[k][j] > 0) lf[k] = z;
+            }
+        }
+        T[p] = t1;
+        chg[p] = 1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) LF[k * P + p] = lf[k];
+    }
+    act = wave_sum(act);
+    lab_act = wave_sum(lab_act);
+    if ((threadIdx.x & 63) == 0) {
+        if (act) atomicAdd(&s->bfs_active, act);
+        if (lab_act) atomicAdd(&s->bfs_labelled, lab_act);
+    }
 }
 
-// Level L -> L+1.  Reads the level-L records (Tin, LFin), writes level L+1.
-__global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
-                                                   const int *__restrict__ LFin, int *__restrict__ Tout,
-                                                   int *__restrict__ LFout, Scratch *s)
+// Level L -> L+1 for one column: threshold arithmetic, then the newly
+// reached heights [cand, T) are labelled L+1 and scanned (from the top, so
+// the last hit is the lowest) for flow-carrying lateral arcs.  Returns the
+// number of newly labelled nodes that hold excess.
+__device__ __forceinline__ int bfs_column_level(const Geom &g, const State &st, int L, int p,
+                                                const int *__restrict__ Tin,
+                                                const int *__restrict__ LFin,
+                                                const int *__restrict__ chg_in,
+                                                int *__restrict__ Tout, int *__restrict__ LFout,
+                                                int *__restrict__ chg_out, bool &changed)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    // the flag of the next level is cleared here; stream order puts this
-    // before every write of level L+1
-    if (p == 0) s->lvl_changed[(L + 1) & 63] = 0;
-    if (p >= g.P) return;
     const int P = g.P, K = g.K, N = g.N, dl = g.delta;
-    int x = p / g.ny, y = p - x * g.ny;
+    const int x = p / g.ny, y = p - x * g.ny;
+    int q[4];
+    const bool self = chg_in[p] != 0;
+    bool near = self;
+    for (int k = 0; k < 4; ++k) {
+        q[k] = nbr(g, x, y, p, k);
+        if (q[k] >= 0 && chg_in[q[k]]) near = true;
+    }
+    // Frontier: with no change at level L-1 around p, nothing of p's inputs
+    // moved.  Both record buffers then already hold p's current record
+    // (it did not change at L-1 either), so nothing is written.
+    if (!near) {
+        chg_out[p] = 0;
+        return 0;
+    }
     const int T = Tin[p];
     int cand = T;
     for (int k = 0; k < 4; ++k) {
-        const int q = nbr(g, x, y, p, k);
-        if (q < 0) continue;
-        const int tq = Tin[q];
+        if (q[k] < 0) continue;
+        const int tq = Tin[q[k]];
         if (tq == 0) cand = 0;
         else if (tq + dl < K) cand = min(cand, tq + dl);
-        const int lq = LFin[(k ^ 1) * P + q];
+        const int lq = LFin[(k ^ 1) * P + q[k]];
         if (lq < K) cand = min(cand, lat_head_of(lq, dl));
     }
     if (T >= 1 && T < K && st.fd[T * P + p] > 0) cand = min(cand, T - 1);
     int lf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) lf[k] = LFin[k * P + p];
+    int lab_act = 0;
     if (cand < T) {
         const int lab = L + 1;
-        // label the newly reached nodes and extend the flow scans downwards;
-        // walking from the top of the new range keeps the lowest hit
         for (int z0 = T - 1; z0 >= cand; z0 -= kCh) {
-            int fv[4][kCh];
+            int fv[4][kCh], ev[kCh];
 #pragma unroll
             for (int j = 0; j < kCh; ++j) {
                 const int z = z0 - j;
+                const bool in = z >= cand;
+                ev[j] = in ? st.e[z * P + p] : 0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    fv[k][j] = z >= cand ? st.fl[(size_t)k * N + z * P + p] : 0;
+                for (int k = 0; k < 4; ++k) fv[k][j] = in ? st.fl[(size_t)k * N + z * P + p] : 0;
             }
 #pragma unroll
             for (int j = 0; j < kCh; ++j) {
                 const int z = z0 - j;
                 if (z < cand) break;
                 st.d[z * P + p] = lab;
+                lab_act += ev[j] > 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (fv[k][j] > 0) lf[k] = z;
             }
         }
-        s->lvl_changed[L & 63] = 1;
+        changed = true;
     }
-    Tout[p] = cand;
+    // a record that changed at L-1 must also reach the other buffer
+    if (cand < T || self) {
+        Tout[p] = cand;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
+        for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
+    }
+    chg_out[p] = cand < T;
+    return lab_act;
+}
+
+// One launch per BFS level.
+__global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
+                                                   const int *__restrict__ LFin,
+                                                   const int *__restrict__ chg_in, int *__restrict__ Tout,
+                                                   int *__restrict__ LFout, int *__restrict__ chg_out,
+                                                   Scratch *s)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // the slots of the next level are cleared here; stream order puts this
+    // before every write of level L+1
+    if (p == 0) {
+        s->lvl_changed[(L + 1) & 63] = 0;
+        s->lvl_lab[(L + 1) & 63] = 0;
+    }
+    bool changed = false;
+    int lab_act = 0;
+    if (p < g.P)
+        lab_act = bfs_column_level(g, st, L, p, Tin, LFin, chg_in, Tout, LFout, chg_out, changed);
+    if (changed) s->lvl_changed[L & 63] = 1;
+    lab_act = wave_sum(lab_act);
+    if ((threadIdx.x & 63) == 0 && lab_act) atomicAdd(&s->bfs_labelled, lab_act);
+}
+
+// End of a global relabel: nodes the search did not reach get `v` (kInf
+// when it ran to completion, else the first level it did not finish, which
+// is a valid lower bound of their distance).
+__global__ void k_bfs_fixup(int *d, int n, int v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && d[i] == kUnl) d[i] = v;
+}
+
+// Per-column work ranges.  rlo/rhi bound the heights of the column's nodes
+// that may hold excess with a finite label (lo > hi: none).  Every step that
+// puts excess on a node records its height in the range of the next phase,
+// so a sweep only walks the parts of columns where there is work.
+
+__device__ __forceinline__ void note_range(int *rlo, int *rhi, int p, int z)
+{
+    atomicMin(rlo + p, z);
+    atomicMax(rhi + p, z);
 }
 
 // Push phase of one sweep (labels fixed).  The thread owning column p walks
-// it top-down (kDown) or bottom-up; each node with excess pushes along
-// admissible arcs d(u) = d(w) + len(u, w): to t, down the column, along
-// reverse lateral arcs (cancelling flow first), along forward lateral arcs,
-// and up along reverse down arcs.  Excess moving in the walking direction
-// is carried in a register and handled at the next node of the same walk.
+// its work range top-down (kDown) or bottom-up; each node with excess pushes
+// along admissible arcs d(u) = d(w) + len(u, w): to t, down the column,
+// along reverse lateral arcs (cancelling flow first), along forward lateral
+// arcs, and up along reverse down arcs.  Excess moving in the walking
+// direction is carried in a register to the next node of the same walk, so
+// the walk continues past the range while a carry is alive.
 template <bool kDown>
-__global__ __launch_bounds__(256) void k_push(Geom g, State st, Scratch *s)
+__global__ __launch_bounds__(256) void k_push(Geom g, State st, const int *__restrict__ rlo_in,
+                                              const int *__restrict__ rhi_in, int *rlo_out,
+                                              int *rhi_out, Scratch *s)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= g.P) return;
+    const int lo = rlo_in[p], hi = rhi_in[p];
+    if (lo > hi) return;
     const int P = g.P, K = g.K, N = g.N, dl = g.delta;
     int x = p / g.ny, y = p - x * g.ny;
     int q[4];
     for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
     int err = 0;
+    int mylo = K, myhi = -1;   // own nodes left holding excess
     long long carry = 0;
-    for (int i0 = 0; i0 < K; i0 += kCh) {
-      int ev[kCh], dv[kCh];
+    // walk index i: z = hi - i (down) or lo + i (up)
+    const int span = kDown ? hi + 1 : K - lo;
+    const int first = kDown ? hi : lo;
+    for (int i0 = 0; i0 < span; i0 += kCh) {
+        if (i0 > (hi - lo) && carry == 0) break;
+        int ev[kCh], dv[kCh];
 #pragma unroll
-      for (int j = 0; j < kCh; ++j) {
-          const int i = i0 + j;
-          ev[j] = 0;
-          dv[j] = kInf;
-          if (i >= K) continue;
-          const int u = (kDown ? K - 1 - i : i) * P + p;
-          ev[j] = st.e[u];
-          dv[j] = st.d[u];
-      }
-      for (int j = 0; j < kCh; ++j) {
-        const int i = i0 + j;
-        if (i >= K) break;
-        const int z = kDown ? K - 1 - i : i;
-        const int u = z * P + p;
-        long long ex = carry;
-        carry = 0;
-        const int eu = ev[j];
-        if (eu <= 0 && ex == 0) continue;
-        const int du = dv[j];
-        if (du >= kInf) {
-            if (ex) add_excess(st.e, u, ex, err);   // not reached: carries follow admissible arcs
-            continue;
+        for (int j = 0; j < kCh; ++j) {
+            const int i = i0 + j;
+            ev[j] = 0;
+            dv[j] = kInf;
+            if (i >= span) continue;
+            const int u = (kDown ? first - i : first + i) * P + p;
+            ev[j] = st.e[u];
+            dv[j] = st.d[u];
         }
-        if (eu > 0) ex += atomicExch(st.e + u, 0);
-        if (du == 1) {
-            int r = st.ts[u];
-            if (r > 0) {
-                int a = (int)min<long long>(ex, r);
-                st.ts[u] = r - a;
-                ex -= a;
+        for (int j = 0; j < kCh; ++j) {
+            const int i = i0 + j;
+            if (i >= span || (i > hi - lo && carry == 0)) break;
+            const int z = kDown ? first - i : first + i;
+            const int u = z * P + p;
+            long long ex = carry;
+            carry = 0;
+            const int eu = ev[j];
+            if (eu <= 0 && ex == 0) continue;
+            const int du = dv[j];
+            if (du >= kInf) {
+                if (ex) add_excess(st.e, u, ex, err);   // not reached: carries follow admissible arcs
+                continue;
             }
-        }
-        if (ex > 0 && z > 0 && st.d[u - P] == du) {
-            st.fd[u] = add_flow(st.fd[u], ex, err);
-            if (kDown) carry = ex;
-            else add_excess(st.e, u - P, ex, err);
-            ex = 0;
-        }
-        if (ex > 0) {
-            int zt = lat_tail(z, dl, K);
-            if (zt >= 0) {
-                for (int k = 0; k < 4 && ex > 0; ++k) {
-                    if (q[k] < 0) continue;
-                    int w = zt * P + q[k];
-                    int *fp = st.fl + (size_t)(k ^ 1) * N + w;
-                    int f = *fp;
-                    if (f > 0 && st.d[w] + 1 == du) {
-                        int a = (int)min<long long>(ex, f);
-                        *fp = f - a;
-                        add_excess(st.e, w, a, err);
-                        ex -= a;
+            if (eu > 0) ex += atomicExch(st.e + u, 0);
+            if (du == 1) {
+                int r = st.ts[u];
+                if (r > 0) {
+                    int a = (int)min<long long>(ex, r);
+                    st.ts[u] = r - a;
+                    ex -= a;
+                }
+            }
+            if (ex > 0 && z > 0 && st.d[u - P] == du) {
+                st.fd[u] = add_flow(st.fd[u], ex, err);
+                if (kDown) {
+                    carry = ex;
+                } else {
+                    add_excess(st.e, u - P, ex, err);
+                    mylo = min(mylo, z - 1);
+                    myhi = max(myhi, z - 1);
+                }
+                ex = 0;
+            }
+            if (ex > 0) {
+                int zt = lat_tail(z, dl, K);
+                if (zt >= 0) {
+                    for (int k = 0; k < 4 && ex > 0; ++k) {
+                        if (q[k] < 0) continue;
+                        int w = zt * P + q[k];
+                        int *fp = st.fl + (size_t)(k ^ 1) * N + w;
+                        int f = *fp;
+                        if (f > 0 && st.d[w] + 1 == du) {
+                            int a = (int)min<long long>(ex, f);
+                            *fp = f - a;
+                            add_excess(st.e, w, a, err);
+                            note_range(rlo_out, rhi_out, q[k], zt);
+                            ex -= a;
+                        }
                     }
                 }
             }
-        }
-        if (ex > 0 && lat_arc(z, dl)) {
-            int zh = lat_head(z, dl) * P;
-            for (int k = 0; k < 4; ++k) {
-                if (q[k] < 0) continue;
-                int w = zh + q[k];
-                if (st.d[w] + 1 == du) {
-                    st.fl[(size_t)k * N + u] = add_flow(st.fl[(size_t)k * N + u], ex, err);
-                    add_excess(st.e, w, ex, err);
-                    ex = 0;
-                    break;
+            if (ex > 0 && lat_arc(z, dl)) {
+                const int zh = lat_head(z, dl);
+                for (int k = 0; k < 4; ++k) {
+                    if (q[k] < 0) continue;
+                    int w = zh * P + q[k];
+                    if (st.d[w] + 1 == du) {
+                        st.fl[(size_t)k * N + u] = add_flow(st.fl[(size_t)k * N + u], ex, err);
+                        add_excess(st.e, w, ex, err);
+                        note_range(rlo_out, rhi_out, q[k], zh);
+                        ex = 0;
+                        break;
+                    }
                 }
             }
-        }
-        if (ex > 0 && z + 1 < K) {
-            int w = u + P;
-            int f = st.fd[w];
-            if (f > 0 && st.d[w] + 1 == du) {
-                int a = (int)min<long long>(ex, f);
-                st.fd[w] = f - a;
-                if (kDown) add_excess(st.e, w, a, err);
-                else carry = a;
-                ex -= a;
+            if (ex > 0 && z + 1 < K) {
+                int w = u + P;
+                int f = st.fd[w];
+                if (f > 0 && st.d[w] + 1 == du) {
+                    int a = (int)min<long long>(ex, f);
+                    st.fd[w] = f - a;
+                    if (kDown) {
+                        add_excess(st.e, w, a, err);
+                        mylo = min(mylo, z + 1);
+                        myhi = max(myhi, z + 1);
+                    } else {
+                        carry = a;
+                    }
+                    ex -= a;
+                }
+            }
+            if (ex > 0) {
+                add_excess(st.e, u, ex, err);
+                mylo = min(mylo, z);
+                myhi = max(myhi, z);
             }
         }
-        if (ex > 0) add_excess(st.e, u, ex, err);
-      }
+    }
+    if (mylo <= myhi) {
+        atomicMin(rlo_out + p, mylo);
+        atomicMax(rhi_out + p, myhi);
     }
     if (err) atomicOr(&s->err, kErrOverflow);
 }
 
-// Relabel phase of one sweep (flows fixed): every node with excess, a finite
-// label and no admissible arc takes d(u) = min over residual arcs of
-// d(w) + len(u, w) (kInf when that exceeds every possible distance).  Also
-// counts the nodes that stay active.
-__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Scratch *s)
+// Relabel phase of one sweep (flows fixed): every node of the work range
+// with excess, a finite label and no admissible arc takes d(u) = min over
+// residual arcs of d(w) + len(u, w) (kInf when that exceeds every possible
+// distance).  The range is then tightened to the nodes that stay active,
+// which are counted; the push phase's input range is reset for reuse.
+__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, int *rlo, int *rhi,
+                                                 int *rlo_reset, int *rhi_reset, Scratch *s)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     int cnt = 0;
     if (p < g.P) {
         const int P = g.P, K = g.K, N = g.N, dl = g.delta;
-        int x = p / g.ny, y = p - x * g.ny;
-        int q[4];
-        for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
-        int prev = kInf;
-        for (int z0 = 0; z0 < K; z0 += kCh) {
-          int ev[kCh], dv[kCh];
+        rlo_reset[p] = K;
+        rhi_reset[p] = -1;
+        const int lo = rlo[p], hi = rhi[p];
+        int alo = K, ahi = -1;
+        if (lo <= hi) {
+            int x = p / g.ny, y = p - x * g.ny;
+            int q[4];
+            for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
+            int prev = lo > 0 ? st.d[(lo - 1) * P + p] : kInf;
+            for (int z0 = lo; z0 <= hi; z0 += kCh) {
+                int ev[kCh], dv[kCh];
 #pragma unroll
-          for (int j = 0; j < kCh; ++j) {
-              const int z = z0 + j;
-              ev[j] = 0;
-              dv[j] = kInf;
-              if (z >= K) continue;
-              ev[j] = st.e[z * P + p];
-              dv[j] = st.d[z * P + p];
-          }
-          for (int j = 0; j < kCh; ++j) {
-            const int z = z0 + j;
-            if (z >= K) break;
-            const int u = z * P + p;
-            int du = dv[j];
-            if (du < kInf && ev[j] > 0) {
-                int b = prev;
-                if (st.ts[u] > 0) b = min(b, 1);
-                if (z + 1 < K && st.fd[u + P] > 0) b = min(b, st.d[u + P] + 1);
-                if (lat_arc(z, dl)) {
-                    int zh = lat_head(z, dl) * P;
-                    for (int k = 0; k < 4; ++k)
-                        if (q[k] >= 0) b = min(b, st.d[zh + q[k]] + 1);
+                for (int j = 0; j < kCh; ++j) {
+                    const int z = z0 + j;
+                    ev[j] = 0;
+                    dv[j] = kInf;
+                    if (z > hi) continue;
+                    ev[j] = st.e[z * P + p];
+                    dv[j] = st.d[z * P + p];
                 }
-                int zt = lat_tail(z, dl, K);
-                if (zt >= 0) {
-                    for (int k = 0; k < 4; ++k) {
-                        if (q[k] < 0) continue;
-                        int w = zt * P + q[k];
-                        if (st.fl[(size_t)(k ^ 1) * N + w] > 0) b = min(b, st.d[w] + 1);
+                for (int j = 0; j < kCh; ++j) {
+                    const int z = z0 + j;
+                    if (z > hi) break;
+                    const int u = z * P + p;
+                    int du = dv[j];
+                    if (du < kInf && ev[j] > 0) {
+                        int b = prev;
+                        if (st.ts[u] > 0) b = min(b, 1);
+                        if (z + 1 < K && st.fd[u + P] > 0) b = min(b, st.d[u + P] + 1);
+                        if (lat_arc(z, dl)) {
+                            int zh = lat_head(z, dl) * P;
+                            for (int k = 0; k < 4; ++k)
+                                if (q[k] >= 0) b = min(b, st.d[zh + q[k]] + 1);
+                        }
+                        int zt = lat_tail(z, dl, K);
+                        if (zt >= 0) {
+                            for (int k = 0; k < 4; ++k) {
+                                if (q[k] < 0) continue;
+                                int w = zt * P + q[k];
+                                if (st.fl[(size_t)(k ^ 1) * N + w] > 0) b = min(b, st.d[w] + 1);
+                            }
+                        }
+                        if (b > du) {
+                            du = b >= g.lab_cap ? kInf : b;
+                            st.d[u] = du;
+                        }
+                        if (du < kInf) {
+                            ++cnt;
+                            alo = min(alo, z);
+                            ahi = z;
+                        }
                     }
+                    prev = du;
                 }
-                if (b > du) {
-                    du = b >= g.lab_cap ? kInf : b;
-                    st.d[u] = du;
-                }
-                if (du < kInf) ++cnt;
             }
-            prev = du;
-          }
         }
+        rlo[p] = alo;
+        rhi[p] = ahi;
     }
     cnt = wave_sum(cnt);
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&s->active, cnt);
@@ -521,16 +653,24 @@ void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, h
     hipLaunchKernelGGL(k_build, grid, dim3(256), 0, st, cost, g, sv, s);
 }
 
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, Scratch *s, hipStream_t st)
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *chg, Scratch *s,
+                     hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_init, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, T, LF, s);
+    hipLaunchKernelGGL(k_bfs_init, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, T, LF, chg, s);
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      int *Tout, int *LFout, Scratch *s, hipStream_t st)
+                      const int *chg_in, int *Tout, int *LFout, int *chg_out, Scratch *s,
+                      hipStream_t st)
 {
     hipLaunchKernelGGL(k_bfs_level, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, L, Tin, LFin,
-                       Tout, LFout, s);
+                       chg_in, Tout, LFout, chg_out, s);
+}
+
+void launch_bfs_fixup(const Geom &g, const State &sv, int v, hipStream_t st)
+{
+    unsigned blocks = (unsigned)(((long long)g.N + 255) / 256);
+    hipLaunchKernelGGL(k_bfs_fixup, dim3(blocks), dim3(256), 0, st, sv.d, g.N, v);
 }
 
 void launch_fill(int *a, int n, int v, hipStream_t st)
@@ -538,17 +678,22 @@ void launch_fill(int *a, int n, int v, hipStream_t st)
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n, v);
 }
 
-void launch_push(const Geom &g, const State &sv, Scratch *s, bool down, hipStream_t st)
+void launch_push(const Geom &g, const State &sv, const int *rlo_in, const int *rhi_in,
+                 int *rlo_out, int *rhi_out, Scratch *s, bool down, hipStream_t st)
 {
     if (down)
-        hipLaunchKernelGGL(k_push<true>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+        hipLaunchKernelGGL(k_push<true>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, rlo_in,
+                           rhi_in, rlo_out, rhi_out, s);
     else
-        hipLaunchKernelGGL(k_push<false>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+        hipLaunchKernelGGL(k_push<false>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, rlo_in,
+                           rhi_in, rlo_out, rhi_out, s);
 }
 
-void launch_relabel(const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+void launch_relabel(const Geom &g, const State &sv, int *rlo, int *rhi, int *rlo_reset,
+                    int *rhi_reset, Scratch *s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_relabel, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, s);
+    hipLaunchKernelGGL(k_relabel, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, rlo, rhi,
+                       rlo_reset, rhi_reset, s);
 }
 
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
