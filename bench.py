@@ -51,7 +51,21 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-crop", type=int, default=48,
                     help="columns per side of the oracle's CPU sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 5}), flush=True)
 
 
 def kernel_source_sha() -> str:
@@ -95,6 +109,9 @@ def cpu_baseline(cost, delta, crop):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the volume is solved whole on a single MI355X)", file=sys.stderr)
