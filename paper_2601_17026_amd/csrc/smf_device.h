@@ -1,11 +1,12 @@
 // Device-side layout and helpers shared by the solver kernels.
 //
-// Node state is stored level-major ("z slowest"): node (p, z) with column
-// p = x*ny + y lives at index z*P + p, P = nx*ny.  A thread that owns column
-// p walks z and every step of a wave touches 64 consecutive columns, so all
-// per-node loads and stores are coalesced, the column-direction carries stay
-// in registers, and the lateral neighbours (p +- 1, p +- ny) of a wave are
-// again contiguous runs.
+// Node state is stored column-major exactly like the caller's cost volume:
+// node (p, z) of column p = x*ny + y lives at index p*K + z (z fastest).  A
+// wave owns one column at a time and processes it in chunks of 64
+// consecutive heights, one lane per height, so every load and store of the
+// column is a coalesced 256-byte access; the lateral neighbours (q, z -+
+// delta) of a chunk are again 64 consecutive words of column q, and the
+// neighbours up and down the column are one lane away.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -16,15 +17,18 @@ constexpr int kInf = 0x40000000;       // label of a node that cannot reach t
 constexpr int kUnl = kInf - 1;         // not (yet) reached by the running BFS
 constexpr int kErrCostRange = 1;       // a cost outside (-2^30, 2^30)
 constexpr int kErrOverflow = 2;        // an int32 excess or flow would overflow
+constexpr int kWave = 64;              // CDNA wavefront width = heights per chunk
 
 struct Geom {
     int nx, ny, K, delta;
-    int P;      // columns
-    int N;      // nodes (< 2^31)
-    int lab_cap; // labels >= lab_cap are unreachable (N + 1, at most kInf)
+    int P;        // columns
+    int N;        // nodes (< 2^31)
+    int lab_cap;  // labels >= lab_cap are unreachable (N + 1, at most kInf)
+    int nch;      // 64-height chunks per column
+    int cpb;      // chunks per work-mask bit (nch <= 64 * cpb)
 };
 
-// Per-node solver state; each array holds N int32 in level-major order.
+// Per-node solver state; each array holds N int32, column-major.
 struct State {
     int *e;    // excess
     int *d;    // distance label (lower bound of the residual distance to t)
@@ -33,19 +37,27 @@ struct State {
     int *fl;   // 4 x N: flow on (p,z) -> (q, zt(z)), q = p + (+x, -x, +y, -y)
 };
 
+// Work tracking of the push/relabel sweeps: per column a 64-bit mask of the
+// chunk groups that may hold a node with excess and a finite label, and a
+// list of the columns whose mask is not empty.
+struct Work {
+    unsigned long long *mask;   // P masks
+    int *list;                  // up to P column ids
+    int *count;                 // device counter of `list`
+};
+
 // Device-resident counters and flags of one solve.
 struct Scratch {
     int bmax;            // max_p c(p, 0)
     int err;             // kErr* bits
-    int changed;         // a BFS / min-cut pass changed something
+    int changed;         // a min-cut pass changed something
     int active;          // active nodes after the last relabel phase
     long long flow;      // sum of flow into t
     long long energy;    // sum_p c(p, h(p))
     int bfs_active;      // nodes with excess and a finite label when the BFS starts
     int bfs_labelled;    // ... of which the running BFS has labelled so far
-    int pad_i[2];
+    int count[2];        // sizes of the two column work lists
     int lvl_changed[64]; // BFS level L labelled something: slot L % 64
-    int lvl_lab[64];     // nodes with excess labelled by level L: slot L % 64
 };
 
 // Lateral arcs kept by the solver: (p,z) -> (q, z - delta) for z > delta,

@@ -1,7 +1,8 @@
 // Host driver and C-ABI of the exact surface max-flow (include/smf.h).
 //
-// One handle owns the level-major node state of one volume (32 bytes per
-// node) plus a small device scratch block and a pinned host mirror of it.
+// One handle owns the node state of one volume (32 bytes per node, in the
+// caller's [nx][ny][K] layout) plus per-column work lists and BFS records,
+// a small device scratch block and a pinned host mirror of it.
 // smf_solve enqueues the build, the initial global relabel and then sweeps
 // of push and relabel phases on the caller's stream; the host polls the
 // device's active-node counter every `poll_every` sweeps (the only
@@ -23,24 +24,23 @@
 namespace smf {
 void launch_init_scratch(Scratch *s, hipStream_t st);
 void launch_set_int(int *p, int v, hipStream_t st);
+void launch_fill(int *a, int n, int v, hipStream_t st);
+void launch_work_init(const Geom &g, const Work &a, const Work &b, hipStream_t st);
 void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st);
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *chg, Scratch *s,
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, Scratch *s,
                      hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *chg_in, int *Tout, int *LFout, int *chg_out, Scratch *s,
+                      const int *CHin, int *Tout, int *LFout, int *CHout, Scratch *s,
                       hipStream_t st);
-void launch_fill(int *a, int n, int v, hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, int v, hipStream_t st);
-
-void launch_push(const Geom &g, const State &sv, const int *rlo_in, const int *rhi_in,
-                 int *rlo_out, int *rhi_out, Scratch *s, bool down, hipStream_t st);
-void launch_relabel(const Geom &g, const State &sv, int *rlo, int *rhi, int *rlo_reset,
-                    int *rhi_reset, Scratch *s, hipStream_t st);
+void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
+                 bool down, hipStream_t st);
+void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
+                    hipStream_t st);
+void launch_compact(const Geom &g, const Work &w, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
 void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
-                   hipStream_t st);
-void launch_export(const Geom &g, const State &sv, int *e, int *ts, int *fd, int *fl,
                    hipStream_t st);
 }  // namespace smf
 
@@ -138,7 +138,9 @@ struct smf_handle {
     int *state = nullptr;      // 8 * N int32
     int *H = nullptr;          // P int32 surface
     int *bfs = nullptr;        // 12 * P int32: two per-column BFS records (T, LF[4], changed)
-    int *rng = nullptr;        // 4 * P int32: two per-column work ranges (lo, hi)
+    unsigned long long *wmask = nullptr;  // 2 * P work masks
+    int *wlist = nullptr;                 // 2 * P work-list entries
+    Work work[2]{};            // push reads work[0] and writes work[1]; relabel the reverse
     Scratch *scr = nullptr;    // device scratch
     Scratch *host = nullptr;   // pinned mirror
     State st{};
@@ -163,7 +165,8 @@ static void release(smf_handle *h)
     if (h->state) (void)hipFree(h->state);
     if (h->H) (void)hipFree(h->H);
     if (h->bfs) (void)hipFree(h->bfs);
-    if (h->rng) (void)hipFree(h->rng);
+    if (h->wmask) (void)hipFree(h->wmask);
+    if (h->wlist) (void)hipFree(h->wlist);
     if (h->scr) (void)hipFree(h->scr);
     if (h->host) (void)hipHostFree(h->host);
     delete h;
@@ -190,11 +193,14 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
     h->g.P = nx * ny;
     h->g.N = (int)N;
     h->g.lab_cap = N + 1 < kInf ? (int)(N + 1) : kInf;
+    h->g.nch = (K + kWave - 1) / kWave;
+    h->g.cpb = (h->g.nch + 63) / 64;
     if (hipGetDevice(&h->device) != hipSuccess ||
         hipMalloc((void **)&h->state, sizeof(int) * 8 * (size_t)N) != hipSuccess ||
         hipMalloc((void **)&h->H, sizeof(int) * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->bfs, sizeof(int) * 12 * (size_t)h->g.P) != hipSuccess ||
-        hipMalloc((void **)&h->rng, sizeof(int) * 4 * (size_t)h->g.P) != hipSuccess ||
+        hipMalloc((void **)&h->wmask, sizeof(unsigned long long) * 2 * (size_t)h->g.P) != hipSuccess ||
+        hipMalloc((void **)&h->wlist, sizeof(int) * 2 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->scr, sizeof(Scratch)) != hipSuccess ||
         hipHostMalloc((void **)&h->host, sizeof(Scratch), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -210,6 +216,11 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
     h->st.ts = b + 2 * n;
     h->st.fd = b + 3 * n;
     h->st.fl = b + 4 * n;
+    for (int i = 0; i < 2; ++i) {
+        h->work[i].mask = h->wmask + (size_t)i * h->g.P;
+        h->work[i].list = h->wlist + (size_t)i * h->g.P;
+        h->work[i].count = &h->scr->count[i];
+    }
     return h;
 }
 
@@ -302,14 +313,8 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     rc = global_relabel(h, s);
     if (rc) return rc;
 
-    // work ranges: every column may hold excess anywhere before the first sweep
-    const int P = h->g.P;
-    int *rlo[2] = {h->rng, h->rng + 2 * (size_t)P};
-    int *rhi[2] = {h->rng + P, h->rng + 3 * (size_t)P};
-    launch_fill(rlo[0], P, 0, s);
-    launch_fill(rhi[0], P, h->g.K - 1, s);
-    launch_fill(rlo[1], P, h->g.K, s);
-    launch_fill(rhi[1], P, -1, s);
+    // work lists: every column may hold excess anywhere before the first sweep
+    launch_work_init(h->g, h->work[0], h->work[1], s);
     bool done = false;
     while (!done) {
         if (h->sweeps >= h->max_sweeps)
@@ -319,15 +324,17 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
                 rc = global_relabel(h, s);
                 if (rc) return rc;
             }
-            const int a = (int)(h->sweeps & 1), b = a ^ 1;
+            launch_set_int(h->work[1].count, 0, s);
             {
                 TimedScope ts(h->timer, KC_PUSH, s);
-                launch_push(h->g, h->st, rlo[a], rhi[a], rlo[b], rhi[b], h->scr, a == 0, s);
+                launch_push(h->g, h->st, h->work[0], h->work[1], h->scr, (h->sweeps & 1) == 0, s);
+                launch_compact(h->g, h->work[1], s);
             }
+            launch_set_int(h->work[0].count, 0, s);
             launch_set_int(&h->scr->active, 0, s);
             {
                 TimedScope ts(h->timer, KC_RELABEL, s);
-                launch_relabel(h->g, h->st, rlo[b], rhi[b], rlo[a], rhi[a], h->scr, s);
+                launch_relabel(h->g, h->st, h->work[1], h->work[0], h->scr, s);
             }
             h->sweeps++;
         }
@@ -335,7 +342,8 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
         rc = sync_scratch(h, s);
         if (rc) return rc;
         done = h->host->active == 0;
-        if (h->verbose) fprintf(stderr, "smf: sweep %lld active %d\n", (long long)h->sweeps, h->host->active);
+        if (h->verbose) fprintf(stderr, "smf: sweep %lld active %d columns %d\n", (long long)h->sweeps,
+                                h->host->active, h->host->count[0]);
     }
 
     {
@@ -399,9 +407,13 @@ extern "C" int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_
     if (!h || !excess_dev || !sink_res_dev || !flow_down_dev || !flow_lat_dev)
         return fail(SMF_ERR_ARG, "smf_export_state: NULL argument");
     if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_export_state: no successful solve");
-    launch_export(h->g, h->st, excess_dev, sink_res_dev, flow_down_dev, flow_lat_dev,
-                  (hipStream_t)stream);
-    HIP_TRY(hipGetLastError());
+    // the state already has the caller's [nx][ny][K] layout
+    const size_t n = sizeof(int) * (size_t)h->g.N;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(excess_dev, h->st.e, n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(sink_res_dev, h->st.ts, n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(flow_down_dev, h->st.fd, n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(flow_lat_dev, h->st.fl, 4 * n, hipMemcpyDeviceToDevice, s));
     return SMF_OK;
 }
 

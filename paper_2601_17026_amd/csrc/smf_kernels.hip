@@ -2,53 +2,76 @@
 //
 // Method: push-relabel (Section 2.1) on the implicit column graph of
 // Section 1.2, with global relabelling by a reverse breadth-first search
-// from the sink (Section 2.1, "global relabeling"; Section 3.2.2) and the
-// minimum cut read out as the residual reach set (Section 1.3, Eq. 6,
-// Theorem 1.1).  Storage is implicit (Section 3.2.3): no edge lists, only
-// per-node excess, label, sink residual and the flows of the five outgoing
-// infinite arcs.
+// from the sink (Section 2.1, "global relabeling"; Section 3.2.2 and
+// Algorithm 3) and the minimum cut read out as the residual reach set
+// (Section 1.3, Eq. 6, Theorem 1.1).  Storage is implicit (Section 3.2.3):
+// no edge lists, only per-node excess, label, sink residual and the flows of
+// the five outgoing infinite arcs.
 //
-// Labels.  A valid labelling here satisfies d(u) <= d(w) + len(u, w) for
-// every residual arc, with len = 0 for the always-residual down arcs
+// Labels.  A valid labelling satisfies d(u) <= d(w) + len(u, w) for every
+// residual arc, with len = 0 for the always-residual down arcs
 // (p,z) -> (p,z-1) and len = 1 for every other arc (sink arcs included,
-// d(t) = 0).  Down arcs never lie on a cycle of length-0 arcs, so pushes
-// along them cannot circulate, and d(v) remains a lower bound of the
-// weighted residual distance to t: a node whose label exceeds N cannot reach
-// t.  Zero-length down arcs let excess fall down a whole column in one
-// sweep and make the breadth-first search count only column changes and
-// upward moves.
+// d(t) = 0).  Down arcs form no cycle, so pushes along them cannot
+// circulate, and d(v) stays a lower bound of the weighted residual distance
+// to t: a node whose label exceeds N cannot reach t.  Zero-length down arcs
+// let excess fall a whole column per sweep and make exact labels
+// non-increasing up every column, which the breadth-first search exploits.
 //
 // Concurrency.  A sweep is two launches: a push phase with all labels fixed,
-// then a relabel phase with all flows fixed.  In the push phase a thread owns
-// one column; an arc and its reverse can never both be admissible under
-// fixed labels, so every flow counter has a single writer per phase, and
-// only excess counters of other columns are updated with atomics.  In the
-// relabel phase labels only grow, so reading a neighbour's old or new label
-// both keep the labelling valid.
+// then a relabel phase with all flows fixed.  In the push phase a wave owns a
+// column; an arc and its reverse are never both admissible under fixed
+// labels, so every flow counter has a single writer per phase, and only the
+// excess counters of other columns take atomics.  In the relabel phase labels
+// only grow, so a neighbour's old or new label both keep the labelling valid.
 #include "smf_device.h"
 #include <limits.h>
 
 namespace smf {
 
+// ---- wave utilities ---------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
 __device__ __forceinline__ int wave_sum(int v)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
 
 __device__ __forceinline__ long long wave_sum64(long long v)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
 
 __device__ __forceinline__ int wave_max(int v)
 {
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
     return v;
 }
 
-__device__ __forceinline__ void add_excess(int *e, int w, long long a, int &err)
+__device__ __forceinline__ long long shfl64(long long v, int src)
+{
+    int lo = __shfl((int)(v & 0xffffffffLL), src, kWave);
+    int hi = __shfl((int)(v >> 32), src, kWave);
+    return ((long long)hi << 32) | (unsigned int)lo;
+}
+
+__device__ __forceinline__ long long shfl64_down(long long v, int off)
+{
+    int lo = __shfl_down((int)(v & 0xffffffffLL), off, kWave);
+    int hi = __shfl_down((int)(v >> 32), off, kWave);
+    return ((long long)hi << 32) | (unsigned int)lo;
+}
+
+__device__ __forceinline__ long long shfl64_up(long long v, int off)
+{
+    int lo = __shfl_up((int)(v & 0xffffffffLL), off, kWave);
+    int hi = __shfl_up((int)(v >> 32), off, kWave);
+    return ((long long)hi << 32) | (unsigned int)lo;
+}
+
+__device__ __forceinline__ void add_excess(int *e, size_t w, long long a, int &err)
 {
     if (a > INT_MAX) { err = 1; a = INT_MAX; }
     int old = atomicAdd(e + w, (int)a);
@@ -62,6 +85,56 @@ __device__ __forceinline__ int add_flow(int f, long long a, int &err)
     return (int)r;
 }
 
+// ---- carries along a column as a scan of clamp functions --------------------
+//
+// Within one push phase the excess that leaves a node along its column arc
+// is a function of the excess that arrives from the previous node of the
+// walk: c -> min(U, max(L, c + A)).  Such clamp functions are closed under
+// composition, so the carries of 64 consecutive heights follow from one
+// wave-wide scan instead of a 64-step dependency chain.
+constexpr long long kBig = 1LL << 60;
+
+struct Clamp {
+    long long A, L, U;
+};
+
+__device__ __forceinline__ long long clampv(long long x, long long l, long long u)
+{
+    return x < l ? l : (x > u ? u : x);
+}
+
+__device__ __forceinline__ long long apply(const Clamp &f, long long c)
+{
+    return clampv(c + f.A, f.L, f.U);
+}
+
+// s o t: apply t first, then s.
+__device__ __forceinline__ Clamp compose(const Clamp &s, const Clamp &t)
+{
+    Clamp r;
+    r.A = t.A + s.A;
+    r.L = clampv(t.L + s.A, s.L, s.U);
+    r.U = clampv(t.U + s.A, s.L, s.U);
+    return r;
+}
+
+__device__ __forceinline__ Clamp shfl_clamp_down(const Clamp &f, int off)
+{
+    return {shfl64_down(f.A, off), shfl64_down(f.L, off), shfl64_down(f.U, off)};
+}
+
+__device__ __forceinline__ Clamp shfl_clamp_up(const Clamp &f, int off)
+{
+    return {shfl64_up(f.A, off), shfl64_up(f.L, off), shfl64_up(f.U, off)};
+}
+
+__device__ __forceinline__ Clamp shfl_clamp(const Clamp &f, int src)
+{
+    return {shfl64(f.A, src), shfl64(f.L, src), shfl64(f.U, src)};
+}
+
+// ---- small kernels ------------------------------------------------------------
+
 __global__ void k_init_scratch(Scratch *s)
 {
     s->bmax = INT_MIN;
@@ -72,6 +145,8 @@ __global__ void k_init_scratch(Scratch *s)
     s->energy = 0;
     s->bfs_active = 0;
     s->bfs_labelled = 0;
+    s->count[0] = 0;
+    s->count[1] = 0;
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
@@ -82,69 +157,402 @@ __global__ void k_fill(int *a, int n, int v)
     if (i < n) a[i] = v;
 }
 
+// Work lists before the first sweep: every column, every chunk group.
+__global__ void k_work_init(unsigned long long *mask_a, int *list_a, int *count_a,
+                            unsigned long long *mask_b, unsigned long long full, int P)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) {
+        mask_a[i] = full;
+        list_a[i] = i;
+        mask_b[i] = 0;
+    }
+    if (i == 0) *count_a = P;
+}
+
 // B - 1 = max_p c(p, 0): the bottom shift that makes every bottom node a
 // source node (w(p,0) < 0), so that the empty cut never wins.
 __global__ void k_bottom_max(const int *__restrict__ cost, int P, int K, Scratch *s)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    int v = p < P ? cost[(long long)p * K] : INT_MIN;
+    int v = p < P ? cost[(size_t)p * K] : INT_MIN;
     v = wave_max(v);
-    if ((threadIdx.x & 63) == 0) atomicMax(&s->bmax, v);
+    if (lane_id() == 0) atomicMax(&s->bmax, v);
 }
 
-// Graph build: node weights w (Section 1.2), source arcs pre-saturated into
-// the excess (Section 2.1 initialisation), sink residuals, zero flows and
-// labels 0 (valid lower bounds) until the first breadth-first search.  A 64-column
-// x 64-level tile is transposed through LDS from the caller's z-fastest
-// layout to the level-major state layout.
+// Graph build, one thread per node: node weights w (Section 1.2), source
+// arcs pre-saturated into the excess (Section 2.1 initialisation), sink
+// residuals, zero flows and labels 0 (valid lower bounds) until the first
+// breadth-first search.  The state has the cost volume's own layout.
 __global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geom g, State st,
                                                Scratch *s)
 {
-    __shared__ int tile[64][65];
-    __shared__ int below[64];
-    const int p0 = blockIdx.x * 64, z0 = blockIdx.y * 64;
-    const int tid = threadIdx.x;
     int bad = 0;
-    for (int i = 0; i < 16; ++i) {
-        int l = tid + 256 * i, pc = l >> 6, zc = l & 63;
-        int p = p0 + pc, z = z0 + zc;
-        int c = 0;
-        if (p < g.P && z < g.K) {
-            c = cost[(long long)p * g.K + z];
-            if (c <= -(1 << 30) || c >= (1 << 30)) bad = 1;
-        }
-        tile[pc][zc] = c;
-    }
-    if (tid < 64) {
-        int p = p0 + tid;
-        below[tid] = (z0 > 0 && p < g.P) ? cost[(long long)p * g.K + z0 - 1] : 0;
-    }
-    __syncthreads();
-    const int B = s->bmax + 1;
     long long ts_sum = 0;
-    for (int i = 0; i < 16; ++i) {
-        int l = tid + 256 * i, zc = l >> 6, pc = l & 63;
-        int p = p0 + pc, z = z0 + zc;
-        if (p >= g.P || z >= g.K) continue;
-        int c = tile[pc][zc];
-        int cb = zc > 0 ? tile[pc][zc - 1] : below[pc];
-        int w = z == 0 ? c - B : c - cb;
-        int v = z * g.P + p;
+    const int B = s->bmax + 1;
+    const int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.N; v += stride) {
+        const int z = v % g.K;
+        const int c = cost[v];
+        const int cb = z > 0 ? cost[v - 1] : B;
+        if (c <= -(1 << 30) || c >= (1 << 30)) bad = 1;
+        const int w = c - cb;
         st.e[v] = w < 0 ? -w : 0;
         st.ts[v] = w > 0 ? w : 0;
         ts_sum += w > 0 ? w : 0;
-        st.d[v] = 0;   // valid lower bound until the first global relabel
+        st.d[v] = 0;
         st.fd[v] = 0;
+#pragma unroll
         for (int k = 0; k < 4; ++k) st.fl[(size_t)k * g.N + v] = 0;
     }
     ts_sum = wave_sum64(ts_sum);
-    if ((tid & 63) == 0 && ts_sum) atomicAdd((unsigned long long *)&s->flow, (unsigned long long)ts_sum);
+    if (lane_id() == 0 && ts_sum) atomicAdd((unsigned long long *)&s->flow, (unsigned long long)ts_sum);
     if (bad) atomicOr(&s->err, kErrCostRange);
 }
 
-// Loads are issued a chunk of kCh levels at a time so that a thread keeps
-// many independent loads in flight instead of one level's worth.
-constexpr int kCh = 8;
+// ---- push phase -----------------------------------------------------------
+
+// Appends `value` for every lane with `want` to a device list with one
+// counter atomic per wave (a single counter shared by all waves would
+// otherwise serialise every append).  Called by all lanes of the wave.
+__device__ __forceinline__ void wave_append(int *list, int *count, bool want, int value)
+{
+    const unsigned long long b = __ballot(want);
+    if (!b) return;
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)b) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(b));
+    base = __shfl(base, leader, kWave);
+    if (want) list[base + __popcll(b & ((1ULL << lane) - 1ULL))] = value;
+}
+
+// Records that column q may hold work in the chunk groups `bits` after the
+// push phase.  No value is returned, so the wave does not wait for it; the
+// phase's column list is built afterwards from the masks (k_compact).
+__device__ __forceinline__ void mark_mask(const Work &w, int q, unsigned long long bits)
+{
+    atomicOr(w.mask + q, bits);
+}
+
+// Column list of every column with a non-empty work mask.
+__global__ __launch_bounds__(256) void k_compact(Work w, int P)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool want = p < P && w.mask[p] != 0;
+    wave_append(w.list, w.count, want, p);
+}
+
+// Loads of one 64-height chunk of a column: the node words of every lane,
+// plus the label below lane 0 and the label and down flow above lane 63.
+struct ChunkIn {
+    int e, d, ts, fd;      // this lane's node
+    int d_below;           // label of (p, z-1) (kInf at z = 0 or outside)
+    int d_above, fd_above; // label and down flow of (p, z+1) (kInf / 0 at the top)
+};
+
+__device__ __forceinline__ ChunkIn load_chunk(const State &st, size_t v, int z, int K, int lane)
+{
+    ChunkIn r;
+    const bool in = z < K;
+    r.e = in ? st.e[v] : 0;
+    r.d = in ? st.d[v] : kInf;
+    r.ts = in ? st.ts[v] : 0;
+    r.fd = in ? st.fd[v] : 0;
+    const int edge_below = (lane == 0 && in && z > 0) ? st.d[v - 1] : kInf;
+    const bool top_lane = lane == kWave - 1 && z + 1 < K;
+    const int edge_d_above = top_lane ? st.d[v + 1] : kInf;
+    const int edge_fd_above = top_lane ? st.fd[v + 1] : 0;
+    const int sd_below = __shfl_up(r.d, 1, kWave);
+    const int sd_above = __shfl_down(r.d, 1, kWave);
+    const int sfd_above = __shfl_down(r.fd, 1, kWave);
+    r.d_below = lane == 0 ? edge_below : (in ? sd_below : kInf);
+    if (lane == kWave - 1) {
+        r.d_above = edge_d_above;
+        r.fd_above = edge_fd_above;
+    } else {
+        r.d_above = z + 1 < K ? sd_above : kInf;
+        r.fd_above = z + 1 < K ? sfd_above : 0;
+    }
+    return r;
+}
+
+// Lateral neighbourhood of one node: labels of the heads of its forward
+// lateral arcs, and flow and tail label of the lateral arcs that end at it
+// (its reverse residual arcs).  Loaded only for lanes that need them; the
+// words of a chunk are 64 consecutive heights of the neighbour column.
+struct Lateral {
+    int d_fwd[4];   // label of (q, zh) (kInf: no arc)
+    int f_rev[4];   // flow on (q, zt) -> (p, z) (0: no arc)
+    int d_rev[4];   // label of (q, zt)
+};
+
+__device__ __forceinline__ void load_lateral(Lateral &l, const State &st, const int q[4], int z,
+                                             int K, int N, int dl, bool need)
+{
+    const bool fwd = need && lat_arc(z, dl);
+    const int zh = lat_head(z, dl);
+    const int zt = lat_tail(z, dl, K);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool has = q[k] >= 0;
+        l.d_fwd[k] = (fwd && has) ? st.d[(size_t)q[k] * K + zh] : kInf;
+        const bool rev = need && has && zt >= 0;
+        const size_t w = (size_t)(has ? q[k] : 0) * K + (zt >= 0 ? zt : 0);
+        l.f_rev[k] = rev ? st.fl[(size_t)(k ^ 1) * N + w] : 0;
+        l.d_rev[k] = rev ? st.d[w] : kInf;
+    }
+}
+
+// Push phase of one sweep (labels fixed).  A wave takes a column from the
+// work list and walks the chunks of its work mask top-down (kDown) or
+// bottom-up.  Every node with excess pushes along admissible arcs
+// d(u) = d(w) + len(u, w): to t, then along its column arc in the walking
+// direction (all of it down a length-0 down arc; up a reverse down arc as
+// far as its flow allows), the rest along the column arc against the walking
+// direction, reverse lateral arcs (cancelling flow first) and a forward
+// lateral arc.  The carries along the column come from one clamp-function
+// scan per chunk and continue into the next chunk, so the walk extends past
+// the mask while a carry is alive.  A node's excess word is read once and
+// corrected by one atomic add of the net change; other columns only add to
+// it, so the value read is a valid lower bound of what the node holds.
+template <bool kDown>
+__global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work wout, Scratch *s)
+{
+    const int lane = lane_id();
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    const int K = g.K, N = g.N, dl = g.delta;
+    const int count = *win.count;
+    long long worst = 0;   // largest excess word produced by an atomic add
+    int err = 0;
+    // batches of up to 64 list entries per wave, sized so that every wave of
+    // the grid gets one: lane i fetches entry i, then the wave works through
+    // the batch one column at a time
+    const int bs = min(kWave, max(1, (count + nwaves - 1) / nwaves));
+    for (int b0 = wave * bs; b0 < count; b0 += nwaves * bs) {
+      const int myp = (lane < bs && b0 + lane < count) ? win.list[b0 + lane] : -1;
+      const unsigned long long mym = myp >= 0 ? win.mask[myp] : 0ULL;
+      if (myp >= 0) win.mask[myp] = 0;
+      unsigned long long myown = 0;
+      unsigned long long todo = __ballot(mym != 0);
+      while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int p = __shfl(myp, src, kWave);
+        const unsigned long long m = (unsigned long long)shfl64((long long)mym, src);
+        const int x = p / g.ny, y = p - x * g.ny;
+        int q[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
+        const size_t base = (size_t)p * K;
+        const int gtop = 63 - __clzll(m), glow = __ffsll((long long)m) - 1;
+        const int ctop = min(g.nch - 1, gtop * g.cpb + g.cpb - 1), clow = glow * g.cpb;
+        unsigned long long own = 0;      // own chunk groups left holding excess
+        long long carry = 0;             // wave-uniform carry into the next chunk
+        for (int step = 0; step < g.nch; ++step) {
+            const int c = kDown ? ctop - step : clow + step;
+            if (c < 0 || c >= g.nch) break;
+            const bool set = (m >> (c / g.cpb)) & 1ULL;
+            if (!set && carry == 0) {
+                if (kDown ? c < clow : c > ctop) break;
+                continue;
+            }
+            const int z = c * kWave + lane;
+            const bool in = z < K;
+            const size_t v = base + z;
+            const ChunkIn ci = load_chunk(st, v, z, K, lane);
+            const int dv = ci.d;
+            const bool live = in && dv < kInf;
+            const long long taken = (live && ci.e > 0) ? ci.e : 0;
+            const long long sink_cap = (live && dv == 1) ? ci.ts : 0;
+            const bool adm_down = live && z > 0 && ci.d_below == dv;
+            const bool adm_up = live && !adm_down && ci.fd_above > 0 && ci.d_above + 1 == dv;
+            // the carry function of this node in the walking direction
+            Clamp f = {0, 0, 0};
+            if (kDown && adm_down) f = {taken - sink_cap, 0, kBig};
+            if (!kDown && adm_up) f = {taken - sink_cap, 0, (long long)ci.fd_above};
+            // inclusive scan in the walking direction, then shift by one lane
+            Clamp sc = f;
+            long long cin;
+            if (kDown) {
+                for (int off = 1; off < kWave; off <<= 1) {
+                    Clamp o = shfl_clamp_down(sc, off);
+                    if (lane + off < kWave) sc = compose(sc, o);
+                }
+                Clamp prev = shfl_clamp_down(sc, 1);
+                cin = lane + 1 < kWave ? apply(prev, carry) : carry;
+                carry = apply(shfl_clamp(sc, 0), carry);
+            } else {
+                for (int off = 1; off < kWave; off <<= 1) {
+                    Clamp o = shfl_clamp_up(sc, off);
+                    if (lane >= off) sc = compose(sc, o);
+                }
+                Clamp prev = shfl_clamp_up(sc, 1);
+                cin = lane > 0 ? apply(prev, carry) : carry;
+                carry = apply(shfl_clamp(sc, kWave - 1), carry);
+            }
+            long long rem = live ? taken + cin : 0;
+            if (rem > 0 && sink_cap > 0) {
+                const long long a = min(rem, sink_cap);
+                st.ts[v] = ci.ts - (int)a;
+                rem -= a;
+            }
+            // results of excess atomics are only inspected at the end of the
+            // chunk, so the wave does not wait for each of them in turn
+            int o_col = 0, o_rev[4] = {0, 0, 0, 0}, o_fwd = 0, o_own = 0;
+            long long a_col = 0, a_rev[4] = {0, 0, 0, 0}, a_fwd = 0, a_own = 0;
+            if (rem > 0 && adm_down) {
+                st.fd[v] = add_flow(ci.fd, rem, err);
+                if (!kDown) {
+                    a_col = rem;
+                    o_col = atomicAdd(st.e + v - 1, (int)min(rem, (long long)INT_MAX));
+                    own |= 1ULL << ((z - 1) / kWave / g.cpb);
+                }
+                rem = 0;   // walking down: the carry scan already moved it
+            }
+            if (rem > 0 && adm_up) {
+                const long long a = min(rem, (long long)ci.fd_above);
+                st.fd[v + 1] = ci.fd_above - (int)a;
+                if (kDown) {
+                    a_col = a;
+                    o_col = atomicAdd(st.e + v + 1, (int)a);
+                    own |= 1ULL << ((z + 1) / kWave / g.cpb);
+                }
+                rem -= a;  // walking up: the carry scan already moved it
+            }
+            const bool need = rem > 0;
+            if (__ballot(need)) {
+                Lateral lt;
+                load_lateral(lt, st, q, z, K, N, dl, need);
+                int fown[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    fown[k] = (need && q[k] >= 0 && lat_arc(z, dl)) ? st.fl[(size_t)k * N + v] : 0;
+                const int zt = lat_tail(z, dl, K), zh = lat_head(z, dl);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const bool go = rem > 0 && lt.f_rev[k] > 0 && lt.d_rev[k] + 1 == dv;
+                    if (go) {
+                        const long long a = min(rem, (long long)lt.f_rev[k]);
+                        const size_t w = (size_t)q[k] * K + zt;
+                        st.fl[(size_t)(k ^ 1) * N + w] = lt.f_rev[k] - (int)a;
+                        a_rev[k] = a;
+                        o_rev[k] = atomicAdd(st.e + w, (int)a);
+                        rem -= a;
+                    }
+                    if (go) mark_mask(wout, q[k], 1ULL << (zt / kWave / g.cpb));
+                }
+                int fwd_k = -1;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (fwd_k < 0 && rem > 0 && lt.d_fwd[k] + 1 == dv) fwd_k = k;
+                if (fwd_k >= 0) {
+                    const size_t w = (size_t)q[fwd_k] * K + zh;
+                    st.fl[(size_t)fwd_k * N + v] = add_flow(fown[fwd_k], rem, err);
+                    a_fwd = rem;
+                    o_fwd = atomicAdd(st.e + w, (int)min(rem, (long long)INT_MAX));
+                    rem = 0;
+                }
+                if (fwd_k >= 0) mark_mask(wout, q[fwd_k], 1ULL << (zh / kWave / g.cpb));
+            }
+            // net change of this node's excess word
+            const long long delta = rem - taken;
+            if (delta != 0) {
+                if (rem > INT_MAX) err = 1;
+                a_own = delta;
+                o_own = atomicAdd(st.e + v, (int)delta);
+            }
+            if (rem > 0) own |= 1ULL << (c / g.cpb);
+            worst = max(worst, a_col ? o_col + a_col : 0);
+            worst = max(worst, a_fwd ? o_fwd + a_fwd : 0);
+            worst = max(worst, a_own ? o_own + a_own : 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) worst = max(worst, a_rev[k] ? o_rev[k] + a_rev[k] : 0);
+        }
+        // combine the lanes' own-column marks; the batch lane of this column
+        // keeps them until the batch is done
+        unsigned lo32 = (unsigned)own, hi32 = (unsigned)(own >> 32);
+        for (int off = 32; off > 0; off >>= 1) {
+            lo32 |= (unsigned)__shfl_xor((int)lo32, off, kWave);
+            hi32 |= (unsigned)__shfl_xor((int)hi32, off, kWave);
+        }
+        if (lane == src) myown = ((unsigned long long)hi32 << 32) | lo32;
+      }
+      if (myown) mark_mask(wout, myp, myown);
+    }
+    if (err || worst > INT_MAX) atomicOr(&s->err, kErrOverflow);
+}
+
+// Relabel phase of one sweep (flows fixed).  A wave takes a column of the
+// push phase's output list: every node of its marked chunks with excess, a
+// finite label and no admissible arc takes d(u) = min over residual arcs of
+// d(w) + len(u, w) (kInf when that exceeds every possible distance).  The
+// column's mask is rebuilt from the nodes that stay active, which are
+// counted, and the column goes on the next push phase's list.
+__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Work wout, Scratch *s)
+{
+    const int lane = lane_id();
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    const int K = g.K, N = g.N, dl = g.delta;
+    const int count = *win.count;
+    int cnt = 0;
+    const int bs = min(kWave, max(1, (count + nwaves - 1) / nwaves));
+    for (int b0 = wave * bs; b0 < count; b0 += nwaves * bs) {
+      const int myp = (lane < bs && b0 + lane < count) ? win.list[b0 + lane] : -1;
+      const unsigned long long mym = myp >= 0 ? win.mask[myp] : 0ULL;
+      if (myp >= 0) win.mask[myp] = 0;
+      unsigned long long mynm = 0;
+      unsigned long long todo = __ballot(mym != 0);
+      while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int p = __shfl(myp, src, kWave);
+        const unsigned long long m = (unsigned long long)shfl64((long long)mym, src);
+        const int x = p / g.ny, y = p - x * g.ny;
+        int q[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
+        const size_t base = (size_t)p * K;
+        unsigned long long nm = 0;
+        for (int c = 0; c < g.nch; ++c) {
+            if (!((m >> (c / g.cpb)) & 1ULL)) continue;
+            const int z = c * kWave + lane;
+            const bool in = z < K;
+            const size_t v = base + z;
+            const ChunkIn ci = load_chunk(st, v, z, K, lane);
+            int dv = ci.d;
+            bool act = in && ci.e > 0 && dv < kInf;
+            if (!__ballot(act)) continue;
+            Lateral lt;
+            load_lateral(lt, st, q, z, K, N, dl, act);
+            if (act) {
+                int b = ci.d_below;   // length-0 down arc
+                if (ci.ts > 0) b = min(b, 1);
+                if (ci.fd_above > 0) b = min(b, ci.d_above + 1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    b = min(b, lt.d_fwd[k] + 1);
+                    if (lt.f_rev[k] > 0) b = min(b, lt.d_rev[k] + 1);
+                }
+                if (b > dv) {
+                    dv = b >= g.lab_cap ? kInf : b;
+                    st.d[v] = dv;
+                }
+                act = dv < kInf;
+            }
+            if (__ballot(act)) nm |= 1ULL << (c / g.cpb);
+            cnt += act ? 1 : 0;
+        }
+        if (lane == src) mynm = nm;
+      }
+      if (mynm) wout.mask[myp] = mynm;
+      wave_append(wout.list, wout.count, mynm != 0, myp);
+    }
+    cnt = wave_sum(cnt);
+    if (lane == 0 && cnt) atomicAdd(&s->active, cnt);
+}
 
 // ---- global relabel: level-synchronous reverse breadth-first search -------
 //
@@ -163,175 +571,199 @@ constexpr int kCh = 8;
 // and the labels d = L+1 are written once, on [T_{L+1}(p), T_L(p)).  Level 1
 // is the suffix above the lowest node with a residual sink arc.  The whole
 // search reads and writes every node O(1) times; each level touches only
-// nx*ny thresholds plus the nodes it labels.
+// the thresholds of columns next to a change plus the nodes it labels.
 //
 // Per-column BFS record, double-buffered by level parity:
 //   T[p]      threshold T_L(p) (K when no node of the column is labelled);
 //   LF[k][p]  lowest z' >= T_L(p) whose lateral arc in direction k carries
-//             flow (K if none) -- the reverse-arc term seen by neighbour k.
+//             flow (K if none) -- the reverse-arc term seen by neighbour k;
+//   CH[p]     the record changed when level L was produced.
 
 __device__ __forceinline__ int lat_head_of(int zp, int dl) { return zp == 0 ? 0 : zp - dl; }
 
-__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *chg,
+// Level 1, one wave per column (all columns).  Nodes that could not reach t
+// before keep kInf: new residual arcs only ever join nodes that reach t, so
+// a node cut off from t stays cut off.  Counts the nodes with excess and a
+// finite label, and those of them labelled 1, for the early stop.
+__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *CH,
                                                   Scratch *s)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
-        s->lvl_changed[1] = 0;
-        s->lvl_lab[1] = 0;
-    }
+    const int lane = lane_id();
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    const int K = g.K, N = g.N, P = g.P;
+    if (blockIdx.x == 0 && threadIdx.x == 0) s->lvl_changed[1] = 0;
     int act = 0, lab_act = 0;
-    if (p < g.P) {
-        const int P = g.P, K = g.K, N = g.N;
+    for (int p = wave; p < P; p += nwaves) {
+        const size_t base = (size_t)p * K;
         int t1 = K;
         int lf[4] = {K, K, K, K};
-        for (int z0 = 0; z0 < K; z0 += kCh) {
-            int tsv[kCh], ev[kCh], dv[kCh], fv[4][kCh];
+        for (int c = 0; c < g.nch; ++c) {
+            const int z = c * kWave + lane;
+            const bool in = z < K;
+            const size_t v = base + z;
+            int tsv = 0, ev = 0, dv = kInf;
+            int fv[4] = {0, 0, 0, 0};
+            if (in) {
+                tsv = st.ts[v];
+                ev = st.e[v];
+                dv = st.d[v];
 #pragma unroll
-            for (int j = 0; j < kCh; ++j) {
-                const int z = z0 + j;
-                tsv[j] = 0;
-                ev[j] = 0;
-                dv[j] = kInf;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k][j] = 0;
-                if (z >= K) continue;
-                const int u = z * P + p;
-                tsv[j] = st.ts[u];
-                ev[j] = st.e[u];
-                dv[j] = st.d[u];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k][j] = st.fl[(size_t)k * N + u];
+                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * N + v];
+            }
+            if (t1 == K) {
+                const unsigned long long sm = __ballot(in && tsv > 0);
+                if (sm) t1 = c * kWave + __ffsll((long long)sm) - 1;
+            }
+            const bool lab = in && z >= t1;
+            if (in) st.d[v] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
+            if (in && ev > 0 && dv < kInf) {
+                ++act;
+                if (lab) ++lab_act;
             }
 #pragma unroll
-            for (int j = 0; j < kCh; ++j) {
-                const int z = z0 + j;
-                if (z >= K) break;
-                if (t1 == K && tsv[j] > 0) t1 = z;
-                const bool lab = t1 < K;
-                // a node that could not reach t never can again (new residual
-                // arcs only join nodes that reach t), so kInf is kept
-                st.d[z * P + p] = lab ? 1 : (dv[j] >= kInf ? kInf : kUnl);
-                if (ev[j] > 0 && dv[j] < kInf) {
-                    ++act;
-                    if (lab) ++lab_act;
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (lab && lf[k] == K && fv[k][j] > 0) lf[k] = z;
+            for (int k = 0; k < 4; ++k) {
+                if (lf[k] < K) continue;
+                const unsigned long long fm = __ballot(lab && fv[k] > 0);
+                if (fm) lf[k] = c * kWave + __ffsll((long long)fm) - 1;
             }
         }
-        T[p] = t1;
-        chg[p] = 1;
+        if (lane == 0) {
+            T[p] = t1;
+            CH[p] = 1;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) LF[k * P + p] = lf[k];
+            for (int k = 0; k < 4; ++k) LF[k * P + p] = lf[k];
+        }
     }
     act = wave_sum(act);
     lab_act = wave_sum(lab_act);
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         if (act) atomicAdd(&s->bfs_active, act);
         if (lab_act) atomicAdd(&s->bfs_labelled, lab_act);
     }
 }
 
-// Level L -> L+1 for one column: threshold arithmetic, then the newly
-// reached heights [cand, T) are labelled L+1 and scanned (from the top, so
-// the last hit is the lowest) for flow-carrying lateral arcs.  Returns the
-// number of newly labelled nodes that hold excess.
-__device__ __forceinline__ int bfs_column_level(const Geom &g, const State &st, int L, int p,
-                                                const int *__restrict__ Tin,
-                                                const int *__restrict__ LFin,
-                                                const int *__restrict__ chg_in,
-                                                int *__restrict__ Tout, int *__restrict__ LFout,
-                                                int *__restrict__ chg_out, bool &changed)
+// Level L -> L+1, one lane per column for the threshold arithmetic.  The
+// newly reached heights [cand, T) are labelled L+1 and scanned for the
+// lowest flow-carrying lateral arc per direction: by the lane itself for a
+// short range, by the whole wave (64 heights at a time) for a long one.
+constexpr int kShortRange = 16;
+
+__global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
+                                                   const int *__restrict__ LFin,
+                                                   const int *__restrict__ CHin, int *__restrict__ Tout,
+                                                   int *__restrict__ LFout, int *__restrict__ CHout,
+                                                   Scratch *s)
 {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    // the flag of the next level is cleared here; stream order puts this
+    // before every write of level L+1
+    if (p == 0) s->lvl_changed[(L + 1) & 63] = 0;
     const int P = g.P, K = g.K, N = g.N, dl = g.delta;
-    const int x = p / g.ny, y = p - x * g.ny;
-    int q[4];
-    const bool self = chg_in[p] != 0;
-    bool near = self;
-    for (int k = 0; k < 4; ++k) {
-        q[k] = nbr(g, x, y, p, k);
-        if (q[k] >= 0 && chg_in[q[k]]) near = true;
-    }
-    // Frontier: with no change at level L-1 around p, nothing of p's inputs
-    // moved.  Both record buffers then already hold p's current record
-    // (it did not change at L-1 either), so nothing is written.
-    if (!near) {
-        chg_out[p] = 0;
-        return 0;
-    }
-    const int T = Tin[p];
-    int cand = T;
-    for (int k = 0; k < 4; ++k) {
-        if (q[k] < 0) continue;
-        const int tq = Tin[q[k]];
-        if (tq == 0) cand = 0;
-        else if (tq + dl < K) cand = min(cand, tq + dl);
-        const int lq = LFin[(k ^ 1) * P + q[k]];
-        if (lq < K) cand = min(cand, lat_head_of(lq, dl));
-    }
-    if (T >= 1 && T < K && st.fd[T * P + p] > 0) cand = min(cand, T - 1);
-    int lf[4];
+    const bool valid = p < P;
+    bool self = false, near = false;
+    int T = 0, cand = 0;
+    int lf[4] = {K, K, K, K};
+    if (valid) {
+        const int x = p / g.ny, y = p - x * g.ny;
+        int q[4];
+        self = CHin[p] != 0;
+        near = self;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) lf[k] = LFin[k * P + p];
+        for (int k = 0; k < 4; ++k) {
+            q[k] = nbr(g, x, y, p, k);
+            if (q[k] >= 0 && CHin[q[k]]) near = true;
+        }
+        // Frontier: with no change at level L-1 around p none of p's inputs
+        // moved, and both record buffers already hold p's record.
+        if (near) {
+            T = Tin[p];
+            cand = T;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (q[k] < 0) continue;
+                const int tq = Tin[q[k]];
+                if (tq == 0) cand = 0;
+                else if (tq + dl < K) cand = min(cand, tq + dl);
+                const int lq = LFin[(k ^ 1) * P + q[k]];
+                if (lq < K) cand = min(cand, lat_head_of(lq, dl));
+            }
+            if (T >= 1 && T < K && st.fd[(size_t)p * K + T] > 0) cand = min(cand, T - 1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lf[k] = LFin[k * P + p];
+        }
+    }
+    const int lab = L + 1;
     int lab_act = 0;
-    if (cand < T) {
-        const int lab = L + 1;
-        for (int z0 = T - 1; z0 >= cand; z0 -= kCh) {
-            int fv[4][kCh], ev[kCh];
+    const bool need = valid && near && cand < T;
+    if (need && T - cand <= kShortRange) {
+        // loads of 8 heights are issued before any of their stores
+        const size_t base = (size_t)p * K;
+        for (int z0 = T - 1; z0 >= cand; z0 -= 8) {
+            int ev[8], fv[4][8];
 #pragma unroll
-            for (int j = 0; j < kCh; ++j) {
+            for (int j = 0; j < 8; ++j) {
                 const int z = z0 - j;
                 const bool in = z >= cand;
-                ev[j] = in ? st.e[z * P + p] : 0;
+                ev[j] = in ? st.e[base + z] : 0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k][j] = in ? st.fl[(size_t)k * N + z * P + p] : 0;
+                for (int k = 0; k < 4; ++k) fv[k][j] = in ? st.fl[(size_t)k * N + base + z] : 0;
             }
 #pragma unroll
-            for (int j = 0; j < kCh; ++j) {
+            for (int j = 0; j < 8; ++j) {
                 const int z = z0 - j;
                 if (z < cand) break;
-                st.d[z * P + p] = lab;
+                st.d[base + z] = lab;
                 lab_act += ev[j] > 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (fv[k][j] > 0) lf[k] = z;
             }
         }
-        changed = true;
     }
-    // a record that changed at L-1 must also reach the other buffer
-    if (cand < T || self) {
-        Tout[p] = cand;
+    unsigned long long todo = __ballot(need && T - cand > kShortRange);
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int pp = __shfl(p, src, kWave);
+        const int lo = __shfl(cand, src, kWave);
+        const int hi = __shfl(T, src, kWave);
+        int found[4] = {-1, -1, -1, -1};
+        for (int z0 = lo; z0 < hi; z0 += kWave) {
+            const int z = z0 + lane;
+            const bool in = z < hi;
+            const size_t v = (size_t)pp * K + z;
+            int fv[4] = {0, 0, 0, 0};
+            if (in) {
+                st.d[v] = lab;
+                lab_act += st.e[v] > 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
+                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * N + v];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned long long b = __ballot(fv[k] > 0);
+                if (found[k] < 0 && b) found[k] = z0 + __ffsll((long long)b) - 1;
+            }
+        }
+        if (lane == src) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (found[k] >= 0) lf[k] = found[k];
+        }
     }
-    chg_out[p] = cand < T;
-    return lab_act;
-}
-
-// One launch per BFS level.
-__global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
-                                                   const int *__restrict__ LFin,
-                                                   const int *__restrict__ chg_in, int *__restrict__ Tout,
-                                                   int *__restrict__ LFout, int *__restrict__ chg_out,
-                                                   Scratch *s)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    // the slots of the next level are cleared here; stream order puts this
-    // before every write of level L+1
-    if (p == 0) {
-        s->lvl_changed[(L + 1) & 63] = 0;
-        s->lvl_lab[(L + 1) & 63] = 0;
+    if (valid) {
+        if (need || self) {
+            Tout[p] = need ? cand : T;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
+        }
+        CHout[p] = need;
     }
-    bool changed = false;
-    int lab_act = 0;
-    if (p < g.P)
-        lab_act = bfs_column_level(g, st, L, p, Tin, LFin, chg_in, Tout, LFout, chg_out, changed);
-    if (changed) s->lvl_changed[L & 63] = 1;
+    if (__ballot(need) && lane == 0) s->lvl_changed[L & 63] = 1;
     lab_act = wave_sum(lab_act);
-    if ((threadIdx.x & 63) == 0 && lab_act) atomicAdd(&s->bfs_labelled, lab_act);
+    if (lane == 0 && lab_act) atomicAdd(&s->bfs_labelled, lab_act);
 }
 
 // End of a global relabel: nodes the search did not reach get `v` (kInf
@@ -343,380 +775,180 @@ __global__ void k_bfs_fixup(int *d, int n, int v)
     if (i < n && d[i] == kUnl) d[i] = v;
 }
 
-// Per-column work ranges.  rlo/rhi bound the heights of the column's nodes
-// that may hold excess with a finite label (lo > hi: none).  Every step that
-// puts excess on a node records its height in the range of the next phase,
-// so a sweep only walks the parts of columns where there is work.
+// ---- minimum cut ---------------------------------------------------------------
+//
+// S_min is the set reached in the residual graph from the nodes that keep
+// excess (the source arcs are saturated).  Down arcs are always residual,
+// so S_min meets every column in a prefix {0..h(p)}; the passes below raise
+// h to the fixed point of the residual arcs.
 
-__device__ __forceinline__ void note_range(int *rlo, int *rhi, int p, int z)
-{
-    atomicMin(rlo + p, z);
-    atomicMax(rhi + p, z);
-}
-
-// Push phase of one sweep (labels fixed).  The thread owning column p walks
-// its work range top-down (kDown) or bottom-up; each node with excess pushes
-// along admissible arcs d(u) = d(w) + len(u, w): to t, down the column,
-// along reverse lateral arcs (cancelling flow first), along forward lateral
-// arcs, and up along reverse down arcs.  Excess moving in the walking
-// direction is carried in a register to the next node of the same walk, so
-// the walk continues past the range while a carry is alive.
-template <bool kDown>
-__global__ __launch_bounds__(256) void k_push(Geom g, State st, const int *__restrict__ rlo_in,
-                                              const int *__restrict__ rhi_in, int *rlo_out,
-                                              int *rhi_out, Scratch *s)
-{
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= g.P) return;
-    const int lo = rlo_in[p], hi = rhi_in[p];
-    if (lo > hi) return;
-    const int P = g.P, K = g.K, N = g.N, dl = g.delta;
-    int x = p / g.ny, y = p - x * g.ny;
-    int q[4];
-    for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
-    int err = 0;
-    int mylo = K, myhi = -1;   // own nodes left holding excess
-    long long carry = 0;
-    // walk index i: z = hi - i (down) or lo + i (up)
-    const int span = kDown ? hi + 1 : K - lo;
-    const int first = kDown ? hi : lo;
-    for (int i0 = 0; i0 < span; i0 += kCh) {
-        if (i0 > (hi - lo) && carry == 0) break;
-        int ev[kCh], dv[kCh];
-#pragma unroll
-        for (int j = 0; j < kCh; ++j) {
-            const int i = i0 + j;
-            ev[j] = 0;
-            dv[j] = kInf;
-            if (i >= span) continue;
-            const int u = (kDown ? first - i : first + i) * P + p;
-            ev[j] = st.e[u];
-            dv[j] = st.d[u];
-        }
-        for (int j = 0; j < kCh; ++j) {
-            const int i = i0 + j;
-            if (i >= span || (i > hi - lo && carry == 0)) break;
-            const int z = kDown ? first - i : first + i;
-            const int u = z * P + p;
-            long long ex = carry;
-            carry = 0;
-            const int eu = ev[j];
-            if (eu <= 0 && ex == 0) continue;
-            const int du = dv[j];
-            if (du >= kInf) {
-                if (ex) add_excess(st.e, u, ex, err);   // not reached: carries follow admissible arcs
-                continue;
-            }
-            if (eu > 0) ex += atomicExch(st.e + u, 0);
-            if (du == 1) {
-                int r = st.ts[u];
-                if (r > 0) {
-                    int a = (int)min<long long>(ex, r);
-                    st.ts[u] = r - a;
-                    ex -= a;
-                }
-            }
-            if (ex > 0 && z > 0 && st.d[u - P] == du) {
-                st.fd[u] = add_flow(st.fd[u], ex, err);
-                if (kDown) {
-                    carry = ex;
-                } else {
-                    add_excess(st.e, u - P, ex, err);
-                    mylo = min(mylo, z - 1);
-                    myhi = max(myhi, z - 1);
-                }
-                ex = 0;
-            }
-            if (ex > 0) {
-                int zt = lat_tail(z, dl, K);
-                if (zt >= 0) {
-                    for (int k = 0; k < 4 && ex > 0; ++k) {
-                        if (q[k] < 0) continue;
-                        int w = zt * P + q[k];
-                        int *fp = st.fl + (size_t)(k ^ 1) * N + w;
-                        int f = *fp;
-                        if (f > 0 && st.d[w] + 1 == du) {
-                            int a = (int)min<long long>(ex, f);
-                            *fp = f - a;
-                            add_excess(st.e, w, a, err);
-                            note_range(rlo_out, rhi_out, q[k], zt);
-                            ex -= a;
-                        }
-                    }
-                }
-            }
-            if (ex > 0 && lat_arc(z, dl)) {
-                const int zh = lat_head(z, dl);
-                for (int k = 0; k < 4; ++k) {
-                    if (q[k] < 0) continue;
-                    int w = zh * P + q[k];
-                    if (st.d[w] + 1 == du) {
-                        st.fl[(size_t)k * N + u] = add_flow(st.fl[(size_t)k * N + u], ex, err);
-                        add_excess(st.e, w, ex, err);
-                        note_range(rlo_out, rhi_out, q[k], zh);
-                        ex = 0;
-                        break;
-                    }
-                }
-            }
-            if (ex > 0 && z + 1 < K) {
-                int w = u + P;
-                int f = st.fd[w];
-                if (f > 0 && st.d[w] + 1 == du) {
-                    int a = (int)min<long long>(ex, f);
-                    st.fd[w] = f - a;
-                    if (kDown) {
-                        add_excess(st.e, w, a, err);
-                        mylo = min(mylo, z + 1);
-                        myhi = max(myhi, z + 1);
-                    } else {
-                        carry = a;
-                    }
-                    ex -= a;
-                }
-            }
-            if (ex > 0) {
-                add_excess(st.e, u, ex, err);
-                mylo = min(mylo, z);
-                myhi = max(myhi, z);
-            }
-        }
-    }
-    if (mylo <= myhi) {
-        atomicMin(rlo_out + p, mylo);
-        atomicMax(rhi_out + p, myhi);
-    }
-    if (err) atomicOr(&s->err, kErrOverflow);
-}
-
-// Relabel phase of one sweep (flows fixed): every node of the work range
-// with excess, a finite label and no admissible arc takes d(u) = min over
-// residual arcs of d(w) + len(u, w) (kInf when that exceeds every possible
-// distance).  The range is then tightened to the nodes that stay active,
-// which are counted; the push phase's input range is reset for reuse.
-__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, int *rlo, int *rhi,
-                                                 int *rlo_reset, int *rhi_reset, Scratch *s)
-{
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    int cnt = 0;
-    if (p < g.P) {
-        const int P = g.P, K = g.K, N = g.N, dl = g.delta;
-        rlo_reset[p] = K;
-        rhi_reset[p] = -1;
-        const int lo = rlo[p], hi = rhi[p];
-        int alo = K, ahi = -1;
-        if (lo <= hi) {
-            int x = p / g.ny, y = p - x * g.ny;
-            int q[4];
-            for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
-            int prev = lo > 0 ? st.d[(lo - 1) * P + p] : kInf;
-            for (int z0 = lo; z0 <= hi; z0 += kCh) {
-                int ev[kCh], dv[kCh];
-#pragma unroll
-                for (int j = 0; j < kCh; ++j) {
-                    const int z = z0 + j;
-                    ev[j] = 0;
-                    dv[j] = kInf;
-                    if (z > hi) continue;
-                    ev[j] = st.e[z * P + p];
-                    dv[j] = st.d[z * P + p];
-                }
-                for (int j = 0; j < kCh; ++j) {
-                    const int z = z0 + j;
-                    if (z > hi) break;
-                    const int u = z * P + p;
-                    int du = dv[j];
-                    if (du < kInf && ev[j] > 0) {
-                        int b = prev;
-                        if (st.ts[u] > 0) b = min(b, 1);
-                        if (z + 1 < K && st.fd[u + P] > 0) b = min(b, st.d[u + P] + 1);
-                        if (lat_arc(z, dl)) {
-                            int zh = lat_head(z, dl) * P;
-                            for (int k = 0; k < 4; ++k)
-                                if (q[k] >= 0) b = min(b, st.d[zh + q[k]] + 1);
-                        }
-                        int zt = lat_tail(z, dl, K);
-                        if (zt >= 0) {
-                            for (int k = 0; k < 4; ++k) {
-                                if (q[k] < 0) continue;
-                                int w = zt * P + q[k];
-                                if (st.fl[(size_t)(k ^ 1) * N + w] > 0) b = min(b, st.d[w] + 1);
-                            }
-                        }
-                        if (b > du) {
-                            du = b >= g.lab_cap ? kInf : b;
-                            st.d[u] = du;
-                        }
-                        if (du < kInf) {
-                            ++cnt;
-                            alo = min(alo, z);
-                            ahi = z;
-                        }
-                    }
-                    prev = du;
-                }
-            }
-        }
-        rlo[p] = alo;
-        rhi[p] = ahi;
-    }
-    cnt = wave_sum(cnt);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&s->active, cnt);
-}
-
-// Minimum cut: S_min is the set reached in the residual graph from the
-// nodes that keep excess (the source arcs are saturated).  Down arcs are
-// always residual, so S_min meets every column in a prefix {0..h(p)}; the
-// passes below raise h to the fixed point of the residual arcs.
+// h(p) = highest node of the column with excess (-1 if none); one wave per column.
 __global__ __launch_bounds__(256) void k_mincut_init(Geom g, State st, int *H)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= g.P) return;
-    int h = -1;
-    for (int z = 0; z < g.K; ++z)
-        if (st.e[z * g.P + p] > 0) h = z;
-    H[p] = h;
+    const int lane = lane_id();
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    for (int p = wave; p < g.P; p += nwaves) {
+        int h = -1;
+        for (int c = g.nch - 1; c >= 0 && h < 0; --c) {
+            const int z = c * kWave + lane;
+            const bool hit = z < g.K && st.e[(size_t)p * g.K + z] > 0;
+            const unsigned long long b = __ballot(hit);
+            if (b) h = c * kWave + 63 - __clzll(b);
+        }
+        if (lane == 0) H[p] = h;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, Scratch *s)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= g.P) return;
-    const int P = g.P, K = g.K, N = g.N, dl = g.delta;
-    int x = p / g.ny, y = p - x * g.ny;
+    const int K = g.K, N = g.N, dl = g.delta;
+    const int x = p / g.ny, y = p - x * g.ny;
+    const size_t base = (size_t)p * K;
     const int h0 = H[p];
     int h = h0;
     for (int k = 0; k < 4; ++k) {
-        int qq = nbr(g, x, y, p, k);
+        const int qq = nbr(g, x, y, p, k);
         if (qq < 0) continue;
-        int hq = H[qq];
+        const int hq = H[qq];
         if (hq < 0) continue;
         // forward lateral arcs of q's reached prefix land at heights <= hq - delta (or 0)
         h = max(h, hq > dl ? hq - dl : 0);
         // reverse residual of p's own lateral arcs into q's reached prefix
-        int top = min(K - 1, hq + dl);
+        const int top = min(K - 1, hq + dl);
         for (int z = top; z > h; --z) {
-            if (lat_arc(z, dl) && st.fl[(size_t)k * N + z * P + p] > 0) { h = z; break; }
+            if (lat_arc(z, dl) && st.fl[(size_t)k * N + base + z] > 0) {
+                h = z;
+                break;
+            }
         }
     }
     // reverse residual of down arcs with flow: (p,h) -> (p,h+1)
-    while (h >= 0 && h + 1 < K && st.fd[(h + 1) * P + p] > 0) ++h;
+    while (h >= 0 && h + 1 < K && st.fd[base + h + 1] > 0) ++h;
     if (h != h0) {
         H[p] = h;
         s->changed = 1;
     }
 }
 
-// Flow value F = sum_v (w+(v) - ts(v)) and energy E = sum_p c(p, h(p)).
+// Flow value F = sum_v (w+(v) - ts(v)): the build accumulated sum w+; here
+// the residual sink capacities are subtracted (one thread per node), and
+// E = sum_p c(p, h(p)) is added by the first P threads.
 __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Geom g, State st,
                                                 const int *H, Scratch *s)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
     long long r = 0, en = 0;
-    if (p < g.P) {
-        for (int z = 0; z < g.K; ++z) r += st.ts[z * g.P + p];
-        int h = H[p];
-        if (h >= 0) en = cost[(long long)p * g.K + h];
+    for (int i = i0; i < g.N; i += stride) r += st.ts[i];
+    for (int i = i0; i < g.P; i += stride) {
+        const int h = H[i];
+        if (h >= 0) en += cost[(size_t)i * g.K + h];
     }
     r = wave_sum64(r);
     en = wave_sum64(en);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd((unsigned long long *)&s->flow, (unsigned long long)(-r));
-        atomicAdd((unsigned long long *)&s->energy, (unsigned long long)en);
+    if (lane_id() == 0) {
+        if (r) atomicAdd((unsigned long long *)&s->flow, (unsigned long long)(-r));
+        if (en) atomicAdd((unsigned long long *)&s->energy, (unsigned long long)en);
     }
-}
-
-// Level-major state -> caller's z-fastest layout.
-__global__ void k_export(Geom g, State st, int *e, int *ts, int *fd, int *fl)
-{
-    long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= g.N) return;
-    int p = (int)(o / g.K), z = (int)(o - (long long)p * g.K);
-    int v = z * g.P + p;
-    e[o] = st.e[v];
-    ts[o] = st.ts[v];
-    fd[o] = st.fd[v];
-    for (int k = 0; k < 4; ++k) fl[(long long)k * g.N + o] = st.fl[(long long)k * g.N + v];
 }
 
 // ---- launchers --------------------------------------------------------------
 
-static inline unsigned cols_blocks(const Geom &g) { return (unsigned)((g.P + 255) / 256); }
+static inline unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
+
+// Grid of the grid-stride node kernels (one reduction atomic per wave).
+static inline unsigned stride_blocks(long long n)
+{
+    unsigned b = blocks_for(n);
+    return b < 4096 ? b : 4096;
+}
+
+// Grid of the wave-per-column kernels: enough waves to fill the chip, each
+// looping over its share of the columns.
+static inline unsigned wave_blocks(const Geom &g)
+{
+    long long want = (g.P + 3) / 4;     // 4 waves per 256-thread block
+    return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+}
 
 void launch_init_scratch(Scratch *s, hipStream_t st) { hipLaunchKernelGGL(k_init_scratch, 1, 1, 0, st, s); }
 void launch_set_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_set_int, 1, 1, 0, st, p, v); }
 
-void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+void launch_fill(int *a, int n, int v, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bottom_max, dim3(cols_blocks(g)), dim3(256), 0, st, cost, g.P, g.K, s);
-    dim3 grid((g.P + 63) / 64, (g.K + 63) / 64);
-    hipLaunchKernelGGL(k_build, grid, dim3(256), 0, st, cost, g, sv, s);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, st, a, n, v);
 }
 
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *chg, Scratch *s,
+void launch_work_init(const Geom &g, const Work &a, const Work &b, hipStream_t st)
+{
+    const int bits = (g.nch + g.cpb - 1) / g.cpb;
+    const unsigned long long full = bits >= 64 ? ~0ULL : ((1ULL << bits) - 1);
+    hipLaunchKernelGGL(k_work_init, dim3(blocks_for(g.P)), dim3(256), 0, st, a.mask, a.list,
+                       a.count, b.mask, full, g.P);
+}
+
+void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bottom_max, dim3(blocks_for(g.P)), dim3(256), 0, st, cost, g.P, g.K, s);
+    hipLaunchKernelGGL(k_build, dim3(stride_blocks(g.N)), dim3(256), 0, st, cost, g, sv, s);
+}
+
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, Scratch *s,
                      hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_init, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, T, LF, chg, s);
+    hipLaunchKernelGGL(k_bfs_init, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, T, LF, CH, s);
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *chg_in, int *Tout, int *LFout, int *chg_out, Scratch *s,
+                      const int *CHin, int *Tout, int *LFout, int *CHout, Scratch *s,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_level, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, L, Tin, LFin,
-                       chg_in, Tout, LFout, chg_out, s);
+    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(g.P)), dim3(256), 0, st, g, sv, L, Tin, LFin,
+                       CHin, Tout, LFout, CHout, s);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int v, hipStream_t st)
 {
-    unsigned blocks = (unsigned)(((long long)g.N + 255) / 256);
-    hipLaunchKernelGGL(k_bfs_fixup, dim3(blocks), dim3(256), 0, st, sv.d, g.N, v);
+    hipLaunchKernelGGL(k_bfs_fixup, dim3(blocks_for(g.N)), dim3(256), 0, st, sv.d, g.N, v);
 }
 
-void launch_fill(int *a, int n, int v, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n, v);
-}
-
-void launch_push(const Geom &g, const State &sv, const int *rlo_in, const int *rhi_in,
-                 int *rlo_out, int *rhi_out, Scratch *s, bool down, hipStream_t st)
+void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
+                 bool down, hipStream_t st)
 {
     if (down)
-        hipLaunchKernelGGL(k_push<true>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, rlo_in,
-                           rhi_in, rlo_out, rhi_out, s);
+        hipLaunchKernelGGL(k_push<true>, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
     else
-        hipLaunchKernelGGL(k_push<false>, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, rlo_in,
-                           rhi_in, rlo_out, rhi_out, s);
+        hipLaunchKernelGGL(k_push<false>, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
 }
 
-void launch_relabel(const Geom &g, const State &sv, int *rlo, int *rhi, int *rlo_reset,
-                    int *rhi_reset, Scratch *s, hipStream_t st)
+void launch_compact(const Geom &g, const Work &w, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_relabel, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, rlo, rhi,
-                       rlo_reset, rhi_reset, s);
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(g.P)), dim3(256), 0, st, w, g.P);
+}
+
+void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_relabel, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
 }
 
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mincut_init, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, H);
+    hipLaunchKernelGGL(k_mincut_init, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, H);
 }
 
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mincut_pass, dim3(cols_blocks(g)), dim3(256), 0, st, g, sv, H, s);
+    hipLaunchKernelGGL(k_mincut_pass, dim3(blocks_for(g.P)), dim3(256), 0, st, g, sv, H, s);
 }
 
 void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
                    hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finish, dim3(cols_blocks(g)), dim3(256), 0, st, cost, g, sv, H, s);
-}
-
-void launch_export(const Geom &g, const State &sv, int *e, int *ts, int *fd, int *fl,
-                   hipStream_t st)
-{
-    unsigned blocks = (unsigned)(((long long)g.N + 255) / 256);
-    hipLaunchKernelGGL(k_export, dim3(blocks), dim3(256), 0, st, g, sv, e, ts, fd, fl);
+    hipLaunchKernelGGL(k_finish, dim3(stride_blocks(g.N)), dim3(256), 0, st, cost, g, sv, H, s);
 }
 
 }  // namespace smf
