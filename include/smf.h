@@ -102,8 +102,10 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
- *   "kernel_timing"   -- 1: bracket every kernel launch of a solve with HIP
- *                        events on the solve stream (for benchmarks); 0: off
+ *   "kernel_timing"   -- bit mask of kernel classes (bit 0 build, 1 bfs_reset,
+ *                        2 bfs, 3 push, 4 relabel, 5 mincut, 6 finish): every
+ *                        launch of a selected class is bracketed by HIP events
+ *                        on the solve stream (for benchmarks); 0: off
  * Returns SMF_ERR_ARG for an unknown key or an out-of-range value. */
 int smf_set_param(smf_handle *h, const char *key, int64_t value);
 

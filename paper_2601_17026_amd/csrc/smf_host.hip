@@ -68,7 +68,7 @@ static const char *const kKClassName[KC_COUNT] = {"build", "bfs_reset", "bfs", "
                                                   "mincut", "finish"};
 
 struct KernelTimer {
-    bool on = false;
+    unsigned on = 0;   // bit i: time kernel class i
     struct Pending { int kc; hipEvent_t a, b; };
     std::vector<hipEvent_t> pool;
     std::vector<Pending> pending;
@@ -120,7 +120,7 @@ struct TimedScope {
     hipEvent_t a = nullptr;
     TimedScope(KernelTimer &t_, int kc_, hipStream_t s_) : t(t_), kc(kc_), s(s_)
     {
-        if (t.on && (a = t.take())) (void)hipEventRecord(a, s);
+        if (((t.on >> kc) & 1u) && (a = t.take())) (void)hipEventRecord(a, s);
     }
     ~TimedScope()
     {
@@ -436,8 +436,9 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
         return SMF_OK;
     }
     else if (!strcmp(key, "kernel_timing")) {
-        if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: kernel_timing is 0 or 1");
-        h->timer.on = value == 1;
+        if (value < 0 || value >= (1 << KC_COUNT))
+            return fail(SMF_ERR_ARG, "smf_set_param: kernel_timing is a mask of the kernel classes");
+        h->timer.on = (unsigned)value;
         return SMF_OK;
     }
     if (!slot) return fail(SMF_ERR_ARG, std::string("smf_set_param: unknown key ") + key);

@@ -644,11 +644,11 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
 }
 
 // Level L -> L+1, one lane per column for the threshold arithmetic.  The
-// newly reached heights [cand, T) are labelled L+1 and scanned for the
-// lowest flow-carrying lateral arc per direction: by the lane itself for a
-// short range, by the whole wave (64 heights at a time) for a long one.
-constexpr int kShortRange = 16;
-
+// newly reached heights [cand, T) of the wave's 64 columns are then
+// labelled L+1 as one flattened list of (column, height) items, 64 per
+// step, so a wave's time follows the number of nodes it labels rather than
+// its longest range.  Flow-carrying lateral arcs among them lower the
+// column's record with atomicMin.
 __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin,
                                                    const int *__restrict__ CHin, int *__restrict__ Tout,
@@ -694,65 +694,7 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
             for (int k = 0; k < 4; ++k) lf[k] = LFin[k * P + p];
         }
     }
-    const int lab = L + 1;
-    int lab_act = 0;
     const bool need = valid && near && cand < T;
-    if (need && T - cand <= kShortRange) {
-        // loads of 8 heights are issued before any of their stores
-        const size_t base = (size_t)p * K;
-        for (int z0 = T - 1; z0 >= cand; z0 -= 8) {
-            int ev[8], fv[4][8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int z = z0 - j;
-                const bool in = z >= cand;
-                ev[j] = in ? st.e[base + z] : 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k][j] = in ? st.fl[(size_t)k * N + base + z] : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int z = z0 - j;
-                if (z < cand) break;
-                st.d[base + z] = lab;
-                lab_act += ev[j] > 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (fv[k][j] > 0) lf[k] = z;
-            }
-        }
-    }
-    unsigned long long todo = __ballot(need && T - cand > kShortRange);
-    while (todo) {
-        const int src = __ffsll((long long)todo) - 1;
-        todo &= todo - 1;
-        const int pp = __shfl(p, src, kWave);
-        const int lo = __shfl(cand, src, kWave);
-        const int hi = __shfl(T, src, kWave);
-        int found[4] = {-1, -1, -1, -1};
-        for (int z0 = lo; z0 < hi; z0 += kWave) {
-            const int z = z0 + lane;
-            const bool in = z < hi;
-            const size_t v = (size_t)pp * K + z;
-            int fv[4] = {0, 0, 0, 0};
-            if (in) {
-                st.d[v] = lab;
-                lab_act += st.e[v] > 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * N + v];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const unsigned long long b = __ballot(fv[k] > 0);
-                if (found[k] < 0 && b) found[k] = z0 + __ffsll((long long)b) - 1;
-            }
-        }
-        if (lane == src) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (found[k] >= 0) lf[k] = found[k];
-        }
-    }
     if (valid) {
         if (need || self) {
             Tout[p] = need ? cand : T;
@@ -762,6 +704,45 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
         CHout[p] = need;
     }
     if (__ballot(need) && lane == 0) s->lvl_changed[L & 63] = 1;
+    // flattened labelling of the wave's new ranges
+    const int len = need ? T - cand : 0;
+    int incl = len;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
+    }
+    const int excl = incl - len;
+    const int total = __shfl(incl, kWave - 1, kWave);
+    const int lab = L + 1;
+    int lab_act = 0;
+    if (total > 0) {
+        __threadfence_block();   // the record stores above precede the atomicMin below
+        for (int i0 = 0; i0 < total; i0 += kWave) {
+            const int item = i0 + lane;
+            // owner: the last lane whose exclusive prefix is <= item
+            int o = 0;
+            for (int step = 32; step > 0; step >>= 1) {
+                const int c = o + step;
+                const int ex = __shfl(excl, c < kWave ? c : kWave - 1, kWave);
+                if (c < kWave && ex <= item) o = c;
+            }
+            const int pp = __shfl(p, o, kWave);
+            const int hi = __shfl(T, o, kWave);
+            const int z = hi - 1 - (item - __shfl(excl, o, kWave));
+            if (item < total) {
+                const size_t v = (size_t)pp * K + z;
+                const int ev = st.e[v];
+                int fv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * N + v];
+                st.d[v] = lab;
+                lab_act += ev > 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (fv[k] > 0) atomicMin(LFout + k * P + pp, z);
+            }
+        }
+    }
     lab_act = wave_sum(lab_act);
     if (lane == 0 && lab_act) atomicAdd(&s->bfs_labelled, lab_act);
 }
