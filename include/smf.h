@@ -102,6 +102,9 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
+ *   "count_work"      -- 1: kernels count their algorithmic bytes ("bytes.<class>"
+ *                        statistics of bfs, push, relabel; one atomic per wave
+ *                        into 64 spread counters)
  *   "kernel_timing"   -- bit mask of kernel classes (bit 0 build, 1 bfs_reset,
  *                        2 bfs, 3 push, 4 relabel, 5 mincut, 6 finish): every
  *                        launch of a selected class is bracketed by HIP events
@@ -112,7 +115,10 @@ int smf_set_param(smf_handle *h, const char *key, int64_t value);
 /* Counters of the last solve.  Keys: "sweeps", "global_relabels",
  * "bfs_passes", "mincut_passes", "gap_relabels", and with kernel_timing on,
  * "time_ns.<class>" (summed event time) and "launches.<class>" for the
- * kernel classes build, bfs_reset, bfs, push, relabel, mincut, finish. */
+ * kernel classes build, bfs_reset, bfs, push, relabel, mincut, finish, and
+ * "bytes.<class>": algorithmic bytes of the class over the solve (state words
+ * read or written, each access counted once; counted on the device for the
+ * data-dependent classes bfs, push and relabel). */
 int smf_get_stat(const smf_handle *h, const char *key, int64_t *out);
 
 /* Static text for a status code. */

@@ -26,7 +26,12 @@ struct Geom {
     int lab_cap;  // labels >= lab_cap are unreachable (N + 1, at most kInf)
     int nch;      // 64-height chunks per column
     int cpb;      // chunks per work-mask bit (nch <= 64 * cpb)
+    int count_work;  // 1: kernels add their algorithmic bytes to `work`
+    // [3 classes][64 slots][16] counters: a wave adds to slot blockIdx % 64 of
+    // its class (entry 0 of the slot), so the adds spread over 64 cache lines
+    unsigned long long *work;
 };
+constexpr int kWorkSlots = 64, kWorkStride = 16;
 
 // Per-node solver state; each array holds N int32, column-major.
 struct State {

@@ -69,7 +69,7 @@ static const char *const kKClassName[KC_COUNT] = {"build", "bfs_reset", "bfs", "
 
 struct KernelTimer {
     unsigned on = 0;   // bit i: time kernel class i
-    struct Pending { int kc; hipEvent_t a, b; };
+    struct Pending { int kc; int n; hipEvent_t a, b; };
     std::vector<hipEvent_t> pool;
     std::vector<Pending> pending;
     double ns[KC_COUNT] = {};
@@ -97,7 +97,7 @@ struct KernelTimer {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
                 ns[p.kc] += 1e6 * (double)ms;
-                launches[p.kc] += 1;
+                launches[p.kc] += p.n;
             }
             pool.push_back(p.a);
             pool.push_back(p.b);
@@ -112,13 +112,15 @@ struct KernelTimer {
 };
 
 // RAII bracket: records a start event before and an end event after the
-// launches made in its scope.
+// `n` back-to-back launches of one class made in its scope (events around
+// every launch of a microsecond-scale kernel would distort its duration).
 struct TimedScope {
     KernelTimer &t;
     int kc;
     hipStream_t s;
+    int n;
     hipEvent_t a = nullptr;
-    TimedScope(KernelTimer &t_, int kc_, hipStream_t s_) : t(t_), kc(kc_), s(s_)
+    TimedScope(KernelTimer &t_, int kc_, hipStream_t s_, int n_ = 1) : t(t_), kc(kc_), s(s_), n(n_)
     {
         if (((t.on >> kc) & 1u) && (a = t.take())) (void)hipEventRecord(a, s);
     }
@@ -128,7 +130,7 @@ struct TimedScope {
         hipEvent_t b = t.take();
         if (!b) { t.pool.push_back(a); return; }
         (void)hipEventRecord(b, s);
-        t.pending.push_back({kc, a, b});
+        t.pending.push_back({kc, n, a, b});
     }
 };
 
@@ -138,6 +140,8 @@ struct smf_handle {
     int *state = nullptr;      // 8 * N int32
     int *H = nullptr;          // P int32 surface
     int *bfs = nullptr;        // 12 * P int32: two per-column BFS records (T, LF[4], changed)
+    unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
+    unsigned long long work_bytes[3] = {};  // their sums after the last solve
     unsigned long long *wmask = nullptr;  // 2 * P work masks
     int *wlist = nullptr;                 // 2 * P work-list entries
     Work work[2]{};            // push reads work[0] and writes work[1]; relabel the reverse
@@ -165,6 +169,7 @@ static void release(smf_handle *h)
     if (h->state) (void)hipFree(h->state);
     if (h->H) (void)hipFree(h->H);
     if (h->bfs) (void)hipFree(h->bfs);
+    if (h->wcount) (void)hipFree(h->wcount);
     if (h->wmask) (void)hipFree(h->wmask);
     if (h->wlist) (void)hipFree(h->wlist);
     if (h->scr) (void)hipFree(h->scr);
@@ -199,6 +204,7 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
         hipMalloc((void **)&h->state, sizeof(int) * 8 * (size_t)N) != hipSuccess ||
         hipMalloc((void **)&h->H, sizeof(int) * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->bfs, sizeof(int) * 12 * (size_t)h->g.P) != hipSuccess ||
+        hipMalloc((void **)&h->wcount, sizeof(unsigned long long) * 3 * kWorkSlots * kWorkStride) != hipSuccess ||
         hipMalloc((void **)&h->wmask, sizeof(unsigned long long) * 2 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->wlist, sizeof(int) * 2 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->scr, sizeof(Scratch)) != hipSuccess ||
@@ -209,6 +215,7 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
                                 std::to_string(32.0 * N / (1 << 20)) + " MiB failed");
         return nullptr;
     }
+    h->g.work = h->wcount;
     int *b = h->state;
     size_t n = (size_t)N;
     h->st.e = b;
@@ -260,13 +267,13 @@ static int global_relabel(smf_handle *h, hipStream_t s)
     int L = 1;
     int fill = kInf;
     for (;;) {
-        for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L) {
-            {
-                TimedScope ts(h->timer, KC_BFS, s);
+        {
+            TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
+            for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L) {
                 launch_bfs_level(h->g, h->st, L, T[L & 1], LF[L & 1], CH[L & 1], T[(L + 1) & 1],
                                  LF[(L + 1) & 1], CH[(L + 1) & 1], h->scr, s);
+                h->bfs_passes++;
             }
-            h->bfs_passes++;
         }
         HIP_TRY(hipGetLastError());
         int rc = sync_scratch(h, s);
@@ -302,6 +309,8 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     HIP_TRY(hipSetDevice(h->device));
 
     h->timer.reset();
+    if (h->g.count_work)
+        launch_fill((int *)h->wcount, 2 * 3 * kWorkSlots * kWorkStride, 0, s);
     launch_init_scratch(h->scr, s);
     {
         TimedScope ts(h->timer, KC_BUILD, s);
@@ -328,8 +337,8 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
             {
                 TimedScope ts(h->timer, KC_PUSH, s);
                 launch_push(h->g, h->st, h->work[0], h->work[1], h->scr, (h->sweeps & 1) == 0, s);
-                launch_compact(h->g, h->work[1], s);
             }
+            launch_compact(h->g, h->work[1], s);
             launch_set_int(h->work[0].count, 0, s);
             launch_set_int(&h->scr->active, 0, s);
             {
@@ -372,6 +381,17 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     if (rc) return rc;
     h->flow = h->host->flow;
     h->energy = h->host->energy;
+    if (h->g.count_work) {
+        unsigned long long w[3 * kWorkSlots * kWorkStride];
+        HIP_TRY(hipMemcpyAsync(w, h->wcount, sizeof(w), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int c = 0; c < 3; ++c) {
+            h->work_bytes[c] = 0;
+            for (int i = 0; i < kWorkSlots; ++i) h->work_bytes[c] += w[(c * kWorkSlots + i) * kWorkStride];
+        }
+    } else {
+        h->work_bytes[0] = h->work_bytes[1] = h->work_bytes[2] = 0;
+    }
     h->solved = true;
     return SMF_OK;
 }
@@ -425,6 +445,11 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     else if (!strcmp(key, "max_sweeps")) slot = &h->max_sweeps;
     else if (!strcmp(key, "poll_every")) slot = &h->poll_every;
     else if (!strcmp(key, "bfs_poll_every")) slot = &h->bfs_poll_every;
+    else if (!strcmp(key, "count_work")) {
+        if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: count_work is 0 or 1");
+        h->g.count_work = (int)value;
+        return SMF_OK;
+    }
     else if (!strcmp(key, "verbose")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: verbose is 0 or 1");
         h->verbose = value;
@@ -455,6 +480,20 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
     else if (!strcmp(key, "bfs_passes")) *out = h->bfs_passes;
     else if (!strcmp(key, "mincut_passes")) *out = h->mincut_passes;
     else if (!strcmp(key, "gap_relabels")) *out = h->gap_relabels;
+    else if (!strncmp(key, "bytes.", 6)) {
+        // algorithmic bytes of the last solve per kernel class: counted on the
+        // device for the data-dependent kernels, by formula for the others
+        const char *name = key + 6;
+        const int64_t N = h->g.N, P = h->g.P;
+        if (!strcmp(name, "bfs")) *out = (int64_t)h->work_bytes[0];
+        else if (!strcmp(name, "push")) *out = (int64_t)h->work_bytes[1];
+        else if (!strcmp(name, "relabel")) *out = (int64_t)h->work_bytes[2];
+        else if (!strcmp(name, "build")) *out = 36 * N + 4 * P;
+        else if (!strcmp(name, "bfs_reset")) *out = h->global_relabels * (32 * N + 4 * N);
+        else if (!strcmp(name, "finish")) *out = 4 * N + 8 * P;
+        else if (!strcmp(name, "mincut")) *out = 4 * N + h->mincut_passes * 24 * P;
+        else return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown kernel class in ") + key);
+    }
     else if (!strncmp(key, "time_ns.", 8) || !strncmp(key, "launches.", 9)) {
         bool t = key[0] == 't';
         const char *name = key + (t ? 8 : 9);

@@ -71,6 +71,16 @@ __device__ __forceinline__ long long shfl64_up(long long v, int off)
     return ((long long)hi << 32) | (unsigned int)lo;
 }
 
+// Adds a wave's algorithmic bytes (state words read or written, each access
+// counted once) to the solve counter of kernel class `cls`.
+__device__ __forceinline__ void count_bytes(const Geom &g, int cls, long long lane_bytes)
+{
+    const long long b = wave_sum64(lane_bytes);
+    if ((threadIdx.x & (kWave - 1)) == 0 && b)
+        atomicAdd(g.work + ((size_t)cls * kWorkSlots + (blockIdx.x & (kWorkSlots - 1))) * kWorkStride,
+                  (unsigned long long)b);
+}
+
 __device__ __forceinline__ void add_excess(int *e, size_t w, long long a, int &err)
 {
     if (a > INT_MAX) { err = 1; a = INT_MAX; }
@@ -325,6 +335,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
     const int K = g.K, N = g.N, dl = g.delta;
     const int count = *win.count;
     long long worst = 0;   // largest excess word produced by an atomic add
+    long long bytes = 0;   // algorithmic bytes moved by this lane
     int err = 0;
     // batches of up to 64 list entries per wave, sized so that every wave of
     // the grid gets one: lane i fetches entry i, then the wave works through
@@ -362,6 +373,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
             const bool in = z < K;
             const size_t v = base + z;
             const ChunkIn ci = load_chunk(st, v, z, K, lane);
+            bytes += in ? 16 : 0;
             const int dv = ci.d;
             const bool live = in && dv < kInf;
             const long long taken = (live && ci.e > 0) ? ci.e : 0;
@@ -397,6 +409,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
                 const long long a = min(rem, sink_cap);
                 st.ts[v] = ci.ts - (int)a;
                 rem -= a;
+                bytes += 4;
             }
             // results of excess atomics are only inspected at the end of the
             // chunk, so the wave does not wait for each of them in turn
@@ -404,6 +417,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
             long long a_col = 0, a_rev[4] = {0, 0, 0, 0}, a_fwd = 0, a_own = 0;
             if (rem > 0 && adm_down) {
                 st.fd[v] = add_flow(ci.fd, rem, err);
+                bytes += kDown ? 4 : 12;
                 if (!kDown) {
                     a_col = rem;
                     o_col = atomicAdd(st.e + v - 1, (int)min(rem, (long long)INT_MAX));
@@ -414,6 +428,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
             if (rem > 0 && adm_up) {
                 const long long a = min(rem, (long long)ci.fd_above);
                 st.fd[v + 1] = ci.fd_above - (int)a;
+                bytes += kDown ? 12 : 4;
                 if (kDown) {
                     a_col = a;
                     o_col = atomicAdd(st.e + v + 1, (int)a);
@@ -425,6 +440,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
             if (__ballot(need)) {
                 Lateral lt;
                 load_lateral(lt, st, q, z, K, N, dl, need);
+                bytes += need ? 64 : 0;
                 int fown[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -440,6 +456,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
                         a_rev[k] = a;
                         o_rev[k] = atomicAdd(st.e + w, (int)a);
                         rem -= a;
+                        bytes += 8;
                     }
                     if (go) mark_mask(wout, q[k], 1ULL << (zt / kWave / g.cpb));
                 }
@@ -453,6 +470,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
                     a_fwd = rem;
                     o_fwd = atomicAdd(st.e + w, (int)min(rem, (long long)INT_MAX));
                     rem = 0;
+                    bytes += 8;
                 }
                 if (fwd_k >= 0) mark_mask(wout, q[fwd_k], 1ULL << (zh / kWave / g.cpb));
             }
@@ -462,6 +480,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
                 if (rem > INT_MAX) err = 1;
                 a_own = delta;
                 o_own = atomicAdd(st.e + v, (int)delta);
+                bytes += 4;
             }
             if (rem > 0) own |= 1ULL << (c / g.cpb);
             worst = max(worst, a_col ? o_col + a_col : 0);
@@ -481,6 +500,7 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
       }
       if (myown) mark_mask(wout, myp, myown);
     }
+    if (g.count_work) count_bytes(g, 1, bytes);
     if (err || worst > INT_MAX) atomicOr(&s->err, kErrOverflow);
 }
 
@@ -498,6 +518,7 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
     const int K = g.K, N = g.N, dl = g.delta;
     const int count = *win.count;
     int cnt = 0;
+    long long bytes = 0;
     const int bs = min(kWave, max(1, (count + nwaves - 1) / nwaves));
     for (int b0 = wave * bs; b0 < count; b0 += nwaves * bs) {
       const int myp = (lane < bs && b0 + lane < count) ? win.list[b0 + lane] : -1;
@@ -522,11 +543,13 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
             const bool in = z < K;
             const size_t v = base + z;
             const ChunkIn ci = load_chunk(st, v, z, K, lane);
+            bytes += in ? 16 : 0;
             int dv = ci.d;
             bool act = in && ci.e > 0 && dv < kInf;
             if (!__ballot(act)) continue;
             Lateral lt;
             load_lateral(lt, st, q, z, K, N, dl, act);
+            bytes += act ? 48 : 0;
             if (act) {
                 int b = ci.d_below;   // length-0 down arc
                 if (ci.ts > 0) b = min(b, 1);
@@ -539,6 +562,7 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
                 if (b > dv) {
                     dv = b >= g.lab_cap ? kInf : b;
                     st.d[v] = dv;
+                    bytes += 4;
                 }
                 act = dv < kInf;
             }
@@ -550,6 +574,7 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
       if (mynm) wout.mask[myp] = mynm;
       wave_append(wout.list, wout.count, mynm != 0, myp);
     }
+    if (g.count_work) count_bytes(g, 2, bytes);
     cnt = wave_sum(cnt);
     if (lane == 0 && cnt) atomicAdd(&s->active, cnt);
 }
@@ -695,6 +720,10 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
         }
     }
     const bool need = valid && near && cand < T;
+    long long bytes = valid ? 4 * (1 + (p % g.ny != 0) + (p % g.ny != g.ny - 1) + (p >= g.ny) +
+                                   (p < P - g.ny)) + 4 : 0;
+    if (valid && near) bytes += 4 * 14;
+    if (valid && (need || self)) bytes += 20;
     if (valid) {
         if (need || self) {
             Tout[p] = need ? cand : T;
@@ -737,12 +766,14 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
                 for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * N + v];
                 st.d[v] = lab;
                 lab_act += ev > 0;
+                bytes += 24;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (fv[k] > 0) atomicMin(LFout + k * P + pp, z);
             }
         }
     }
+    if (g.count_work) count_bytes(g, 0, bytes);
     lab_act = wave_sum(lab_act);
     if (lane == 0 && lab_act) atomicAdd(&s->bfs_labelled, lab_act);
 }
