@@ -99,6 +99,9 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *   "max_sweeps"      -- sweep cap before SMF_ERR_NOT_CONVERGED (>= 1)
  *   "poll_every"      -- sweeps between host termination checks (>= 1)
  *   "bfs_poll_every"  -- BFS levels between host convergence checks (>= 1)
+ *   "gap_every"       -- sweeps between searches for an empty label (gap
+ *                        heuristic, Section 2.1; labels below 4096 are
+ *                        tracked); 0 turns it off (default 0)
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
@@ -113,13 +116,26 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
 int smf_set_param(smf_handle *h, const char *key, int64_t value);
 
 /* Counters of the last solve.  Keys: "sweeps", "global_relabels",
- * "bfs_passes", "mincut_passes", "gap_relabels", and with kernel_timing on,
+ * "bfs_passes", "mincut_passes", "gap_relabels" (active nodes frozen by the
+ * gap heuristic), "gap_searches", and with kernel_timing on,
  * "time_ns.<class>" (summed event time) and "launches.<class>" for the
  * kernel classes build, bfs_reset, bfs, push, relabel, mincut, finish, and
  * "bytes.<class>": algorithmic bytes of the class over the solve (state words
  * read or written, each access counted once; counted on the device for the
  * data-dependent classes bfs, push and relabel). */
 int smf_get_stat(const smf_handle *h, const char *key, int64_t *out);
+
+/* Backward of the optimal energy with respect to the costs (Section 1.1,
+ * Eq. 1): grad_cost[b][x][y][z] = grad_energy[b] if z == surface[b][x][y],
+ * else 0, for a batch of n surfaces.  All pointers are device pointers:
+ * surface [n][nx][ny] int32 (heights in [0, K-1]), grad_energy [n] float,
+ * grad_cost [n][nx][ny][K] float (fully overwritten; 16-byte aligned when
+ * K % 4 == 0).  The indicator is the derivative wherever a column's optimal
+ * height is unique and a supergradient otherwise.  Enqueued on `stream`;
+ * returns SMF_ERR_ARG for bad sizes or NULL pointers. */
+int smf_onehot_backward(const int32_t *surface_dev, const float *grad_energy_dev,
+                        float *grad_cost_dev, int32_t n, int32_t nx, int32_t ny, int32_t K,
+                        void *stream);
 
 /* Static text for a status code. */
 const char *smf_status_string(int status);

@@ -1,0 +1,67 @@
+"""Differentiable optimal-surface energy.
+
+`SurfaceEnergy.apply(cost, delta)` takes a float32 CUDA tensor of shape
+(B, nx, ny, K), quantises it to int32 costs c_i = round(scale * cost) (torch
+rounds half to even), solves every volume exactly with the C-ABI library and
+returns (E, h): E[b] = sum_p c_i[b](p, h_b(p)) / scale as float32, and the
+pointwise-lowest optimal surface h (int32, not differentiable).
+
+E is a minimum of functions linear in the costs (Section 1.1, Eq. 1), so its
+gradient is the one-hot indicator of the optimal height of each column
+(exact where the column's optimal height is unique, a supergradient
+otherwise).  The backward pass passes it straight through the quantisation
+and runs as the library's HIP scatter kernel (smf_onehot_backward).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import smf
+
+_SOLVERS: dict = {}
+
+
+def _solver(nx: int, ny: int, K: int, delta: int) -> smf.Solver:
+    key = (torch.cuda.current_device(), nx, ny, K, delta)
+    s = _SOLVERS.get(key)
+    if s is None:
+        s = smf.Solver(nx, ny, K, delta)
+        _SOLVERS[key] = s
+    return s
+
+
+def quantize(cost: torch.Tensor, scale: float = 16.0) -> torch.Tensor:
+    """int32 costs round(scale * cost) (half to even)."""
+    return torch.round(cost * scale).to(torch.int32).contiguous()
+
+
+class SurfaceEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, cost: torch.Tensor, delta: int, scale: float = 16.0):
+        if cost.dim() != 4 or cost.device.type != "cuda":
+            raise ValueError("cost must be a (B, nx, ny, K) CUDA tensor")
+        B, nx, ny, K = cost.shape
+        ci = quantize(cost.detach().float(), scale)
+        solver = _solver(nx, ny, K, int(delta))
+        h = torch.empty((B, nx, ny), dtype=torch.int32, device=cost.device)
+        energies = []
+        for b in range(B):
+            solver.solve(ci[b])
+            solver.surface(out=h[b])
+            energies.append(solver.energy())
+        E = torch.tensor([e / scale for e in energies], dtype=torch.float32, device=cost.device)
+        ctx.save_for_backward(h)
+        ctx.K = K
+        ctx.mark_non_differentiable(h)
+        return E, h
+
+    @staticmethod
+    def backward(ctx, grad_E, grad_h):
+        (h,) = ctx.saved_tensors
+        g = grad_E.detach().float().contiguous()
+        grad = smf.onehot_backward(h, g, ctx.K)
+        return grad, None, None
+
+
+def surface_energy(cost: torch.Tensor, delta: int, scale: float = 16.0):
+    return SurfaceEnergy.apply(cost, delta, scale)

@@ -30,6 +30,8 @@ struct Geom {
     // [3 classes][64 slots][16] counters: a wave adds to slot blockIdx % 64 of
     // its class (entry 0 of the slot), so the adds spread over 64 cache lines
     unsigned long long *work;
+    int *hist;       // number of nodes per finite label, labels < hist_len
+    int hist_len;
 };
 constexpr int kWorkSlots = 64, kWorkStride = 16;
 
@@ -62,6 +64,8 @@ struct Scratch {
     int bfs_active;      // nodes with excess and a finite label when the BFS starts
     int bfs_labelled;    // ... of which the running BFS has labelled so far
     int count[2];        // sizes of the two column work lists
+    int gap;             // labels above `gap` cannot reach t (kInf: no gap known)
+    int gap_frozen;      // active nodes cut off by the gap heuristic
     int lvl_changed[64]; // BFS level L labelled something: slot L % 64
 };
 

@@ -38,6 +38,7 @@ void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wo
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                     hipStream_t st);
 void launch_compact(const Geom &g, const Work &w, hipStream_t st);
+void launch_gap_find(const Geom &g, const State &sv, Scratch *s, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
 void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
@@ -134,6 +135,8 @@ struct TimedScope {
     }
 };
 
+constexpr int kHistLen = 4096;      // labels tracked by the gap heuristic (LDS bins)
+
 struct smf_handle {
     Geom g{};
     int device = 0;
@@ -141,6 +144,7 @@ struct smf_handle {
     int *H = nullptr;          // P int32 surface
     int *bfs = nullptr;        // 12 * P int32: two per-column BFS records (T, LF[4], changed)
     unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
+    int *hist = nullptr;                  // label histogram (Geom::hist)
     unsigned long long work_bytes[3] = {};  // their sums after the last solve
     unsigned long long *wmask = nullptr;  // 2 * P work masks
     int *wlist = nullptr;                 // 2 * P work-list entries
@@ -155,11 +159,13 @@ struct smf_handle {
     int64_t bfs_poll_every = 16;
     int64_t bfs_early_stop = 1;
     int64_t verbose = 0;           // 1: progress lines on stderr
+    int64_t gap_every = 0;         // sweeps between gap searches (0: off)
 
     // results and counters of the last solve
     bool solved = false;
     int64_t flow = 0, energy = 0;
     int64_t sweeps = 0, global_relabels = 0, bfs_passes = 0, mincut_passes = 0, gap_relabels = 0;
+    int64_t gap_searches = 0;
     KernelTimer timer;
 };
 
@@ -170,6 +176,7 @@ static void release(smf_handle *h)
     if (h->H) (void)hipFree(h->H);
     if (h->bfs) (void)hipFree(h->bfs);
     if (h->wcount) (void)hipFree(h->wcount);
+    if (h->hist) (void)hipFree(h->hist);
     if (h->wmask) (void)hipFree(h->wmask);
     if (h->wlist) (void)hipFree(h->wlist);
     if (h->scr) (void)hipFree(h->scr);
@@ -205,6 +212,7 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
         hipMalloc((void **)&h->H, sizeof(int) * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->bfs, sizeof(int) * 12 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->wcount, sizeof(unsigned long long) * 3 * kWorkSlots * kWorkStride) != hipSuccess ||
+        hipMalloc((void **)&h->hist, sizeof(int) * kHistLen) != hipSuccess ||
         hipMalloc((void **)&h->wmask, sizeof(unsigned long long) * 2 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->wlist, sizeof(int) * 2 * (size_t)h->g.P) != hipSuccess ||
         hipMalloc((void **)&h->scr, sizeof(Scratch)) != hipSuccess ||
@@ -216,6 +224,8 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
         return nullptr;
     }
     h->g.work = h->wcount;
+    h->g.hist = h->hist;
+    h->g.hist_len = kHistLen;
     int *b = h->state;
     size_t n = (size_t)N;
     h->st.e = b;
@@ -260,6 +270,7 @@ static int global_relabel(smf_handle *h, hipStream_t s)
     int *CH[2] = {h->bfs + 10 * (size_t)P, h->bfs + 11 * (size_t)P};
     launch_set_int(&h->scr->bfs_active, 0, s);
     launch_set_int(&h->scr->bfs_labelled, 0, s);
+    launch_set_int(&h->scr->gap, kInf, s);
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
         launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], h->scr, s);   // level 1 lives in buffer 1
@@ -306,6 +317,7 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     hipStream_t s = (hipStream_t)stream;
     h->solved = false;
     h->sweeps = h->global_relabels = h->bfs_passes = h->mincut_passes = h->gap_relabels = 0;
+    h->gap_searches = 0;
     HIP_TRY(hipSetDevice(h->device));
 
     h->timer.reset();
@@ -346,6 +358,10 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
                 launch_relabel(h->g, h->st, h->work[1], h->work[0], h->scr, s);
             }
             h->sweeps++;
+            if (h->gap_every > 0 && h->sweeps % h->gap_every == 0) {
+                launch_gap_find(h->g, h->st, h->scr, s);
+                h->gap_searches++;
+            }
         }
         HIP_TRY(hipGetLastError());
         rc = sync_scratch(h, s);
@@ -381,6 +397,7 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     if (rc) return rc;
     h->flow = h->host->flow;
     h->energy = h->host->energy;
+    h->gap_relabels = h->host->gap_frozen;
     if (h->g.count_work) {
         unsigned long long w[3 * kWorkSlots * kWorkStride];
         HIP_TRY(hipMemcpyAsync(w, h->wcount, sizeof(w), hipMemcpyDeviceToHost, s));
@@ -445,6 +462,11 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     else if (!strcmp(key, "max_sweeps")) slot = &h->max_sweeps;
     else if (!strcmp(key, "poll_every")) slot = &h->poll_every;
     else if (!strcmp(key, "bfs_poll_every")) slot = &h->bfs_poll_every;
+    else if (!strcmp(key, "gap_every")) {
+        if (value < 0) return fail(SMF_ERR_ARG, "smf_set_param: gap_every must be >= 0");
+        h->gap_every = value;
+        return SMF_OK;
+    }
     else if (!strcmp(key, "count_work")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: count_work is 0 or 1");
         h->g.count_work = (int)value;
@@ -480,6 +502,7 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
     else if (!strcmp(key, "bfs_passes")) *out = h->bfs_passes;
     else if (!strcmp(key, "mincut_passes")) *out = h->mincut_passes;
     else if (!strcmp(key, "gap_relabels")) *out = h->gap_relabels;
+    else if (!strcmp(key, "gap_searches")) *out = h->gap_searches;
     else if (!strncmp(key, "bytes.", 6)) {
         // algorithmic bytes of the last solve per kernel class: counted on the
         // device for the data-dependent kernels, by formula for the others

@@ -143,6 +143,30 @@ __device__ __forceinline__ Clamp shfl_clamp(const Clamp &f, int src)
     return {shfl64(f.A, src), shfl64(f.L, src), shfl64(f.U, src)};
 }
 
+// ---- label histogram (gap heuristic) ---------------------------------------------
+//
+// With labels that drop by at most one along a residual arc (len <= 1), a
+// label g held by no node cuts every node labelled above g off from t
+// (Section 2.1, gap relabelling).  The histogram of the finite labels below
+// hist_len is rebuilt from all nodes whenever a gap search runs.
+
+// Per-block histogram in LDS, flushed to the global one.
+__global__ __launch_bounds__(256) void k_hist_build(Geom g, const int *__restrict__ d)
+{
+    extern __shared__ int bins[];
+    const int len = g.hist_len;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) bins[i] = 0;
+    __syncthreads();
+    const int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.N; v += stride) {
+        const int l = d[v];
+        if (l >= 1 && l < len) atomicAdd(&bins[l], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += blockDim.x)
+        if (bins[i]) atomicAdd(g.hist + i, bins[i]);
+}
+
 // ---- small kernels ------------------------------------------------------------
 
 __global__ void k_init_scratch(Scratch *s)
@@ -157,6 +181,8 @@ __global__ void k_init_scratch(Scratch *s)
     s->bfs_labelled = 0;
     s->count[0] = 0;
     s->count[1] = 0;
+    s->gap = kInf;
+    s->gap_frozen = 0;
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
@@ -517,7 +543,8 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
     const int nwaves = gridDim.x * blockDim.x / kWave;
     const int K = g.K, N = g.N, dl = g.delta;
     const int count = *win.count;
-    int cnt = 0;
+    const int gap = s->gap;
+    int cnt = 0, frozen = 0;
     long long bytes = 0;
     const int bs = min(kWave, max(1, (count + nwaves - 1) / nwaves));
     for (int b0 = wave * bs; b0 < count; b0 += nwaves * bs) {
@@ -546,6 +573,13 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
             bytes += in ? 16 : 0;
             int dv = ci.d;
             bool act = in && ci.e > 0 && dv < kInf;
+            if (act && dv > gap) {
+                // cut off from t by a label gap: frozen for good
+                dv = kInf;
+                st.d[v] = kInf;
+                act = false;
+                ++frozen;
+            }
             if (!__ballot(act)) continue;
             Lateral lt;
             load_lateral(lt, st, q, z, K, N, dl, act);
@@ -576,7 +610,9 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
     }
     if (g.count_work) count_bytes(g, 2, bytes);
     cnt = wave_sum(cnt);
+    frozen = wave_sum(frozen);
     if (lane == 0 && cnt) atomicAdd(&s->active, cnt);
+    if (lane == 0 && frozen) atomicAdd(&s->gap_frozen, frozen);
 }
 
 // ---- global relabel: level-synchronous reverse breadth-first search -------
@@ -781,10 +817,42 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
 // End of a global relabel: nodes the search did not reach get `v` (kInf
 // when it ran to completion, else the first level it did not finish, which
 // is a valid lower bound of their distance).
-__global__ void k_bfs_fixup(int *d, int n, int v)
+__global__ __launch_bounds__(256) void k_bfs_fixup(Geom g, int *d, int n, int v)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && d[i] == kUnl) d[i] = v;
+    int filled = 0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (d[i] == kUnl) {
+            d[i] = v;
+            ++filled;
+        }
+    }
+    (void)filled;
+}
+
+// First label g >= 1 held by no node while some node holds a larger label
+// (kInf if none): one block scans the histogram.
+__global__ __launch_bounds__(1024) void k_gap_find(Geom g, Scratch *s)
+{
+    __shared__ int first_zero, last_used;
+    if (threadIdx.x == 0) {
+        first_zero = INT_MAX;
+        last_used = 0;
+    }
+    __syncthreads();
+    const int len = g.hist_len;
+    const int per = (len + blockDim.x - 1) / blockDim.x;
+    const int lo = max(1, (int)threadIdx.x * per), hi = min(len, ((int)threadIdx.x + 1) * per);
+    int fz = INT_MAX, lu = 0;
+    for (int l = lo; l < hi; ++l) {
+        const int c = g.hist[l];
+        if (c == 0 && fz == INT_MAX) fz = l;
+        if (c > 0) lu = l;
+    }
+    if (fz != INT_MAX) atomicMin(&first_zero, fz);
+    if (lu) atomicMax(&last_used, lu);
+    __syncthreads();
+    if (threadIdx.x == 0) s->gap = first_zero < last_used ? first_zero : kInf;
 }
 
 // ---- minimum cut ---------------------------------------------------------------
@@ -924,7 +992,16 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int v, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_fixup, dim3(blocks_for(g.N)), dim3(256), 0, st, sv.d, g.N, v);
+    hipLaunchKernelGGL(k_bfs_fixup, dim3(stride_blocks(g.N)), dim3(256), 0, st, g, sv.d, g.N, v);
+}
+
+void launch_gap_find(const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(g.hist_len)), dim3(256), 0, st, g.hist, g.hist_len, 0);
+    unsigned blocks = stride_blocks(g.N);
+    if (blocks > 512) blocks = 512;
+    hipLaunchKernelGGL(k_hist_build, dim3(blocks), dim3(256), sizeof(int) * g.hist_len, st, g, sv.d);
+    hipLaunchKernelGGL(k_gap_find, dim3(1), dim3(1024), 0, st, g, s);
 }
 
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,

@@ -45,6 +45,8 @@ _lib.smf_set_param.argtypes = [_P, ctypes.c_char_p, _I64]
 _lib.smf_get_stat.argtypes = [_P, ctypes.c_char_p, _PI64]
 _lib.smf_status_string.argtypes = [ctypes.c_int]
 _lib.smf_status_string.restype = ctypes.c_char_p
+_lib.smf_onehot_backward.argtypes = [_P, _P, _P, _I32, _I32, _I32, _I32, _P]
+_lib.smf_onehot_backward.restype = ctypes.c_int
 _lib.smf_last_error.argtypes = []
 _lib.smf_last_error.restype = ctypes.c_char_p
 for _name in ("smf_solve", "smf_flow_value", "smf_energy", "smf_surface",
@@ -53,7 +55,7 @@ for _name in ("smf_solve", "smf_flow_value", "smf_energy", "smf_surface",
 
 EXPORTED = ("smf_create", "smf_destroy", "smf_solve", "smf_flow_value", "smf_energy",
             "smf_surface", "smf_export_state", "smf_set_param", "smf_get_stat",
-            "smf_status_string", "smf_last_error")
+            "smf_status_string", "smf_last_error", "smf_onehot_backward")
 
 
 class SmfError(RuntimeError):
@@ -94,9 +96,10 @@ class Solver:
         self._h = h
 
     def close(self) -> None:
-        if getattr(self, "_h", None):
-            _lib.smf_destroy(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and _lib is not None:
+            _lib.smf_destroy(h)
 
     def __del__(self):
         self.close()
@@ -151,6 +154,23 @@ class Solver:
         _check(_lib.smf_export_state(self._h, e.data_ptr(), ts.data_ptr(), fd.data_ptr(),
                                      fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
         return e, ts, fd, fl
+
+
+def onehot_backward(surface: torch.Tensor, grad_energy: torch.Tensor, K: int,
+                    out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """grad[b, x, y, z] = grad_energy[b] * [z == surface[b, x, y]] (device tensors)."""
+    if surface.dim() != 3:
+        raise ValueError("surface must be (n, nx, ny)")
+    n, nx, ny = surface.shape
+    _dev_i32(surface, (n, nx, ny), "surface")
+    if grad_energy.device.type != "cuda" or grad_energy.dtype != torch.float32 \
+            or not grad_energy.is_contiguous() or tuple(grad_energy.shape) != (n,):
+        raise ValueError("grad_energy must be a contiguous float32 CUDA tensor of shape (n,)")
+    if out is None:
+        out = torch.empty((n, nx, ny, K), dtype=torch.float32, device=surface.device)
+    _check(_lib.smf_onehot_backward(surface.data_ptr(), grad_energy.data_ptr(), out.data_ptr(),
+                                    n, nx, ny, int(K), _stream_ptr(stream)), "smf_onehot_backward")
+    return out
 
 
 def solve(cost: torch.Tensor, delta: int, stream=None):

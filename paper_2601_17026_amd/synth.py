@@ -32,6 +32,7 @@ __all__ = [
     "config_seismic",
     "batch_shapes",
     "batch_instance",
+    "diff_costs",
     "sha256",
 ]
 
@@ -152,6 +153,28 @@ def batch_shapes(n=64, seed=4000):
 def batch_instance(i, shape):
     nx, ny, K, delta = shape
     return layered_cost(nx, ny, K, 2, 0.4, 255, 0.0, 4001 + i), delta
+
+
+def diff_costs(batch=8, n=128, K=128, seed0=5001, net_seed=5000, device="cuda"):
+    """Float costs of the differentiable workload: a batch of noisy layered
+    intensities (two horizons, sigma 0.3) through a seeded 3-layer 3x3x3
+    convolution net (1 -> 16 -> 16 -> 1 channels, ReLU between, fp32),
+    standardised per volume to mean 0 and std 4.  Returns the (B, n, n, K)
+    costs (no autograd history), the net and its (B, 1, n, n, K) input."""
+    import torch
+
+    torch.manual_seed(net_seed)
+    net = torch.nn.Sequential(
+        torch.nn.Conv3d(1, 16, 3, padding=1), torch.nn.ReLU(),
+        torch.nn.Conv3d(16, 16, 3, padding=1), torch.nn.ReLU(),
+        torch.nn.Conv3d(16, 1, 3, padding=1)).to(device)
+    vols = [layered_intensity(n, n, K, 2, 0.3, seed0 + b)[0] for b in range(batch)]
+    x = torch.from_numpy(np.stack(vols).astype(np.float32))[:, None].to(device)
+    with torch.no_grad():
+        y = net(x)[:, 0]
+    mu = y.mean(dim=(1, 2, 3), keepdim=True)
+    sd = y.std(dim=(1, 2, 3), keepdim=True).clamp_min(1e-6)
+    return ((y - mu) / sd * 4.0).contiguous(), net, x
 
 
 def sha256(a: np.ndarray) -> str:

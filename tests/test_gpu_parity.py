@@ -166,3 +166,21 @@ def test_error_paths(smf):
             s.set_param("no_such_key", 1)
         with pytest.raises(smf.SmfError):
             s.set_param("relabel_period", 0)
+
+
+@pytest.mark.parametrize("params", [
+    {"gap_every": 1},
+    {"gap_every": 2, "relabel_period": 20},
+    {"bfs_early_stop": 0},
+    {"relabel_period": 1},
+    {"relabel_period": 40},
+    {"poll_every": 4, "bfs_poll_every": 3},
+])
+def test_parameter_variants(smf, params):
+    # every schedule knob leaves the exact result unchanged
+    for cost, delta in (synth.config_small(),
+                        (synth.layered_cost(37, 29, 70, 2, 0.4, 255, 0.05, 23), 1)):
+        print(f"case: params {params} shape {cost.shape}", flush=True)
+        g = _gpu_solve(smf, cost, delta, certify=True, params=params)
+        _assert_matches_oracle(cost, delta, g)
+        assert g["cert"].ok, g["cert"]
