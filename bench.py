@@ -6,8 +6,13 @@ One step is one complete solve (graph build, push-relabel with global
 relabels, minimum-cut surface, flow value and energy) of the seismic-scale
 volume: 512 x 512 columns x K = 384 nodes, delta = 2, five nested synthetic
 horizons with sigma 0.4, costs in [0, 1023] and 10% random fault columns.
-The cost volume is resident in HBM before the timed region starts.  Prints
-one JSON line.  Only one GPU is supported.
+The cost volume is resident in HBM before the timed region starts.
+
+The batched leg then solves the 64-volume batch workload (nx, ny, K uniform
+in [64, 256], delta in {1, 2, 3}, layered costs with per-volume seeds) once
+as one batch and once as 64 plain solves one after another on the same
+stream, and reports both rates under "batched".  Prints one JSON line.
+Only one GPU is supported.
 """
 from __future__ import annotations
 
@@ -43,6 +48,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--cpu-crop", type=int, default=48,
                     help="columns per side of the oracle's CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
@@ -98,6 +105,56 @@ def cpu_baseline(cost, delta, crop):
         "seconds": round(dt, 2),
         "sample": f"x<{crop}, y<{crop} crop ({crop}x{crop}x{cost.shape[2]}) of the same "
                   f"volume, delta={delta}; single-threaded Dinic (oracle/oracle.c)",
+    }
+
+
+def batched_leg(args, torch, smf, synth, stream):
+    """Batch of 64 uneven volumes: one batch solve against 64 plain solves."""
+    shapes = synth.batch_shapes()
+    vols = [synth.batch_instance(i, sh)[0] for i, sh in enumerate(shapes)]
+    V = sum(v.size for v in vols)
+    batch = smf.BatchSolver(shapes)
+    packed = batch.pack([torch.from_numpy(v).cuda() for v in vols])
+    plain = [smf.Solver(*sh) for sh in shapes]
+    offs = batch.offsets
+    views = [packed[o:o + v.size].view(v.shape) for o, v in zip(offs, vols)]
+
+    batch.solve(packed, stream=stream)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        batch.solve(packed, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.batch_steps
+    flows = batch.flow_values()
+    sweeps = batch.stat("sweeps")
+
+    for i in range(4):                           # warm-up
+        plain[i].solve(views[i], stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, v in zip(plain, views):
+        s.solve(v, stream)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    same = all(s.flow_value() == f for s, f in zip(plain, flows))
+    for s in plain:
+        s.close()
+    batch.close()
+    return {
+        "value": round(V / t_batch / 1e6, 3),
+        "unit": "Mvoxels/s",
+        "ms_per_batch": round(1e3 * t_batch, 2),
+        "steps": args.batch_steps,
+        "sequential_plain_value": round(V / t_seq / 1e6, 3),
+        "ms_sequential_plain": round(1e3 * t_seq, 2),
+        "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        "volumes": len(shapes),
+        "voxels": V,
+        "batch_sweeps": sweeps,
+        "flows_equal_plain": same,
+        "workload": "64 volumes, nx, ny, K ~ U{64..256}, delta ~ U{1,2,3}, two layered "
+                    "horizons, sigma 0.4, costs 0..255 (per-volume seeds)",
     }
 
 
@@ -208,6 +265,8 @@ def main():
                      "bfs_passes": passes / args.steps},
         "kernels_warmup": kernels,
     }
+    if not args.no_batch:
+        out["batched"] = batched_leg(args, torch, smf, synth, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cost, delta, args.cpu_crop)
     print(json.dumps(out), flush=True)

@@ -43,7 +43,8 @@ enum {
     SMF_OK = 0,
     SMF_ERR_ARG = -1,           /* bad argument (NULL, size, shape mismatch) */
     SMF_ERR_NOMEM = -2,         /* device or host allocation failed */
-    SMF_ERR_RANGE = -3,         /* |cost| >= 2^30, nx*ny*K >= 2^31, or an int32
+    SMF_ERR_RANGE = -3,         /* |cost| >= 2^30, nx*ny*K > 2^30 - 2 for a volume,
+                                   2^31 or more columns in a batch, or an int32
                                    excess/flow counter would overflow */
     SMF_ERR_NOT_CONVERGED = -4, /* sweep cap reached before termination */
     SMF_ERR_HIP = -5,           /* a HIP runtime call failed */
@@ -55,8 +56,23 @@ typedef struct smf_handle smf_handle;
 /* Allocates all solver state for one nx x ny x K volume with smoothness
  * bound delta (Section 1.2, the "edge interval") on the current device:
  * 32 bytes per node plus O(nx*ny).  Returns NULL on failure (see
- * smf_last_error).  Requires nx, ny, K >= 1, delta >= 0, nx*ny*K < 2^31. */
+ * smf_last_error).  Requires nx, ny, K >= 1, delta >= 0,
+ * nx*ny*K <= 2^30 - 2 (every finite distance label then stays below the
+ * solver's reserved label values).  The handle is a batch of one volume:
+ * the smf_batch_* calls accept it too. */
 smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t delta);
+
+/* Allocates one handle for a batch of n independent volumes of uneven
+ * shapes (nx[i], ny[i], K[i], delta[i]; host arrays of n entries, read
+ * during the call only), each meeting the limits of smf_create; the batch
+ * holds fewer than 2^31 columns in total.  The volumes are solved together:
+ * every kernel launch of a solve covers all of them, each with its own
+ * work lists, global-relabel schedule and termination (the paper solves
+ * one volume at a time; batching serves many small volumes, which alone
+ * would leave most of the GPU idle).  Node state is packed volume after
+ * volume in the order given, 32 bytes per node. */
+smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int32_t *ny,
+                             const int32_t *K, const int32_t *delta);
 
 /* Releases the handle and its device memory.  NULL is allowed. */
 void smf_destroy(smf_handle *h);
@@ -65,19 +81,43 @@ void smf_destroy(smf_handle *h);
  * value in (-2^30, 2^30)).  Work is enqueued on `stream`; the call drives
  * the iteration from the host and returns when the result is complete, so
  * on SMF_OK the flow value, energy and surface are ready.  The cost buffer
- * is only read. */
+ * is only read.  SMF_ERR_ARG for a batch handle of more than one volume. */
 int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream);
 
-/* Max-flow value F of the last successful solve (host int64 out). */
+/* Solves every volume of a batch handle.  Volume i's [nx][ny][K] int32
+ * costs start at packed_cost_dev + offsets_host[i] (device pointer plus a
+ * host array of n non-negative int64 element offsets, read during the call;
+ * NULL offsets mean densely packed in order).  Same value range, stream and
+ * completion rules as smf_solve; one failing volume fails the call. */
+int smf_batch_solve(smf_handle *h, const int32_t *packed_cost_dev, const int64_t *offsets_host,
+                    void *stream);
+
+/* Max-flow value F of the last successful solve (host int64 out).
+ * SMF_ERR_ARG for a batch of more than one volume. */
 int smf_flow_value(const smf_handle *h, int64_t *out);
 
-/* Optimal energy E* = sum_p c(p, h(p)) of the last successful solve. */
+/* Optimal energy E* = sum_p c(p, h(p)) of the last successful solve.
+ * SMF_ERR_ARG for a batch of more than one volume. */
 int smf_energy(const smf_handle *h, int64_t *out);
+
+/* Max-flow values of every volume of the last successful batch solve
+ * (host array of n int64, Eq. 5 per volume). */
+int smf_batch_flow_values(const smf_handle *h, int64_t *out);
+
+/* Optimal energies E* of every volume of the last successful batch solve
+ * (host array of n int64). */
+int smf_batch_energies(const smf_handle *h, int64_t *out);
 
 /* Copies the minimal-cut surface h (values in [0, K-1]) of the last
  * successful solve into `out_dev` (device pointer, [nx][ny] int32),
  * enqueued on `stream`. */
 int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream);
+
+/* Copies the surfaces of every volume of the last successful batch solve
+ * into `packed_out_dev` (device pointer, sum_i nx[i]*ny[i] int32): volume
+ * i's [nx][ny] heights follow those of volumes 0..i-1.  Enqueued on
+ * `stream`. */
+int smf_batch_surfaces(const smf_handle *h, int32_t *packed_out_dev, void *stream);
 
 /* Copies the final preflow of the last successful solve into caller device
  * buffers, each [nx][ny][K] int32 (z fastest) except `flow_lat_dev`, which
@@ -89,16 +129,19 @@ int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream);
  *                   and on (p,0) -> (q,0); 0 for absent arcs.  The solver
  *                   omits the arcs (p,z) -> (q,0) for 1 <= z <= delta, which
  *                   are implied by (p,z) -> (p,0) -> (q,0) and change no cut.
- * Source arcs are saturated and never carry flow back.  For certificates and
- * debugging; enqueued on `stream`. */
+ * Source arcs are saturated and never carry flow back.  For a batch, each
+ * buffer holds the volumes' nodes packed in order (total T nodes; flow_lat
+ * [4][T]).  For certificates and debugging; enqueued on `stream`. */
 int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res_dev,
                      int32_t *flow_down_dev, int32_t *flow_lat_dev, void *stream);
 
 /* Tuning and limits.  Keys:
- *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1)
+ *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1;
+ *                        for a batch: of every volume, replacing any per-volume
+ *                        periods)
  *   "max_sweeps"      -- sweep cap before SMF_ERR_NOT_CONVERGED (>= 1)
  *   "poll_every"      -- sweeps between host termination checks (>= 1)
- *   "bfs_poll_every"  -- BFS levels between host convergence checks (>= 1)
+ *   "bfs_poll_every"  -- BFS levels between host convergence checks (1..62)
  *   "gap_every"       -- sweeps between searches for an empty label (gap
  *                        heuristic, Section 2.1; labels below 4096 are
  *                        tracked); 0 turns it off (default 0)
@@ -115,6 +158,12 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  * Returns SMF_ERR_ARG for an unknown key or an out-of-range value. */
 int smf_set_param(smf_handle *h, const char *key, int64_t value);
 
+/* Per-volume tuning of a batch: `values` is a host array of n int64.
+ * Key "relabel_period": sweeps between global relabels of each volume
+ * (0: the handle's relabel_period).  SMF_ERR_ARG for other keys or
+ * negative values. */
+int smf_batch_set_param(smf_handle *h, const char *key, const int64_t *values);
+
 /* Counters of the last solve.  Keys: "sweeps", "global_relabels",
  * "bfs_passes", "mincut_passes", "gap_relabels" (active nodes frozen by the
  * gap heuristic), "gap_searches", and with kernel_timing on,
@@ -122,8 +171,49 @@ int smf_set_param(smf_handle *h, const char *key, int64_t value);
  * kernel classes build, bfs_reset, bfs, push, relabel, mincut, finish, and
  * "bytes.<class>": algorithmic bytes of the class over the solve (state words
  * read or written, each access counted once; counted on the device for the
- * data-dependent classes bfs, push and relabel). */
+ * data-dependent classes bfs, push and relabel), and the sizes "volumes",
+ * "columns" and "nodes".  For a batch the counters cover the whole batch
+ * ("sweeps" and "global_relabels" count batch-wide steps). */
 int smf_get_stat(const smf_handle *h, const char *key, int64_t *out);
+
+/* Per-volume values into a host array of n int64.  Counters of the last
+ * batch solve: "sweeps" (sweeps while the volume still had active nodes),
+ * "global_relabels" (searches the volume took part in), "gap_relabels";
+ * settings: "relabel_period" (the period in use) and the shape keys "nx",
+ * "ny", "K", "delta". */
+int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
+
+/* Autotuner of the relabel period (the paper tunes its relabel factor
+ * empirically, Section 3.4).  Volumes fall into classes keyed by
+ * (ceil log2 K, min(delta, 4), floor log2 (nx*ny)).  For every class of the
+ * handle's volumes that the process-wide tuning cache does not hold yet,
+ * the largest volume of that class is solved on a temporary handle with
+ * each candidate period (2, 3, 4, 6, 8, 12, 16, 24), timed on the host
+ * clock, and the fastest period is cached; then every volume of `h` gets
+ * its class's period (smf_batch_set_param).  `packed_cost_dev` and
+ * `offsets_host` are as for smf_batch_solve (a plain handle: the volume,
+ * NULL offsets).  Allocates and frees the temporary handles; work runs on
+ * `stream`.  If the environment variable SMF_TUNE_CACHE names a file, the
+ * cache is loaded from it on first use and saved to it after new timings.
+ * The cache is shared by all host threads (calls serialise on a lock). */
+int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev, const int64_t *offsets_host,
+                 void *stream);
+
+/* Gives every volume of `h` the cached period of its class, without timing
+ * (volumes of unknown classes keep the handle's relabel_period). */
+int smf_tune_apply(smf_handle *h);
+
+/* Adds the entries of a tuning-cache text file (lines "kbits delta pbits
+ * period best_ns") to the cache, or writes the cache to one.  SMF_ERR_ARG
+ * if the file cannot be opened. */
+int smf_tune_cache_load(const char *path);
+int smf_tune_cache_save(const char *path);
+
+/* Empties the tuning cache (and stops it reading SMF_TUNE_CACHE). */
+int smf_tune_cache_clear(void);
+
+/* Cached period for a volume shape (0 if its class is not cached). */
+int smf_tune_lookup(int32_t nx, int32_t ny, int32_t K, int32_t delta, int64_t *period);
 
 /* Backward of the optimal energy with respect to the costs (Section 1.1,
  * Eq. 1): grad_cost[b][x][y][z] = grad_energy[b] if z == surface[b][x][y],

@@ -2,9 +2,10 @@
 
 `SurfaceEnergy.apply(cost, delta)` takes a float32 CUDA tensor of shape
 (B, nx, ny, K), quantises it to int32 costs c_i = round(scale * cost) (torch
-rounds half to even), solves every volume exactly with the C-ABI library and
-returns (E, h): E[b] = sum_p c_i[b](p, h_b(p)) / scale as float32, and the
-pointwise-lowest optimal surface h (int32, not differentiable).
+rounds half to even), solves the B volumes exactly as one batch with the
+C-ABI library (smf_batch_solve) and returns (E, h):
+E[b] = sum_p c_i[b](p, h_b(p)) / scale as float32, and the pointwise-lowest
+optimal surface h (int32, not differentiable).
 
 E is a minimum of functions linear in the costs (Section 1.1, Eq. 1), so its
 gradient is the one-hot indicator of the optimal height of each column
@@ -21,11 +22,11 @@ from . import smf
 _SOLVERS: dict = {}
 
 
-def _solver(nx: int, ny: int, K: int, delta: int) -> smf.Solver:
-    key = (torch.cuda.current_device(), nx, ny, K, delta)
+def _solver(B: int, nx: int, ny: int, K: int, delta: int) -> smf.BatchSolver:
+    key = (torch.cuda.current_device(), B, nx, ny, K, delta)
     s = _SOLVERS.get(key)
     if s is None:
-        s = smf.Solver(nx, ny, K, delta)
+        s = smf.BatchSolver([(nx, ny, K, delta)] * B)
         _SOLVERS[key] = s
     return s
 
@@ -42,14 +43,12 @@ class SurfaceEnergy(torch.autograd.Function):
             raise ValueError("cost must be a (B, nx, ny, K) CUDA tensor")
         B, nx, ny, K = cost.shape
         ci = quantize(cost.detach().float(), scale)
-        solver = _solver(nx, ny, K, int(delta))
+        solver = _solver(B, nx, ny, K, int(delta))
         h = torch.empty((B, nx, ny), dtype=torch.int32, device=cost.device)
-        energies = []
-        for b in range(B):
-            solver.solve(ci[b])
-            solver.surface(out=h[b])
-            energies.append(solver.energy())
-        E = torch.tensor([e / scale for e in energies], dtype=torch.float32, device=cost.device)
+        solver.solve(ci.view(-1))
+        solver.surfaces(out=h.view(-1))
+        E = torch.tensor([e / scale for e in solver.energies()], dtype=torch.float32,
+                         device=cost.device)
         ctx.save_for_backward(h)
         ctx.K = K
         ctx.mark_non_differentiable(h)

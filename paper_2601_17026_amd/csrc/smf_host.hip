@@ -1,17 +1,20 @@
 // Host driver and C-ABI of the exact surface max-flow (include/smf.h).
 //
-// One handle owns the node state of one volume (32 bytes per node, in the
-// caller's [nx][ny][K] layout) plus per-column work lists and BFS records,
-// a small device scratch block and a pinned host mirror of it.
-// smf_solve enqueues the build, the initial global relabel and then sweeps
-// of push and relabel phases on the caller's stream; the host polls the
-// device's active-node counter every `poll_every` sweeps (the only
-// device-to-host traffic of the loop) and runs a global relabel every
-// `relabel_period` sweeps.  Termination: no node with excess and a finite
-// label remains (Section 3.2.4 decides this with flags and locks across
-// threads; here it is one counter written by the relabel phase).
+// A handle owns the node state of a batch of n volumes (n = 1 for the plain
+// entry points): 32 bytes per node, packed volume after volume in each
+// volume's own [nx][ny][K] layout, plus per-column work lists and BFS
+// records, the volume table, per-volume counters and their pinned host
+// mirror.  A solve enqueues the build, the initial global relabel and then
+// sweeps of push and relabel phases on the caller's stream, every launch
+// covering all volumes.  The host polls the per-volume active-node counters
+// every `poll_every` sweeps (the only device-to-host traffic of the loop)
+// and runs a global relabel for the volumes whose relabel period has come
+// round.  Termination: no node with excess and a finite label remains in
+// any volume (Section 3.2.4 decides this with flags and locks across
+// threads; here it is one counter per volume written by the relabel phase).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -22,27 +25,25 @@
 #include "smf_device.h"
 
 namespace smf {
-void launch_init_scratch(Scratch *s, hipStream_t st);
+void launch_init_scratch(const Geom &g, Scratch *s, hipStream_t st);
 void launch_set_int(int *p, int v, hipStream_t st);
-void launch_fill(int *a, int n, int v, hipStream_t st);
+void launch_fill(int *a, long long n, int v, hipStream_t st);
+void launch_zero_field(const Geom &g, int *f0, bool only_part, hipStream_t st);
 void launch_work_init(const Geom &g, const Work &a, const Work &b, hipStream_t st);
 void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st);
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, Scratch *s,
-                     hipStream_t st);
+void launch_bfs_begin(const Geom &g, hipStream_t st);
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *CHin, int *Tout, int *LFout, int *CHout, Scratch *s,
-                      hipStream_t st);
-void launch_bfs_fixup(const Geom &g, const State &sv, int v, hipStream_t st);
+                      const int *CHin, int *Tout, int *LFout, int *CHout, hipStream_t st);
+void launch_bfs_fixup(const Geom &g, const State &sv, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
-void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
-                    hipStream_t st);
+void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st);
 void launch_compact(const Geom &g, const Work &w, hipStream_t st);
-void launch_gap_find(const Geom &g, const State &sv, Scratch *s, hipStream_t st);
+void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
-void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
-                   hipStream_t st);
+void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, hipStream_t st);
 }  // namespace smf
 
 using namespace smf;
@@ -54,6 +55,12 @@ static int fail(int code, const std::string &msg)
     g_last_error = msg;
     return code;
 }
+
+namespace smf {
+// Records the failure of an entry point defined in another source file.
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+void clear_error() { g_last_error.clear(); }
+}  // namespace smf
 
 #define HIP_TRY(call)                                                                     \
     do {                                                                                  \
@@ -135,25 +142,42 @@ struct TimedScope {
     }
 };
 
-constexpr int kHistLen = 4096;      // labels tracked by the gap heuristic (LDS bins)
+constexpr int kHistLen = 4096;            // labels tracked by the gap heuristic (LDS bins)
+constexpr long long kMaxInstNodes = (1LL << 30) - 2;   // finite labels stay below kUnl
 
 struct smf_handle {
     Geom g{};
     int device = 0;
-    int *state = nullptr;      // 8 * N int32
-    int *H = nullptr;          // P int32 surface
-    int *bfs = nullptr;        // 12 * P int32: two per-column BFS records (T, LF[4], changed)
+    int n = 0;
+    std::vector<Inst> inst;       // host copy of the volume table
+    long long max_inst_nodes = 0;
+    // device memory
+    Inst *inst_dev = nullptr;
+    int *col_inst = nullptr;      // Ptot
+    InstScratch *is_dev = nullptr;
+    int *part_dev = nullptr;      // n: volume takes part in the running global relabel
+    int *fill_dev = nullptr;      // n: fixup label of the running global relabel (-1: none)
+    int *state = nullptr;         // 8 * Ntot int32
+    int *H = nullptr;             // Ptot int32 surfaces
+    int *bfs = nullptr;           // 12 * Ptot int32: two per-column BFS records (T, LF[4], changed)
     unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
-    int *hist = nullptr;                  // label histogram (Geom::hist)
-    unsigned long long work_bytes[3] = {};  // their sums after the last solve
-    unsigned long long *wmask = nullptr;  // 2 * P work masks
-    int *wlist = nullptr;                 // 2 * P work-list entries
-    Work work[2]{};            // push reads work[0] and writes work[1]; relabel the reverse
-    Scratch *scr = nullptr;    // device scratch
-    Scratch *host = nullptr;   // pinned mirror
+    int *hist = nullptr;                  // n x kHistLen label histograms (Geom::hist)
+    unsigned long long *wmask = nullptr;  // 2 * Ptot work masks
+    int *wlist = nullptr;                 // 2 * Ptot work-list entries
+    Scratch *scr = nullptr;
+    // pinned host memory; each upload area is rewritten only after a stream
+    // synchronisation that follows its previous upload
+    Scratch *host = nullptr;
+    InstScratch *is_host = nullptr;
+    Inst *inst_up = nullptr;      // volume table upload
+    int *part_up = nullptr;       // n
+    int *fill_up = nullptr;       // n
     State st{};
+    Work work[2]{};               // push reads work[0] and writes work[1]; relabel the reverse
+    unsigned long long work_bytes[3] = {};  // device byte counters after the last solve
     // parameters
     int64_t relabel_period = 6;
+    std::vector<int64_t> inst_period;       // per volume; 0: relabel_period
     int64_t max_sweeps = 2000000;
     int64_t poll_every = 1;
     int64_t bfs_poll_every = 16;
@@ -163,90 +187,155 @@ struct smf_handle {
 
     // results and counters of the last solve
     bool solved = false;
-    int64_t flow = 0, energy = 0;
+    std::vector<int64_t> flow, energy, inst_sweeps, inst_relabels, inst_gap;
     int64_t sweeps = 0, global_relabels = 0, bfs_passes = 0, mincut_passes = 0, gap_relabels = 0;
     int64_t gap_searches = 0;
+    int64_t reset_nodes = 0;       // nodes swept by level-1 passes and fixups
     KernelTimer timer;
 };
 
 static void release(smf_handle *h)
 {
     if (!h) return;
-    if (h->state) (void)hipFree(h->state);
-    if (h->H) (void)hipFree(h->H);
-    if (h->bfs) (void)hipFree(h->bfs);
-    if (h->wcount) (void)hipFree(h->wcount);
-    if (h->hist) (void)hipFree(h->hist);
-    if (h->wmask) (void)hipFree(h->wmask);
-    if (h->wlist) (void)hipFree(h->wlist);
-    if (h->scr) (void)hipFree(h->scr);
-    if (h->host) (void)hipHostFree(h->host);
+    void *dev[] = {h->inst_dev, h->col_inst, h->is_dev, h->part_dev, h->fill_dev, h->state, h->H,
+                   h->bfs, h->wcount, h->hist, h->wmask, h->wlist, h->scr};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    void *pinned[] = {h->host, h->is_host, h->inst_up, h->part_up, h->fill_up};
+    for (void *p : pinned)
+        if (p) (void)hipHostFree(p);
     delete h;
 }
 
-extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t delta)
+template <typename T>
+static bool dev_alloc(T *&p, size_t count)
+{
+    return hipMalloc((void **)&p, sizeof(T) * (count ? count : 1)) == hipSuccess;
+}
+
+template <typename T>
+static bool host_alloc(T *&p, size_t count)
+{
+    return hipHostMalloc((void **)&p, sizeof(T) * (count ? count : 1), hipHostMallocDefault) == hipSuccess;
+}
+
+extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int32_t *ny,
+                                        const int32_t *K, const int32_t *delta)
 {
     g_last_error.clear();
-    if (nx < 1 || ny < 1 || K < 1 || delta < 0) {
-        fail(SMF_ERR_ARG, "smf_create: need nx, ny, K >= 1 and delta >= 0");
+    if (n < 1 || !nx || !ny || !K || !delta) {
+        fail(SMF_ERR_ARG, "smf_batch_create: need n >= 1 and non-NULL shape arrays");
         return nullptr;
     }
-    long long N = (long long)nx * ny * K;
-    if (N >= (1LL << 31) || 4 * N >= (1LL << 62)) {
-        fail(SMF_ERR_RANGE, "smf_create: nx*ny*K must be below 2^31");
-        return nullptr;
+    std::vector<Inst> inst((size_t)n);
+    long long Ptot = 0, Ntot = 0, max_nodes = 0;
+    for (int i = 0; i < n; ++i) {
+        if (nx[i] < 1 || ny[i] < 1 || K[i] < 1 || delta[i] < 0) {
+            fail(SMF_ERR_ARG, "smf_batch_create: volume " + std::to_string(i) +
+                                  " needs nx, ny, K >= 1 and delta >= 0");
+            return nullptr;
+        }
+        const long long P = (long long)nx[i] * ny[i];
+        const long long N = P * K[i];
+        if (N > kMaxInstNodes) {
+            fail(SMF_ERR_RANGE, "smf_batch_create: volume " + std::to_string(i) +
+                                    " has nx*ny*K above 2^30 - 2");
+            return nullptr;
+        }
+        Inst &I = inst[i];
+        I.nx = nx[i]; I.ny = ny[i]; I.K = K[i]; I.delta = delta[i];
+        I.P = (int)P;
+        I.nch = (K[i] + kWave - 1) / kWave;
+        I.cpb = (I.nch + 63) / 64;
+        I.lab_cap = (int)(N + 1);
+        I.col_base = (int)Ptot;
+        I.pad0 = 0;
+        I.node_base = Ntot;
+        I.cost_base = Ntot;
+        I.N = N;
+        Ptot += P;
+        Ntot += N;
+        max_nodes = std::max(max_nodes, N);
+        if (Ptot >= (1LL << 31)) {
+            fail(SMF_ERR_RANGE, "smf_batch_create: more than 2^31 - 1 columns in the batch");
+            return nullptr;
+        }
     }
     smf_handle *h = new (std::nothrow) smf_handle;
     if (!h) {
-        fail(SMF_ERR_NOMEM, "smf_create: host allocation failed");
+        fail(SMF_ERR_NOMEM, "smf_batch_create: host allocation failed");
         return nullptr;
     }
-    h->g.nx = nx; h->g.ny = ny; h->g.K = K; h->g.delta = delta;
-    h->g.P = nx * ny;
-    h->g.N = (int)N;
-    h->g.lab_cap = N + 1 < kInf ? (int)(N + 1) : kInf;
-    h->g.nch = (K + kWave - 1) / kWave;
-    h->g.cpb = (h->g.nch + 63) / 64;
-    if (hipGetDevice(&h->device) != hipSuccess ||
-        hipMalloc((void **)&h->state, sizeof(int) * 8 * (size_t)N) != hipSuccess ||
-        hipMalloc((void **)&h->H, sizeof(int) * (size_t)h->g.P) != hipSuccess ||
-        hipMalloc((void **)&h->bfs, sizeof(int) * 12 * (size_t)h->g.P) != hipSuccess ||
-        hipMalloc((void **)&h->wcount, sizeof(unsigned long long) * 3 * kWorkSlots * kWorkStride) != hipSuccess ||
-        hipMalloc((void **)&h->hist, sizeof(int) * kHistLen) != hipSuccess ||
-        hipMalloc((void **)&h->wmask, sizeof(unsigned long long) * 2 * (size_t)h->g.P) != hipSuccess ||
-        hipMalloc((void **)&h->wlist, sizeof(int) * 2 * (size_t)h->g.P) != hipSuccess ||
-        hipMalloc((void **)&h->scr, sizeof(Scratch)) != hipSuccess ||
-        hipHostMalloc((void **)&h->host, sizeof(Scratch), hipHostMallocDefault) != hipSuccess) {
+    h->n = n;
+    h->inst = inst;
+    h->max_inst_nodes = max_nodes;
+    h->inst_period.assign((size_t)n, 0);
+    const size_t P = (size_t)Ptot, N = (size_t)Ntot;
+    if (hipGetDevice(&h->device) != hipSuccess || !dev_alloc(h->inst_dev, n) ||
+        !dev_alloc(h->col_inst, P) || !dev_alloc(h->is_dev, n) || !dev_alloc(h->part_dev, n) ||
+        !dev_alloc(h->fill_dev, n) || !dev_alloc(h->state, 8 * N) || !dev_alloc(h->H, P) ||
+        !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->wcount, 3 * kWorkSlots * kWorkStride) ||
+        !dev_alloc(h->hist, (size_t)n * kHistLen) || !dev_alloc(h->wmask, 2 * P) ||
+        !dev_alloc(h->wlist, 2 * P) || !dev_alloc(h->scr, 1) || !host_alloc(h->host, 1) ||
+        !host_alloc(h->is_host, n) || !host_alloc(h->inst_up, n) || !host_alloc(h->part_up, n) ||
+        !host_alloc(h->fill_up, n)) {
         (void)hipGetLastError();
         release(h);
-        fail(SMF_ERR_NOMEM, "smf_create: device allocation of " +
-                                std::to_string(32.0 * N / (1 << 20)) + " MiB failed");
+        fail(SMF_ERR_NOMEM, "smf_batch_create: device allocation of " +
+                                std::to_string(32.0 * (double)Ntot / (1 << 20)) + " MiB failed");
         return nullptr;
     }
-    h->g.work = h->wcount;
-    h->g.hist = h->hist;
-    h->g.hist_len = kHistLen;
+    // the volume table and the column -> volume map are uploaded once
+    std::vector<int> ci(P);
+    for (int i = 0; i < n; ++i)
+        std::fill(ci.begin() + inst[i].col_base, ci.begin() + inst[i].col_base + inst[i].P, i);
+    if (hipMemcpy(h->inst_dev, inst.data(), sizeof(Inst) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->col_inst, ci.data(), sizeof(int) * P, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        release(h);
+        fail(SMF_ERR_HIP, "smf_batch_create: upload of the volume table failed");
+        return nullptr;
+    }
+    Geom &g = h->g;
+    g.n = n;
+    g.Ptot = (int)Ptot;
+    g.Ntot = Ntot;
+    g.inst = h->inst_dev;
+    g.col_inst = h->col_inst;
+    g.is = h->is_dev;
+    g.part = h->part_dev;
+    g.fill = h->fill_dev;
+    g.count_work = 0;
+    g.work = h->wcount;
+    g.hist = h->hist;
+    g.hist_len = kHistLen;
     int *b = h->state;
-    size_t n = (size_t)N;
     h->st.e = b;
-    h->st.d = b + n;
-    h->st.ts = b + 2 * n;
-    h->st.fd = b + 3 * n;
-    h->st.fl = b + 4 * n;
+    h->st.d = b + N;
+    h->st.ts = b + 2 * N;
+    h->st.fd = b + 3 * N;
+    h->st.fl = b + 4 * N;
     for (int i = 0; i < 2; ++i) {
-        h->work[i].mask = h->wmask + (size_t)i * h->g.P;
-        h->work[i].list = h->wlist + (size_t)i * h->g.P;
+        h->work[i].mask = h->wmask + (size_t)i * P;
+        h->work[i].list = h->wlist + (size_t)i * P;
         h->work[i].count = &h->scr->count[i];
     }
     return h;
 }
 
+extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t delta)
+{
+    return smf_batch_create(1, &nx, &ny, &K, &delta);
+}
+
 extern "C" void smf_destroy(smf_handle *h) { release(h); }
 
-// Copies the scratch block to the pinned mirror and waits for the stream.
+// Copies the batch-wide and per-volume counters to the pinned mirrors and
+// waits for the stream.
 static int sync_scratch(smf_handle *h, hipStream_t s)
 {
     HIP_TRY(hipMemcpyAsync(h->host, h->scr, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->is_host, h->is_dev, sizeof(InstScratch) * h->n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     h->timer.collect();
     if (h->host->err & kErrCostRange)
@@ -256,74 +345,108 @@ static int sync_scratch(smf_handle *h, hipStream_t s)
     return SMF_OK;
 }
 
-// Global relabel: level 1 from the sink arcs, then one launch per BFS level
-// until a level labels nothing (exact distances; unreached nodes get kInf)
-// or, with bfs_early_stop, until every node that holds excess is labelled
-// (unreached nodes then get the first unfinished level, a valid lower
-// bound).  The host checks every bfs_poll_every levels; levels launched
-// after the last productive one are no-ops.
-static int global_relabel(smf_handle *h, hipStream_t s)
+// Global relabel of the volumes with part[i]: level 1 from the sink arcs,
+// then one launch per BFS level (covering every taking-part volume) until
+// each of them has either run to completion -- a level labelled nothing:
+// exact distances, unreached nodes get kInf -- or, with bfs_early_stop, has
+// labelled every node that holds excess (unreached nodes then get the first
+// unfinished level, a valid lower bound).  The host checks every
+// bfs_poll_every levels; levels launched after a volume's last productive
+// one are no-ops for it.
+static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> &part)
 {
-    const int P = h->g.P;
-    int *T[2] = {h->bfs, h->bfs + 5 * (size_t)P};
-    int *LF[2] = {h->bfs + P, h->bfs + 6 * (size_t)P};
-    int *CH[2] = {h->bfs + 10 * (size_t)P, h->bfs + 11 * (size_t)P};
-    launch_set_int(&h->scr->bfs_active, 0, s);
-    launch_set_int(&h->scr->bfs_labelled, 0, s);
-    launch_set_int(&h->scr->gap, kInf, s);
+    const int n = h->n;
+    const size_t P = (size_t)h->g.Ptot;
+    int *T[2] = {h->bfs, h->bfs + 5 * P};
+    int *LF[2] = {h->bfs + P, h->bfs + 6 * P};
+    int *CH[2] = {h->bfs + 10 * P, h->bfs + 11 * P};
+    for (int i = 0; i < n; ++i) {
+        h->part_up[i] = part[i] ? 1 : 0;
+        if (part[i]) h->reset_nodes += h->inst[i].N;
+    }
+    HIP_TRY(hipMemcpyAsync(h->part_dev, h->part_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
+    launch_bfs_begin(h->g, s);
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], h->scr, s);   // level 1 lives in buffer 1
+        launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], s);   // level 1 lives in buffer 1
     }
     int L = 1;
-    int fill = kInf;
     for (;;) {
         {
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
             for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L) {
                 launch_bfs_level(h->g, h->st, L, T[L & 1], LF[L & 1], CH[L & 1], T[(L + 1) & 1],
-                                 LF[(L + 1) & 1], CH[(L + 1) & 1], h->scr, s);
+                                 LF[(L + 1) & 1], CH[(L + 1) & 1], s);
                 h->bfs_passes++;
             }
         }
         HIP_TRY(hipGetLastError());
         int rc = sync_scratch(h, s);
         if (rc) return rc;
-        if (!h->host->lvl_changed[(L - 1) & 63]) break;   // the last level launched
-        if (h->bfs_early_stop && h->host->bfs_labelled >= h->host->bfs_active) {
-            fill = L + 1;   // levels <= L are complete
+        // the last level launched produced level L
+        bool all = true;
+        for (int i = 0; i < n && all; ++i) {
+            if (!part[i]) continue;
+            const InstScratch &r = h->is_host[i];
+            const bool complete = !r.lvl_changed[(L - 1) % kLvlSlots];
+            const bool labelled = h->bfs_early_stop && r.bfs_labelled >= r.bfs_active;
+            all = complete || labelled;
+        }
+        if (all) {
+            for (int i = 0; i < n; ++i) {
+                const bool complete = !h->is_host[i].lvl_changed[(L - 1) % kLvlSlots];
+                h->fill_up[i] = !part[i] ? -1 : (complete ? kInf : L + 1);
+            }
             break;
         }
         // every productive level lowers at least one threshold by >= 1
-        if ((int64_t)L > (int64_t)h->g.N + 2 + h->bfs_poll_every)
+        if ((int64_t)L > h->max_inst_nodes + 2 + h->bfs_poll_every)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: breadth-first search did not settle");
     }
+    HIP_TRY(hipMemcpyAsync(h->fill_dev, h->fill_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_fixup(h->g, h->st, fill, s);
+        launch_bfs_fixup(h->g, h->st, s);
     }
-    if (h->verbose)
-        fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d levels, active %d, labelled %d, %s\n",
-                (long long)h->global_relabels, (long long)h->sweeps, L - 1, h->host->bfs_active,
-                h->host->bfs_labelled, fill == kInf ? "complete" : "early stop");
+    if (h->verbose) {
+        int npart = 0, act = 0, lab = 0;
+        for (int i = 0; i < n; ++i)
+            if (part[i]) { ++npart; act += h->is_host[i].bfs_active; lab += h->is_host[i].bfs_labelled; }
+        fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d volumes, %d levels, active %d, labelled %d\n",
+                (long long)h->global_relabels, (long long)h->sweeps, npart, L - 1, act, lab);
+    }
+    for (int i = 0; i < n; ++i)
+        if (part[i]) h->inst_relabels[i]++;
     h->global_relabels++;
     return SMF_OK;
 }
 
-extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
+// Solve of every volume of the batch; costs of volume i start at
+// cost_dev + off[i].
+static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *off, hipStream_t s)
 {
-    g_last_error.clear();
-    if (!h || !cost_dev) return fail(SMF_ERR_ARG, "smf_solve: NULL handle or cost");
-    hipStream_t s = (hipStream_t)stream;
+    const int n = h->n;
     h->solved = false;
     h->sweeps = h->global_relabels = h->bfs_passes = h->mincut_passes = h->gap_relabels = 0;
-    h->gap_searches = 0;
+    h->gap_searches = h->reset_nodes = 0;
+    h->flow.assign(n, 0);
+    h->energy.assign(n, 0);
+    h->inst_sweeps.assign(n, 0);
+    h->inst_relabels.assign(n, 0);
+    h->inst_gap.assign(n, 0);
     HIP_TRY(hipSetDevice(h->device));
+
+    // volume table with this call's cost offsets
+    for (int i = 0; i < n; ++i) {
+        h->inst_up[i] = h->inst[i];
+        h->inst_up[i].cost_base = off ? off[i] : h->inst[i].node_base;
+    }
+    HIP_TRY(hipMemcpyAsync(h->inst_dev, h->inst_up, sizeof(Inst) * n, hipMemcpyHostToDevice, s));
 
     h->timer.reset();
     if (h->g.count_work)
-        launch_fill((int *)h->wcount, 2 * 3 * kWorkSlots * kWorkStride, 0, s);
-    launch_init_scratch(h->scr, s);
+        launch_fill((int *)h->wcount, 2LL * 3 * kWorkSlots * kWorkStride, 0, s);
+    launch_init_scratch(h->g, h->scr, s);
     {
         TimedScope ts(h->timer, KC_BUILD, s);
         launch_build(cost_dev, h->g, h->st, h->scr, s);
@@ -331,19 +454,28 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     HIP_TRY(hipGetLastError());
     int rc = sync_scratch(h, s);
     if (rc) return rc;
-    rc = global_relabel(h, s);
+    std::vector<char> all((size_t)n, 1), part((size_t)n, 0), done((size_t)n, 0);
+    rc = global_relabel(h, s, all);
     if (rc) return rc;
 
+    std::vector<int64_t> since((size_t)n, 0), period((size_t)n);
+    for (int i = 0; i < n; ++i) period[i] = h->inst_period[i] > 0 ? h->inst_period[i] : h->relabel_period;
     // work lists: every column may hold excess anywhere before the first sweep
     launch_work_init(h->g, h->work[0], h->work[1], s);
-    bool done = false;
-    while (!done) {
+    for (;;) {
         if (h->sweeps >= h->max_sweeps)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: sweep cap reached");
-        for (int64_t i = 0; i < h->poll_every; ++i) {
-            if (h->sweeps > 0 && h->sweeps % h->relabel_period == 0) {
-                rc = global_relabel(h, s);
+        for (int64_t it = 0; it < h->poll_every; ++it) {
+            bool any = false;
+            for (int i = 0; i < n; ++i) {
+                part[i] = !done[i] && since[i] >= period[i];
+                any = any || part[i];
+            }
+            if (any) {
+                rc = global_relabel(h, s, part);
                 if (rc) return rc;
+                for (int i = 0; i < n; ++i)
+                    if (part[i]) since[i] = 0;
             }
             launch_set_int(h->work[1].count, 0, s);
             {
@@ -352,23 +484,33 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
             }
             launch_compact(h->g, h->work[1], s);
             launch_set_int(h->work[0].count, 0, s);
-            launch_set_int(&h->scr->active, 0, s);
+            launch_zero_field(h->g, &h->is_dev[0].active, false, s);
             {
                 TimedScope ts(h->timer, KC_RELABEL, s);
-                launch_relabel(h->g, h->st, h->work[1], h->work[0], h->scr, s);
+                launch_relabel(h->g, h->st, h->work[1], h->work[0], s);
             }
             h->sweeps++;
+            for (int i = 0; i < n; ++i)
+                if (!done[i]) { since[i]++; h->inst_sweeps[i]++; }
             if (h->gap_every > 0 && h->sweeps % h->gap_every == 0) {
-                launch_gap_find(h->g, h->st, h->scr, s);
+                launch_gap_find(h->g, h->st, h->max_inst_nodes, s);
                 h->gap_searches++;
             }
         }
         HIP_TRY(hipGetLastError());
         rc = sync_scratch(h, s);
         if (rc) return rc;
-        done = h->host->active == 0;
-        if (h->verbose) fprintf(stderr, "smf: sweep %lld active %d columns %d\n", (long long)h->sweeps,
-                                h->host->active, h->host->count[0]);
+        bool finished = true;
+        int left = 0;
+        for (int i = 0; i < n; ++i) {
+            done[i] = h->is_host[i].active == 0;
+            finished = finished && done[i];
+            left += h->is_host[i].active;
+        }
+        if (h->verbose)
+            fprintf(stderr, "smf: sweep %lld active %d columns %d\n", (long long)h->sweeps, left,
+                    h->host->count[0]);
+        if (finished) break;
     }
 
     {
@@ -385,19 +527,22 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
         rc = sync_scratch(h, s);
         if (rc) return rc;
         if (!h->host->changed) break;
-        if (h->mincut_passes > (int64_t)h->g.N + 2)
+        if (h->mincut_passes > h->max_inst_nodes + 2)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: minimum-cut search did not settle");
     }
     {
         TimedScope ts(h->timer, KC_FINISH, s);
-        launch_finish(cost_dev, h->g, h->st, h->H, h->scr, s);
+        launch_finish(cost_dev, h->g, h->st, h->H, s);
     }
     HIP_TRY(hipGetLastError());
     rc = sync_scratch(h, s);
     if (rc) return rc;
-    h->flow = h->host->flow;
-    h->energy = h->host->energy;
-    h->gap_relabels = h->host->gap_frozen;
+    for (int i = 0; i < n; ++i) {
+        h->flow[i] = h->is_host[i].flow;
+        h->energy[i] = h->is_host[i].energy;
+        h->inst_gap[i] = h->is_host[i].gap_frozen;
+        h->gap_relabels += h->is_host[i].gap_frozen;
+    }
     if (h->g.count_work) {
         unsigned long long w[3 * kWorkSlots * kWorkStride];
         HIP_TRY(hipMemcpyAsync(w, h->wcount, sizeof(w), hipMemcpyDeviceToHost, s));
@@ -413,29 +558,78 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
     return SMF_OK;
 }
 
+extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
+{
+    g_last_error.clear();
+    if (!h || !cost_dev) return fail(SMF_ERR_ARG, "smf_solve: NULL handle or cost");
+    if (h->n != 1) return fail(SMF_ERR_ARG, "smf_solve: the handle holds a batch; use smf_batch_solve");
+    return solve_batch(h, cost_dev, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int smf_batch_solve(smf_handle *h, const int32_t *packed_cost_dev,
+                               const int64_t *offsets_host, void *stream)
+{
+    g_last_error.clear();
+    if (!h || !packed_cost_dev) return fail(SMF_ERR_ARG, "smf_batch_solve: NULL handle or cost");
+    if (offsets_host)
+        for (int i = 0; i < h->n; ++i)
+            if (offsets_host[i] < 0)
+                return fail(SMF_ERR_ARG, "smf_batch_solve: negative cost offset");
+    return solve_batch(h, packed_cost_dev, offsets_host, (hipStream_t)stream);
+}
+
 extern "C" int smf_flow_value(const smf_handle *h, int64_t *out)
 {
     if (!h || !out) return fail(SMF_ERR_ARG, "smf_flow_value: NULL argument");
+    if (h->n != 1) return fail(SMF_ERR_ARG, "smf_flow_value: the handle holds a batch");
     if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_flow_value: no successful solve");
-    *out = h->flow;
+    *out = h->flow[0];
     return SMF_OK;
 }
 
 extern "C" int smf_energy(const smf_handle *h, int64_t *out)
 {
     if (!h || !out) return fail(SMF_ERR_ARG, "smf_energy: NULL argument");
+    if (h->n != 1) return fail(SMF_ERR_ARG, "smf_energy: the handle holds a batch");
     if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_energy: no successful solve");
-    *out = h->energy;
+    *out = h->energy[0];
+    return SMF_OK;
+}
+
+extern "C" int smf_batch_flow_values(const smf_handle *h, int64_t *out)
+{
+    if (!h || !out) return fail(SMF_ERR_ARG, "smf_batch_flow_values: NULL argument");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_batch_flow_values: no successful solve");
+    std::copy(h->flow.begin(), h->flow.end(), out);
+    return SMF_OK;
+}
+
+extern "C" int smf_batch_energies(const smf_handle *h, int64_t *out)
+{
+    if (!h || !out) return fail(SMF_ERR_ARG, "smf_batch_energies: NULL argument");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_batch_energies: no successful solve");
+    std::copy(h->energy.begin(), h->energy.end(), out);
+    return SMF_OK;
+}
+
+static int copy_surfaces(const smf_handle *h, int32_t *out_dev, void *stream, const char *who)
+{
+    if (!h || !out_dev) return fail(SMF_ERR_ARG, std::string(who) + ": NULL argument");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, std::string(who) + ": no successful solve");
+    HIP_TRY(hipMemcpyAsync(out_dev, h->H, sizeof(int) * (size_t)h->g.Ptot, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
     return SMF_OK;
 }
 
 extern "C" int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream)
 {
-    if (!h || !out_dev) return fail(SMF_ERR_ARG, "smf_surface: NULL argument");
-    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_surface: no successful solve");
-    HIP_TRY(hipMemcpyAsync(out_dev, h->H, sizeof(int) * (size_t)h->g.P, hipMemcpyDeviceToDevice,
-                           (hipStream_t)stream));
-    return SMF_OK;
+    if (h && h->n != 1) return fail(SMF_ERR_ARG, "smf_surface: the handle holds a batch");
+    return copy_surfaces(h, out_dev, stream, "smf_surface");
+}
+
+extern "C" int smf_batch_surfaces(const smf_handle *h, int32_t *packed_out_dev, void *stream)
+{
+    return copy_surfaces(h, packed_out_dev, stream, "smf_batch_surfaces");
 }
 
 extern "C" int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res_dev,
@@ -444,8 +638,8 @@ extern "C" int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_
     if (!h || !excess_dev || !sink_res_dev || !flow_down_dev || !flow_lat_dev)
         return fail(SMF_ERR_ARG, "smf_export_state: NULL argument");
     if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_export_state: no successful solve");
-    // the state already has the caller's [nx][ny][K] layout
-    const size_t n = sizeof(int) * (size_t)h->g.N;
+    // the state already has the caller's packed [nx][ny][K] layout
+    const size_t n = sizeof(int) * (size_t)h->g.Ntot;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(excess_dev, h->st.e, n, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(sink_res_dev, h->st.ts, n, hipMemcpyDeviceToDevice, s));
@@ -458,10 +652,20 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
 {
     if (!h || !key) return fail(SMF_ERR_ARG, "smf_set_param: NULL argument");
     int64_t *slot = nullptr;
-    if (!strcmp(key, "relabel_period")) slot = &h->relabel_period;
+    if (!strcmp(key, "relabel_period")) {
+        if (value < 1) return fail(SMF_ERR_ARG, "smf_set_param: relabel_period must be >= 1");
+        h->relabel_period = value;
+        std::fill(h->inst_period.begin(), h->inst_period.end(), 0);
+        return SMF_OK;
+    }
     else if (!strcmp(key, "max_sweeps")) slot = &h->max_sweeps;
     else if (!strcmp(key, "poll_every")) slot = &h->poll_every;
-    else if (!strcmp(key, "bfs_poll_every")) slot = &h->bfs_poll_every;
+    else if (!strcmp(key, "bfs_poll_every")) {
+        if (value < 1 || value > kLvlSlots - 2)
+            return fail(SMF_ERR_ARG, "smf_set_param: bfs_poll_every must lie in [1, 62]");
+        h->bfs_poll_every = value;
+        return SMF_OK;
+    }
     else if (!strcmp(key, "gap_every")) {
         if (value < 0) return fail(SMF_ERR_ARG, "smf_set_param: gap_every must be >= 0");
         h->gap_every = value;
@@ -494,6 +698,18 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     return SMF_OK;
 }
 
+extern "C" int smf_batch_set_param(smf_handle *h, const char *key, const int64_t *values)
+{
+    if (!h || !key || !values) return fail(SMF_ERR_ARG, "smf_batch_set_param: NULL argument");
+    if (strcmp(key, "relabel_period"))
+        return fail(SMF_ERR_ARG, std::string("smf_batch_set_param: unknown key ") + key);
+    for (int i = 0; i < h->n; ++i)
+        if (values[i] < 0)
+            return fail(SMF_ERR_ARG, "smf_batch_set_param: relabel_period must be >= 0");
+    std::copy(values, values + h->n, h->inst_period.begin());
+    return SMF_OK;
+}
+
 extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
 {
     if (!h || !key || !out) return fail(SMF_ERR_ARG, "smf_get_stat: NULL argument");
@@ -503,16 +719,19 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
     else if (!strcmp(key, "mincut_passes")) *out = h->mincut_passes;
     else if (!strcmp(key, "gap_relabels")) *out = h->gap_relabels;
     else if (!strcmp(key, "gap_searches")) *out = h->gap_searches;
+    else if (!strcmp(key, "volumes")) *out = h->n;
+    else if (!strcmp(key, "columns")) *out = h->g.Ptot;
+    else if (!strcmp(key, "nodes")) *out = h->g.Ntot;
     else if (!strncmp(key, "bytes.", 6)) {
         // algorithmic bytes of the last solve per kernel class: counted on the
         // device for the data-dependent kernels, by formula for the others
         const char *name = key + 6;
-        const int64_t N = h->g.N, P = h->g.P;
+        const int64_t N = h->g.Ntot, P = h->g.Ptot;
         if (!strcmp(name, "bfs")) *out = (int64_t)h->work_bytes[0];
         else if (!strcmp(name, "push")) *out = (int64_t)h->work_bytes[1];
         else if (!strcmp(name, "relabel")) *out = (int64_t)h->work_bytes[2];
         else if (!strcmp(name, "build")) *out = 36 * N + 4 * P;
-        else if (!strcmp(name, "bfs_reset")) *out = h->global_relabels * (32 * N + 4 * N);
+        else if (!strcmp(name, "bfs_reset")) *out = 36 * h->reset_nodes;
         else if (!strcmp(name, "finish")) *out = 4 * N + 8 * P;
         else if (!strcmp(name, "mincut")) *out = 4 * N + h->mincut_passes * 24 * P;
         else return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown kernel class in ") + key);
@@ -527,6 +746,30 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
         *out = t ? (int64_t)h->timer.ns[kc] : h->timer.launches[kc];
     }
     else return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown key ") + key);
+    return SMF_OK;
+}
+
+extern "C" int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out)
+{
+    if (!h || !key || !out) return fail(SMF_ERR_ARG, "smf_batch_get_stat: NULL argument");
+    const std::vector<int64_t> *src = nullptr;
+    if (!strcmp(key, "relabel_period")) {
+        for (int i = 0; i < h->n; ++i) out[i] = h->inst_period[i] > 0 ? h->inst_period[i] : h->relabel_period;
+        return SMF_OK;
+    }
+    if (!strcmp(key, "nx") || !strcmp(key, "ny") || !strcmp(key, "K") || !strcmp(key, "delta")) {
+        for (int i = 0; i < h->n; ++i) {
+            const Inst &I = h->inst[i];
+            out[i] = key[0] == 'n' ? (key[1] == 'x' ? I.nx : I.ny) : (key[0] == 'K' ? I.K : I.delta);
+        }
+        return SMF_OK;
+    }
+    if (!strcmp(key, "sweeps")) src = &h->inst_sweeps;
+    else if (!strcmp(key, "global_relabels")) src = &h->inst_relabels;
+    else if (!strcmp(key, "gap_relabels")) src = &h->inst_gap;
+    else return fail(SMF_ERR_ARG, std::string("smf_batch_get_stat: unknown key ") + key);
+    if (src->size() != (size_t)h->n) return fail(SMF_ERR_NOT_SOLVED, "smf_batch_get_stat: no solve yet");
+    std::copy(src->begin(), src->end(), out);
     return SMF_OK;
 }
 

@@ -8,6 +8,11 @@
 // no edge lists, only per-node excess, label, sink residual and the flows of
 // the five outgoing infinite arcs.
 //
+// Batches.  Every kernel works on all volumes of a batch at once: columns
+// are numbered across the batch, each column finds its volume's geometry in
+// the volume table, and counters are kept per volume.  No arc joins two
+// volumes, so the volumes' solves only share launches.
+//
 // Labels.  A valid labelling satisfies d(u) <= d(w) + len(u, w) for every
 // residual arc, with len = 0 for the always-residual down arcs
 // (p,z) -> (p,z-1) and len = 1 for every other arc (sink arcs included,
@@ -32,13 +37,17 @@ namespace smf {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// A value every lane holds alike, moved to a scalar register so that the
+// addresses computed from it use scalar loads.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ int wave_sum(int v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
 
-__device__ __forceinline__ long long wave_sum64(long long v)
+__device__ __forceinline__ long long wave_sum(long long v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
@@ -71,21 +80,72 @@ __device__ __forceinline__ long long shfl64_up(long long v, int off)
     return ((long long)hi << 32) | (unsigned int)lo;
 }
 
+// Field `f` of the counters of volume i, given the same field of volume 0.
+template <typename T>
+__device__ __forceinline__ T *inst_field(T *f0, int i)
+{
+    return (T *)((char *)f0 + (size_t)i * sizeof(InstScratch));
+}
+
+__device__ __forceinline__ void atomic_add(int *p, int v) { atomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(long long *p, long long v)
+{
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);   // two's complement
+}
+
+// Adds `val` of every lane with `has` to field f0 of the lane's volume
+// `key`: one atomic per distinct volume among the lanes (the lanes of a
+// wave nearly always share one).  Called by all lanes of the wave.
+template <typename T>
+__device__ __forceinline__ void wave_add_keyed(T *f0, int key, T val, bool has)
+{
+    const int lane = lane_id();
+    bool pending = has && val != 0;
+    for (;;) {
+        const unsigned long long b = __ballot(pending);
+        if (!b) break;
+        const int leader = __ffsll((long long)b) - 1;
+        const int k = __shfl(key, leader, kWave);
+        const bool mine = pending && key == k;
+        const T s = wave_sum(mine ? val : (T)0);
+        if (lane == leader) atomic_add(inst_field(f0, k), s);
+        if (mine) pending = false;
+    }
+}
+
+// Running per-volume sum of a wave that visits columns in order: the lanes'
+// partial sums are flushed with one atomic whenever the volume changes.
+template <typename T>
+struct VolSum {
+    T *f0;
+    int cur = -1;
+    T acc = 0;
+    __device__ explicit VolSum(T *f) : f0(f) {}
+    // `ii` is wave-uniform
+    __device__ void to(int ii)
+    {
+        if (ii == cur) return;
+        flush();
+        cur = ii;
+    }
+    __device__ void flush()
+    {
+        if (cur >= 0) {
+            const T s = wave_sum(acc);
+            if (lane_id() == 0 && s) atomic_add(inst_field(f0, cur), s);
+        }
+        acc = 0;
+    }
+};
+
 // Adds a wave's algorithmic bytes (state words read or written, each access
 // counted once) to the solve counter of kernel class `cls`.
 __device__ __forceinline__ void count_bytes(const Geom &g, int cls, long long lane_bytes)
 {
-    const long long b = wave_sum64(lane_bytes);
+    const long long b = wave_sum(lane_bytes);
     if ((threadIdx.x & (kWave - 1)) == 0 && b)
         atomicAdd(g.work + ((size_t)cls * kWorkSlots + (blockIdx.x & (kWorkSlots - 1))) * kWorkStride,
                   (unsigned long long)b);
-}
-
-__device__ __forceinline__ void add_excess(int *e, size_t w, long long a, int &err)
-{
-    if (a > INT_MAX) { err = 1; a = INT_MAX; }
-    int old = atomicAdd(e + w, (int)a);
-    if ((long long)old + a > INT_MAX) err = 1;
 }
 
 __device__ __forceinline__ int add_flow(int f, long long a, int &err)
@@ -93,6 +153,45 @@ __device__ __forceinline__ int add_flow(int f, long long a, int &err)
     long long r = (long long)f + a;
     if (r > INT_MAX) { err = 1; r = INT_MAX; }
     return (int)r;
+}
+
+// Contiguous share [lo, hi) of the global columns for the wave-per-column
+// kernels, so that a wave meets few volume boundaries.
+__device__ __forceinline__ void wave_columns(const Geom &g, int &lo, int &hi)
+{
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    const int per = (g.Ptot + nwaves - 1) / nwaves;
+    lo = min(g.Ptot, wave * per);
+    hi = min(g.Ptot, lo + per);
+}
+
+// Geometry of the column's volume, with the column's local coordinates.
+struct Col {
+    Inst I;
+    int ii;        // volume
+    int pl, x, y;  // local column and its coordinates
+    size_t base;   // global node of (p, 0)
+};
+
+__device__ __forceinline__ Col column_of(const Geom &g, int p, int ii)
+{
+    Col c;
+    c.ii = ii;
+    c.I = g.inst[ii];
+    c.pl = p - c.I.col_base;
+    c.x = c.pl / c.I.ny;
+    c.y = c.pl - c.x * c.I.ny;
+    c.base = (size_t)c.I.node_base + (size_t)c.pl * c.I.K;
+    return c;
+}
+
+__device__ __forceinline__ Col column(const Geom &g, int p) { return column_of(g, p, g.col_inst[p]); }
+
+// Same for a wave-uniform column: the volume table is read with scalar loads.
+__device__ __forceinline__ Col column_uniform(const Geom &g, int p)
+{
+    return column_of(g, p, uniform(g.col_inst[p]));
 }
 
 // ---- carries along a column as a scan of clamp functions --------------------
@@ -147,102 +246,177 @@ __device__ __forceinline__ Clamp shfl_clamp(const Clamp &f, int src)
 //
 // With labels that drop by at most one along a residual arc (len <= 1), a
 // label g held by no node cuts every node labelled above g off from t
-// (Section 2.1, gap relabelling).  The histogram of the finite labels below
-// hist_len is rebuilt from all nodes whenever a gap search runs.
+// (Section 2.1, gap relabelling).  The histogram of each volume's finite
+// labels below hist_len is rebuilt from all its nodes whenever a gap search
+// runs.
 
-// Per-block histogram in LDS, flushed to the global one.
+// Per-block histogram in LDS, flushed to the volume's global one; blockIdx.y
+// is the volume.
 __global__ __launch_bounds__(256) void k_hist_build(Geom g, const int *__restrict__ d)
 {
     extern __shared__ int bins[];
+    const int ii = blockIdx.y;
+    const Inst I = g.inst[ii];
     const int len = g.hist_len;
     for (int i = threadIdx.x; i < len; i += blockDim.x) bins[i] = 0;
     __syncthreads();
-    const int stride = gridDim.x * blockDim.x;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.N; v += stride) {
-        const int l = d[v];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const int *dv = d + I.node_base;
+    for (long long v = blockIdx.x * blockDim.x + threadIdx.x; v < I.N; v += stride) {
+        const int l = dv[v];
         if (l >= 1 && l < len) atomicAdd(&bins[l], 1);
     }
     __syncthreads();
+    int *h = g.hist + (size_t)ii * len;
     for (int i = threadIdx.x; i < len; i += blockDim.x)
-        if (bins[i]) atomicAdd(g.hist + i, bins[i]);
+        if (bins[i]) atomicAdd(h + i, bins[i]);
+}
+
+// First label >= 1 held by no node while some node holds a larger label
+// (kInf if none): one block per volume scans its histogram.
+__global__ __launch_bounds__(1024) void k_gap_find(Geom g)
+{
+    __shared__ int first_zero, last_used;
+    const int ii = blockIdx.x;
+    if (threadIdx.x == 0) {
+        first_zero = INT_MAX;
+        last_used = 0;
+    }
+    __syncthreads();
+    const int len = g.hist_len;
+    const int *h = g.hist + (size_t)ii * len;
+    const int per = (len + blockDim.x - 1) / blockDim.x;
+    const int lo = max(1, (int)threadIdx.x * per), hi = min(len, ((int)threadIdx.x + 1) * per);
+    int fz = INT_MAX, lu = 0;
+    for (int l = lo; l < hi; ++l) {
+        const int c = h[l];
+        if (c == 0 && fz == INT_MAX) fz = l;
+        if (c > 0) lu = l;
+    }
+    if (fz != INT_MAX) atomicMin(&first_zero, fz);
+    if (lu) atomicMax(&last_used, lu);
+    __syncthreads();
+    if (threadIdx.x == 0) g.is[ii].gap = first_zero < last_used ? first_zero : kInf;
 }
 
 // ---- small kernels ------------------------------------------------------------
 
-__global__ void k_init_scratch(Scratch *s)
+__global__ void k_init_scratch(Geom g, Scratch *s)
 {
-    s->bmax = INT_MIN;
-    s->err = 0;
-    s->changed = 0;
-    s->active = 0;
-    s->flow = 0;
-    s->energy = 0;
-    s->bfs_active = 0;
-    s->bfs_labelled = 0;
-    s->count[0] = 0;
-    s->count[1] = 0;
-    s->gap = kInf;
-    s->gap_frozen = 0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < g.n) {
+        InstScratch &r = g.is[i];
+        r.flow = 0;
+        r.energy = 0;
+        r.bmax = INT_MIN;
+        r.active = 0;
+        r.bfs_active = 0;
+        r.bfs_labelled = 0;
+        r.gap = kInf;
+        r.gap_frozen = 0;
+    }
+    if (i == 0) {
+        s->err = 0;
+        s->changed = 0;
+        s->count[0] = 0;
+        s->count[1] = 0;
+    }
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
-__global__ void k_fill(int *a, int n, int v)
+__global__ void k_fill(int *a, long long n, int v)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = v;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = v;
+}
+
+// Clears an int field of the per-volume counters (`f0`: the field of
+// volume 0) of every volume, or only of those that take part in the
+// running global relabel.
+__global__ void k_zero_field(Geom g, int *f0, int only_part)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < g.n && (!only_part || g.part[i])) *inst_field(f0, i) = 0;
 }
 
 // Work lists before the first sweep: every column, every chunk group.
-__global__ void k_work_init(unsigned long long *mask_a, int *list_a, int *count_a,
-                            unsigned long long *mask_b, unsigned long long full, int P)
+__global__ void k_work_init(Geom g, Work a, Work b)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P) {
-        mask_a[i] = full;
-        list_a[i] = i;
-        mask_b[i] = 0;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < g.Ptot) {
+        const Inst I = g.inst[g.col_inst[p]];
+        const int bits = (I.nch + I.cpb - 1) / I.cpb;
+        a.mask[p] = bits >= 64 ? ~0ULL : ((1ULL << bits) - 1);
+        a.list[p] = p;
+        b.mask[p] = 0;
     }
-    if (i == 0) *count_a = P;
+    if (p == 0) *a.count = g.Ptot;
 }
 
-// B - 1 = max_p c(p, 0): the bottom shift that makes every bottom node a
-// source node (w(p,0) < 0), so that the empty cut never wins.
-__global__ void k_bottom_max(const int *__restrict__ cost, int P, int K, Scratch *s)
+// B - 1 = max_p c(p, 0) per volume: the bottom shift that makes every
+// bottom node a source node (w(p,0) < 0), so that the empty cut never wins.
+__global__ void k_bottom_max(const int *__restrict__ cost, Geom g)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    int v = p < P ? cost[(size_t)p * K] : INT_MIN;
-    v = wave_max(v);
-    if (lane_id() == 0) atomicMax(&s->bmax, v);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    int ii = -1, v = INT_MIN;
+    if (p < g.Ptot) {
+        const Col c = column(g, p);
+        ii = c.ii;
+        v = cost[(size_t)c.I.cost_base + (size_t)c.pl * c.I.K];
+    }
+    bool pending = ii >= 0;
+    for (;;) {
+        const unsigned long long b = __ballot(pending);
+        if (!b) break;
+        const int leader = __ffsll((long long)b) - 1;
+        const int k = __shfl(ii, leader, kWave);
+        const bool mine = pending && ii == k;
+        const int m = wave_max(mine ? v : INT_MIN);
+        if (lane == leader) atomicMax(&g.is[k].bmax, m);
+        if (mine) pending = false;
+    }
 }
 
-// Graph build, one thread per node: node weights w (Section 1.2), source
+// Graph build, one wave per column: node weights w (Section 1.2), source
 // arcs pre-saturated into the excess (Section 2.1 initialisation), sink
 // residuals, zero flows and labels 0 (valid lower bounds) until the first
 // breadth-first search.  The state has the cost volume's own layout.
 __global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geom g, State st,
                                                Scratch *s)
 {
+    const int lane = lane_id();
+    int lo, hi;
+    wave_columns(g, lo, hi);
     int bad = 0;
-    long long ts_sum = 0;
-    const int B = s->bmax + 1;
-    const int stride = gridDim.x * blockDim.x;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.N; v += stride) {
-        const int z = v % g.K;
-        const int c = cost[v];
-        const int cb = z > 0 ? cost[v - 1] : B;
-        if (c <= -(1 << 30) || c >= (1 << 30)) bad = 1;
-        const int w = c - cb;
-        st.e[v] = w < 0 ? -w : 0;
-        st.ts[v] = w > 0 ? w : 0;
-        ts_sum += w > 0 ? w : 0;
-        st.d[v] = 0;
-        st.fd[v] = 0;
+    VolSum<long long> ts_sum(&g.is[0].flow);
+    for (int p = lo; p < hi; ++p) {
+        const Col c = column_uniform(g, p);
+        ts_sum.to(c.ii);
+        const int K = c.I.K;
+        const int B = g.is[c.ii].bmax + 1;
+        const size_t cb0 = (size_t)c.I.cost_base + (size_t)c.pl * K;
+        for (int ch = 0; ch < c.I.nch; ++ch) {
+            const int z = ch * kWave + lane;
+            const bool in = z < K;
+            const int cv = in ? cost[cb0 + z] : 0;
+            const int up = __shfl_up(cv, 1, kWave);
+            const int cbelow = z == 0 ? B : (lane == 0 ? (in ? cost[cb0 + z - 1] : 0) : up);
+            if (!in) continue;
+            if (cv <= -(1 << 30) || cv >= (1 << 30)) bad = 1;
+            const int w = cv - cbelow;
+            const size_t v = c.base + z;
+            st.e[v] = w < 0 ? -w : 0;
+            st.ts[v] = w > 0 ? w : 0;
+            ts_sum.acc += w > 0 ? w : 0;
+            st.d[v] = 0;
+            st.fd[v] = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) st.fl[(size_t)k * g.N + v] = 0;
+            for (int k = 0; k < 4; ++k) st.fl[(size_t)k * g.Ntot + v] = 0;
+        }
     }
-    ts_sum = wave_sum64(ts_sum);
-    if (lane_id() == 0 && ts_sum) atomicAdd((unsigned long long *)&s->flow, (unsigned long long)ts_sum);
+    ts_sum.flush();
     if (bad) atomicOr(&s->err, kErrCostRange);
 }
 
@@ -317,26 +491,40 @@ __device__ __forceinline__ ChunkIn load_chunk(const State &st, size_t v, int z, 
 // lateral arcs, and flow and tail label of the lateral arcs that end at it
 // (its reverse residual arcs).  Loaded only for lanes that need them; the
 // words of a chunk are 64 consecutive heights of the neighbour column.
+// Node (q, 0) of neighbour k lies dq[k] words from the column's node (p, 0)
+// at `base` (has[k] false: no neighbour).
 struct Lateral {
     int d_fwd[4];   // label of (q, zh) (kInf: no arc)
     int f_rev[4];   // flow on (q, zt) -> (p, z) (0: no arc)
     int d_rev[4];   // label of (q, zt)
 };
 
-__device__ __forceinline__ void load_lateral(Lateral &l, const State &st, const int q[4], int z,
-                                             int K, int N, int dl, bool need)
+__device__ __forceinline__ void load_lateral(Lateral &l, const State &st, size_t base,
+                                             const int dq[4], const bool has[4], int z, int K,
+                                             size_t Ntot, int dl, bool need)
 {
     const bool fwd = need && lat_arc(z, dl);
     const int zh = lat_head(z, dl);
     const int zt = lat_tail(z, dl, K);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const bool has = q[k] >= 0;
-        l.d_fwd[k] = (fwd && has) ? st.d[(size_t)q[k] * K + zh] : kInf;
-        const bool rev = need && has && zt >= 0;
-        const size_t w = (size_t)(has ? q[k] : 0) * K + (zt >= 0 ? zt : 0);
-        l.f_rev[k] = rev ? st.fl[(size_t)(k ^ 1) * N + w] : 0;
+        l.d_fwd[k] = (fwd && has[k]) ? st.d[base + (ptrdiff_t)(dq[k] + zh)] : kInf;
+        const bool rev = need && has[k] && zt >= 0;
+        const size_t w = base + (ptrdiff_t)(rev ? dq[k] + zt : 0);
+        l.f_rev[k] = rev ? st.fl[(size_t)(k ^ 1) * Ntot + w] : 0;
         l.d_rev[k] = rev ? st.d[w] : kInf;
+    }
+}
+
+// Global neighbour columns of a column, and the word offsets of their
+// nodes (q, 0) from the column's node (p, 0).
+__device__ __forceinline__ void neighbours(const Col &c, int p, int q[4], int dq[4], bool has[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        q[k] = nbr(c.I.nx, c.I.ny, c.x, c.y, p, k);
+        has[k] = q[k] >= 0;
+        dq[k] = (q[k] - p) * c.I.K;
     }
 }
 
@@ -353,12 +541,12 @@ __device__ __forceinline__ void load_lateral(Lateral &l, const State &st, const 
 // corrected by one atomic add of the net change; other columns only add to
 // it, so the value read is a valid lower bound of what the node holds.
 template <bool kDown>
-__global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work wout, Scratch *s)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_push(Geom g, State st, Work win, Work wout, Scratch *s)
 {
     const int lane = lane_id();
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int nwaves = gridDim.x * blockDim.x / kWave;
-    const int K = g.K, N = g.N, dl = g.delta;
+    const size_t Ntot = (size_t)g.Ntot;
     const int count = *win.count;
     long long worst = 0;   // largest excess word produced by an atomic add
     long long bytes = 0;   // algorithmic bytes moved by this lane
@@ -376,21 +564,22 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
       while (todo) {
         const int src = __ffsll((long long)todo) - 1;
         todo &= todo - 1;
-        const int p = __shfl(myp, src, kWave);
+        const int p = uniform(__shfl(myp, src, kWave));
         const unsigned long long m = (unsigned long long)shfl64((long long)mym, src);
-        const int x = p / g.ny, y = p - x * g.ny;
-        int q[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
-        const size_t base = (size_t)p * K;
+        const Col col = column_uniform(g, p);
+        const int K = col.I.K, dl = col.I.delta, nch = col.I.nch, cpb = col.I.cpb;
+        int q[4], dq[4];
+        bool has[4];
+        neighbours(col, p, q, dq, has);
+        const size_t base = col.base;
         const int gtop = 63 - __clzll(m), glow = __ffsll((long long)m) - 1;
-        const int ctop = min(g.nch - 1, gtop * g.cpb + g.cpb - 1), clow = glow * g.cpb;
+        const int ctop = min(nch - 1, gtop * cpb + cpb - 1), clow = glow * cpb;
         unsigned long long own = 0;      // own chunk groups left holding excess
         long long carry = 0;             // wave-uniform carry into the next chunk
-        for (int step = 0; step < g.nch; ++step) {
+        for (int step = 0; step < nch; ++step) {
             const int c = kDown ? ctop - step : clow + step;
-            if (c < 0 || c >= g.nch) break;
-            const bool set = (m >> (c / g.cpb)) & 1ULL;
+            if (c < 0 || c >= nch) break;
+            const bool set = (m >> (c / cpb)) & 1ULL;
             if (!set && carry == 0) {
                 if (kDown ? c < clow : c > ctop) break;
                 continue;
@@ -440,14 +629,15 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
             // results of excess atomics are only inspected at the end of the
             // chunk, so the wave does not wait for each of them in turn
             int o_col = 0, o_rev[4] = {0, 0, 0, 0}, o_fwd = 0, o_own = 0;
-            long long a_col = 0, a_rev[4] = {0, 0, 0, 0}, a_fwd = 0, a_own = 0;
+            // amounts those atomics added (an amount beyond int32 has set err)
+            int a_col = 0, a_rev[4] = {0, 0, 0, 0}, a_fwd = 0, a_own = 0;
             if (rem > 0 && adm_down) {
                 st.fd[v] = add_flow(ci.fd, rem, err);
                 bytes += kDown ? 4 : 12;
                 if (!kDown) {
-                    a_col = rem;
-                    o_col = atomicAdd(st.e + v - 1, (int)min(rem, (long long)INT_MAX));
-                    own |= 1ULL << ((z - 1) / kWave / g.cpb);
+                    a_col = (int)min(rem, (long long)INT_MAX);
+                    o_col = atomicAdd(st.e + v - 1, a_col);
+                    own |= 1ULL << ((z - 1) / kWave / cpb);
                 }
                 rem = 0;   // walking down: the carry scan already moved it
             }
@@ -456,64 +646,64 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
                 st.fd[v + 1] = ci.fd_above - (int)a;
                 bytes += kDown ? 12 : 4;
                 if (kDown) {
-                    a_col = a;
-                    o_col = atomicAdd(st.e + v + 1, (int)a);
-                    own |= 1ULL << ((z + 1) / kWave / g.cpb);
+                    a_col = (int)a;
+                    o_col = atomicAdd(st.e + v + 1, a_col);
+                    own |= 1ULL << ((z + 1) / kWave / cpb);
                 }
                 rem -= a;  // walking up: the carry scan already moved it
             }
             const bool need = rem > 0;
             if (__ballot(need)) {
                 Lateral lt;
-                load_lateral(lt, st, q, z, K, N, dl, need);
+                load_lateral(lt, st, base, dq, has, z, K, Ntot, dl, need);
                 bytes += need ? 64 : 0;
                 int fown[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    fown[k] = (need && q[k] >= 0 && lat_arc(z, dl)) ? st.fl[(size_t)k * N + v] : 0;
+                    fown[k] = (need && has[k] && lat_arc(z, dl)) ? st.fl[(size_t)k * Ntot + v] : 0;
                 const int zt = lat_tail(z, dl, K), zh = lat_head(z, dl);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const bool go = rem > 0 && lt.f_rev[k] > 0 && lt.d_rev[k] + 1 == dv;
                     if (go) {
                         const long long a = min(rem, (long long)lt.f_rev[k]);
-                        const size_t w = (size_t)q[k] * K + zt;
-                        st.fl[(size_t)(k ^ 1) * N + w] = lt.f_rev[k] - (int)a;
-                        a_rev[k] = a;
-                        o_rev[k] = atomicAdd(st.e + w, (int)a);
+                        const size_t w = base + (ptrdiff_t)(dq[k] + zt);
+                        st.fl[(size_t)(k ^ 1) * Ntot + w] = lt.f_rev[k] - (int)a;
+                        a_rev[k] = (int)a;
+                        o_rev[k] = atomicAdd(st.e + w, a_rev[k]);
                         rem -= a;
                         bytes += 8;
                     }
-                    if (go) mark_mask(wout, q[k], 1ULL << (zt / kWave / g.cpb));
+                    if (go) mark_mask(wout, q[k], 1ULL << (zt / kWave / cpb));
                 }
                 int fwd_k = -1;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (fwd_k < 0 && rem > 0 && lt.d_fwd[k] + 1 == dv) fwd_k = k;
                 if (fwd_k >= 0) {
-                    const size_t w = (size_t)q[fwd_k] * K + zh;
-                    st.fl[(size_t)fwd_k * N + v] = add_flow(fown[fwd_k], rem, err);
-                    a_fwd = rem;
-                    o_fwd = atomicAdd(st.e + w, (int)min(rem, (long long)INT_MAX));
+                    const size_t w = base + (ptrdiff_t)(dq[fwd_k] + zh);
+                    st.fl[(size_t)fwd_k * Ntot + v] = add_flow(fown[fwd_k], rem, err);
+                    a_fwd = (int)min(rem, (long long)INT_MAX);
+                    o_fwd = atomicAdd(st.e + w, a_fwd);
                     rem = 0;
                     bytes += 8;
                 }
-                if (fwd_k >= 0) mark_mask(wout, q[fwd_k], 1ULL << (zh / kWave / g.cpb));
+                if (fwd_k >= 0) mark_mask(wout, q[fwd_k], 1ULL << (zh / kWave / cpb));
             }
             // net change of this node's excess word
             const long long delta = rem - taken;
             if (delta != 0) {
                 if (rem > INT_MAX) err = 1;
-                a_own = delta;
-                o_own = atomicAdd(st.e + v, (int)delta);
+                a_own = (int)delta;
+                o_own = atomicAdd(st.e + v, a_own);
                 bytes += 4;
             }
-            if (rem > 0) own |= 1ULL << (c / g.cpb);
-            worst = max(worst, a_col ? o_col + a_col : 0);
-            worst = max(worst, a_fwd ? o_fwd + a_fwd : 0);
-            worst = max(worst, a_own ? o_own + a_own : 0);
+            if (rem > 0) own |= 1ULL << (c / cpb);
+            worst = max(worst, a_col ? (long long)o_col + a_col : 0LL);
+            worst = max(worst, a_fwd ? (long long)o_fwd + a_fwd : 0LL);
+            worst = max(worst, a_own ? (long long)o_own + a_own : 0LL);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) worst = max(worst, a_rev[k] ? o_rev[k] + a_rev[k] : 0);
+            for (int k = 0; k < 4; ++k) worst = max(worst, a_rev[k] ? (long long)o_rev[k] + a_rev[k] : 0LL);
         }
         // combine the lanes' own-column marks; the batch lane of this column
         // keeps them until the batch is done
@@ -535,16 +725,16 @@ __global__ __launch_bounds__(256) void k_push(Geom g, State st, Work win, Work w
 // finite label and no admissible arc takes d(u) = min over residual arcs of
 // d(w) + len(u, w) (kInf when that exceeds every possible distance).  The
 // column's mask is rebuilt from the nodes that stay active, which are
-// counted, and the column goes on the next push phase's list.
-__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Work wout, Scratch *s)
+// counted per volume, and the column goes on the next push phase's list.
+__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Work wout)
 {
     const int lane = lane_id();
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int nwaves = gridDim.x * blockDim.x / kWave;
-    const int K = g.K, N = g.N, dl = g.delta;
+    const size_t Ntot = (size_t)g.Ntot;
     const int count = *win.count;
-    const int gap = s->gap;
-    int cnt = 0, frozen = 0;
+    VolSum<int> cnt(&g.is[0].active);
+    VolSum<int> frozen(&g.is[0].gap_frozen);
     long long bytes = 0;
     const int bs = min(kWave, max(1, (count + nwaves - 1) / nwaves));
     for (int b0 = wave * bs; b0 < count; b0 += nwaves * bs) {
@@ -556,16 +746,20 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
       while (todo) {
         const int src = __ffsll((long long)todo) - 1;
         todo &= todo - 1;
-        const int p = __shfl(myp, src, kWave);
+        const int p = uniform(__shfl(myp, src, kWave));
         const unsigned long long m = (unsigned long long)shfl64((long long)mym, src);
-        const int x = p / g.ny, y = p - x * g.ny;
-        int q[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) q[k] = nbr(g, x, y, p, k);
-        const size_t base = (size_t)p * K;
+        const Col col = column_uniform(g, p);
+        const int K = col.I.K, dl = col.I.delta, nch = col.I.nch, cpb = col.I.cpb;
+        cnt.to(col.ii);
+        frozen.to(col.ii);
+        const int gap = g.is[col.ii].gap;
+        int q[4], dq[4];
+        bool has[4];
+        neighbours(col, p, q, dq, has);
+        const size_t base = col.base;
         unsigned long long nm = 0;
-        for (int c = 0; c < g.nch; ++c) {
-            if (!((m >> (c / g.cpb)) & 1ULL)) continue;
+        for (int c = 0; c < nch; ++c) {
+            if (!((m >> (c / cpb)) & 1ULL)) continue;
             const int z = c * kWave + lane;
             const bool in = z < K;
             const size_t v = base + z;
@@ -578,11 +772,11 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
                 dv = kInf;
                 st.d[v] = kInf;
                 act = false;
-                ++frozen;
+                ++frozen.acc;
             }
             if (!__ballot(act)) continue;
             Lateral lt;
-            load_lateral(lt, st, q, z, K, N, dl, act);
+            load_lateral(lt, st, base, dq, has, z, K, Ntot, dl, act);
             bytes += act ? 48 : 0;
             if (act) {
                 int b = ci.d_below;   // length-0 down arc
@@ -594,14 +788,14 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
                     if (lt.f_rev[k] > 0) b = min(b, lt.d_rev[k] + 1);
                 }
                 if (b > dv) {
-                    dv = b >= g.lab_cap ? kInf : b;
+                    dv = b >= col.I.lab_cap ? kInf : b;
                     st.d[v] = dv;
                     bytes += 4;
                 }
                 act = dv < kInf;
             }
-            if (__ballot(act)) nm |= 1ULL << (c / g.cpb);
-            cnt += act ? 1 : 0;
+            if (__ballot(act)) nm |= 1ULL << (c / cpb);
+            cnt.acc += act ? 1 : 0;
         }
         if (lane == src) mynm = nm;
       }
@@ -609,10 +803,8 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
       wave_append(wout.list, wout.count, mynm != 0, myp);
     }
     if (g.count_work) count_bytes(g, 2, bytes);
-    cnt = wave_sum(cnt);
-    frozen = wave_sum(frozen);
-    if (lane == 0 && cnt) atomicAdd(&s->active, cnt);
-    if (lane == 0 && frozen) atomicAdd(&s->gap_frozen, frozen);
+    cnt.flush();
+    frozen.flush();
 }
 
 // ---- global relabel: level-synchronous reverse breadth-first search -------
@@ -634,35 +826,56 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
 // search reads and writes every node O(1) times; each level touches only
 // the thresholds of columns next to a change plus the nodes it labels.
 //
-// Per-column BFS record, double-buffered by level parity:
+// Per-column BFS record, double-buffered by level parity (global columns):
 //   T[p]      threshold T_L(p) (K when no node of the column is labelled);
 //   LF[k][p]  lowest z' >= T_L(p) whose lateral arc in direction k carries
 //             flow (K if none) -- the reverse-arc term seen by neighbour k;
 //   CH[p]     the record changed when level L was produced.
+// Volumes that do not take part in a search keep CH = 0 on all their
+// columns, so every level skips them.
 
 __device__ __forceinline__ int lat_head_of(int zp, int dl) { return zp == 0 ? 0 : zp - dl; }
 
-// Level 1, one wave per column (all columns).  Nodes that could not reach t
-// before keep kInf: new residual arcs only ever join nodes that reach t, so
-// a node cut off from t stays cut off.  Counts the nodes with excess and a
+// Before level 1: clears the early-stop counters and the level-1 flag of
+// the volumes that take part, and forgets their known gap.
+__global__ void k_bfs_begin(Geom g)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < g.n && g.part[i]) {
+        g.is[i].bfs_active = 0;
+        g.is[i].bfs_labelled = 0;
+        g.is[i].gap = kInf;
+        g.is[i].lvl_changed[1] = 0;
+    }
+}
+
+// Level 1, one wave per column.  Nodes that could not reach t before keep
+// kInf: new residual arcs only ever join nodes that reach t, so a node cut
+// off from t stays cut off.  Counts per volume the nodes with excess and a
 // finite label, and those of them labelled 1, for the early stop.
-__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *CH,
-                                                  Scratch *s)
+__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *CH)
 {
     const int lane = lane_id();
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int nwaves = gridDim.x * blockDim.x / kWave;
-    const int K = g.K, N = g.N, P = g.P;
-    if (blockIdx.x == 0 && threadIdx.x == 0) s->lvl_changed[1] = 0;
-    int act = 0, lab_act = 0;
-    for (int p = wave; p < P; p += nwaves) {
-        const size_t base = (size_t)p * K;
+    const size_t Ntot = (size_t)g.Ntot;
+    const int Ptot = g.Ptot;
+    int lo, hi;
+    wave_columns(g, lo, hi);
+    VolSum<int> act(&g.is[0].bfs_active), lab_act(&g.is[0].bfs_labelled);
+    for (int p = lo; p < hi; ++p) {
+        const Col col = column_uniform(g, p);
+        if (!g.part[col.ii]) {
+            if (lane == 0) CH[p] = 0;
+            continue;
+        }
+        act.to(col.ii);
+        lab_act.to(col.ii);
+        const int K = col.I.K;
         int t1 = K;
         int lf[4] = {K, K, K, K};
-        for (int c = 0; c < g.nch; ++c) {
+        for (int c = 0; c < col.I.nch; ++c) {
             const int z = c * kWave + lane;
             const bool in = z < K;
-            const size_t v = base + z;
+            const size_t v = col.base + z;
             int tsv = 0, ev = 0, dv = kInf;
             int fv[4] = {0, 0, 0, 0};
             if (in) {
@@ -670,7 +883,7 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
                 ev = st.e[v];
                 dv = st.d[v];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * N + v];
+                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * Ntot + v];
             }
             if (t1 == K) {
                 const unsigned long long sm = __ballot(in && tsv > 0);
@@ -679,8 +892,8 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
             const bool lab = in && z >= t1;
             if (in) st.d[v] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
             if (in && ev > 0 && dv < kInf) {
-                ++act;
-                if (lab) ++lab_act;
+                ++act.acc;
+                if (lab) ++lab_act.acc;
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -693,15 +906,11 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
             T[p] = t1;
             CH[p] = 1;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) LF[k * P + p] = lf[k];
+            for (int k = 0; k < 4; ++k) LF[(size_t)k * Ptot + p] = lf[k];
         }
     }
-    act = wave_sum(act);
-    lab_act = wave_sum(lab_act);
-    if (lane == 0) {
-        if (act) atomicAdd(&s->bfs_active, act);
-        if (lab_act) atomicAdd(&s->bfs_labelled, lab_act);
-    }
+    act.flush();
+    lab_act.flush();
 }
 
 // Level L -> L+1, one lane per column for the threshold arithmetic.  The
@@ -713,29 +922,40 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
 __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin,
                                                    const int *__restrict__ CHin, int *__restrict__ Tout,
-                                                   int *__restrict__ LFout, int *__restrict__ CHout,
-                                                   Scratch *s)
+                                                   int *__restrict__ LFout, int *__restrict__ CHout)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
-    // the flag of the next level is cleared here; stream order puts this
+    // the flags of the next level are cleared here; stream order puts this
     // before every write of level L+1
-    if (p == 0) s->lvl_changed[(L + 1) & 63] = 0;
-    const int P = g.P, K = g.K, N = g.N, dl = g.delta;
+    if (p < g.n) g.is[p].lvl_changed[(L + 1) % kLvlSlots] = 0;
+    const int P = g.Ptot;
+    const size_t Ntot = (size_t)g.Ntot;
     const bool valid = p < P;
     bool self = false, near = false;
-    int T = 0, cand = 0;
-    int lf[4] = {K, K, K, K};
+    int T = 0, cand = 0, ii = 0, K = 0;
+    long long base = 0;
+    int lf[4] = {0, 0, 0, 0};
+    long long bytes = 0;
     if (valid) {
-        const int x = p / g.ny, y = p - x * g.ny;
+        const Col col = column(g, p);
+        ii = col.ii;
+        K = col.I.K;
+        base = (long long)col.base;
+        const int dl = col.I.delta;
         int q[4];
         self = CHin[p] != 0;
         near = self;
+        int nq = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            q[k] = nbr(g, x, y, p, k);
-            if (q[k] >= 0 && CHin[q[k]]) near = true;
+            q[k] = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
+            if (q[k] >= 0) {
+                ++nq;
+                if (CHin[q[k]]) near = true;
+            }
         }
+        bytes = 4 * (1 + nq) + 4;
         // Frontier: with no change at level L-1 around p none of p's inputs
         // moved, and both record buffers already hold p's record.
         if (near) {
@@ -747,28 +967,37 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
                 const int tq = Tin[q[k]];
                 if (tq == 0) cand = 0;
                 else if (tq + dl < K) cand = min(cand, tq + dl);
-                const int lq = LFin[(k ^ 1) * P + q[k]];
+                const int lq = LFin[(size_t)(k ^ 1) * P + q[k]];
                 if (lq < K) cand = min(cand, lat_head_of(lq, dl));
             }
-            if (T >= 1 && T < K && st.fd[(size_t)p * K + T] > 0) cand = min(cand, T - 1);
+            if (T >= 1 && T < K && st.fd[(size_t)base + T] > 0) cand = min(cand, T - 1);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) lf[k] = LFin[k * P + p];
+            for (int k = 0; k < 4; ++k) lf[k] = LFin[(size_t)k * P + p];
+            bytes += 4 * 14;
         }
     }
     const bool need = valid && near && cand < T;
-    long long bytes = valid ? 4 * (1 + (p % g.ny != 0) + (p % g.ny != g.ny - 1) + (p >= g.ny) +
-                                   (p < P - g.ny)) + 4 : 0;
-    if (valid && near) bytes += 4 * 14;
     if (valid && (need || self)) bytes += 20;
     if (valid) {
         if (need || self) {
             Tout[p] = need ? cand : T;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
+            for (int k = 0; k < 4; ++k) LFout[(size_t)k * P + p] = lf[k];
         }
         CHout[p] = need;
     }
-    if (__ballot(need) && lane == 0) s->lvl_changed[L & 63] = 1;
+    // level L labelled something in the volumes of the lanes with `need`
+    {
+        bool pending = need;
+        for (;;) {
+            const unsigned long long b = __ballot(pending);
+            if (!b) break;
+            const int leader = __ffsll((long long)b) - 1;
+            const int k = __shfl(ii, leader, kWave);
+            if (lane == leader) g.is[k].lvl_changed[L % kLvlSlots] = 1;
+            if (pending && ii == k) pending = false;
+        }
+    }
     // flattened labelling of the wave's new ranges
     const int len = need ? T - cand : 0;
     int incl = len;
@@ -779,7 +1008,6 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
     const int excl = incl - len;
     const int total = __shfl(incl, kWave - 1, kWave);
     const int lab = L + 1;
-    int lab_act = 0;
     if (total > 0) {
         __threadfence_block();   // the record stores above precede the atomicMin below
         for (int i0 = 0; i0 < total; i0 += kWave) {
@@ -793,66 +1021,46 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
             }
             const int pp = __shfl(p, o, kWave);
             const int hi = __shfl(T, o, kWave);
+            const long long pbase = shfl64(base, o);
+            const int pii = __shfl(ii, o, kWave);
             const int z = hi - 1 - (item - __shfl(excl, o, kWave));
+            bool act = false;
             if (item < total) {
-                const size_t v = (size_t)pp * K + z;
+                const size_t v = (size_t)pbase + z;
                 const int ev = st.e[v];
                 int fv[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * N + v];
+                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * Ntot + v];
                 st.d[v] = lab;
-                lab_act += ev > 0;
+                act = ev > 0;
                 bytes += 24;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (fv[k] > 0) atomicMin(LFout + k * P + pp, z);
+                    if (fv[k] > 0) atomicMin(LFout + (size_t)k * P + pp, z);
             }
+            wave_add_keyed(&g.is[0].bfs_labelled, pii, 1, act);
         }
     }
     if (g.count_work) count_bytes(g, 0, bytes);
-    lab_act = wave_sum(lab_act);
-    if (lane == 0 && lab_act) atomicAdd(&s->bfs_labelled, lab_act);
 }
 
-// End of a global relabel: nodes the search did not reach get `v` (kInf
-// when it ran to completion, else the first level it did not finish, which
-// is a valid lower bound of their distance).
-__global__ __launch_bounds__(256) void k_bfs_fixup(Geom g, int *d, int n, int v)
+// End of a global relabel: nodes the search did not reach get the volume's
+// fill label (kInf when its search ran to completion, else the first level
+// it did not finish, which is a valid lower bound of their distance).
+__global__ __launch_bounds__(256) void k_bfs_fixup(Geom g, int *d)
 {
-    int filled = 0;
-    const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (d[i] == kUnl) {
-            d[i] = v;
-            ++filled;
+    const int lane = lane_id();
+    int lo, hi;
+    wave_columns(g, lo, hi);
+    for (int p = lo; p < hi; ++p) {
+        const Col col = column_uniform(g, p);
+        const int fill = g.fill[col.ii];
+        if (fill < 0) continue;
+        for (int c = 0; c < col.I.nch; ++c) {
+            const int z = c * kWave + lane;
+            if (z < col.I.K && d[col.base + z] == kUnl) d[col.base + z] = fill;
         }
     }
-    (void)filled;
-}
-
-// First label g >= 1 held by no node while some node holds a larger label
-// (kInf if none): one block scans the histogram.
-__global__ __launch_bounds__(1024) void k_gap_find(Geom g, Scratch *s)
-{
-    __shared__ int first_zero, last_used;
-    if (threadIdx.x == 0) {
-        first_zero = INT_MAX;
-        last_used = 0;
-    }
-    __syncthreads();
-    const int len = g.hist_len;
-    const int per = (len + blockDim.x - 1) / blockDim.x;
-    const int lo = max(1, (int)threadIdx.x * per), hi = min(len, ((int)threadIdx.x + 1) * per);
-    int fz = INT_MAX, lu = 0;
-    for (int l = lo; l < hi; ++l) {
-        const int c = g.hist[l];
-        if (c == 0 && fz == INT_MAX) fz = l;
-        if (c > 0) lu = l;
-    }
-    if (fz != INT_MAX) atomicMin(&first_zero, fz);
-    if (lu) atomicMax(&last_used, lu);
-    __syncthreads();
-    if (threadIdx.x == 0) s->gap = first_zero < last_used ? first_zero : kInf;
 }
 
 // ---- minimum cut ---------------------------------------------------------------
@@ -866,13 +1074,14 @@ __global__ __launch_bounds__(1024) void k_gap_find(Geom g, Scratch *s)
 __global__ __launch_bounds__(256) void k_mincut_init(Geom g, State st, int *H)
 {
     const int lane = lane_id();
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int nwaves = gridDim.x * blockDim.x / kWave;
-    for (int p = wave; p < g.P; p += nwaves) {
+    int lo, hi;
+    wave_columns(g, lo, hi);
+    for (int p = lo; p < hi; ++p) {
+        const Col col = column_uniform(g, p);
         int h = -1;
-        for (int c = g.nch - 1; c >= 0 && h < 0; --c) {
+        for (int c = col.I.nch - 1; c >= 0 && h < 0; --c) {
             const int z = c * kWave + lane;
-            const bool hit = z < g.K && st.e[(size_t)p * g.K + z] > 0;
+            const bool hit = z < col.I.K && st.e[col.base + z] > 0;
             const unsigned long long b = __ballot(hit);
             if (b) h = c * kWave + 63 - __clzll(b);
         }
@@ -882,15 +1091,16 @@ __global__ __launch_bounds__(256) void k_mincut_init(Geom g, State st, int *H)
 
 __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, Scratch *s)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= g.P) return;
-    const int K = g.K, N = g.N, dl = g.delta;
-    const int x = p / g.ny, y = p - x * g.ny;
-    const size_t base = (size_t)p * K;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.Ptot) return;
+    const Col col = column(g, p);
+    const int K = col.I.K, dl = col.I.delta;
+    const size_t Ntot = (size_t)g.Ntot;
+    const size_t base = col.base;
     const int h0 = H[p];
     int h = h0;
     for (int k = 0; k < 4; ++k) {
-        const int qq = nbr(g, x, y, p, k);
+        const int qq = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
         if (qq < 0) continue;
         const int hq = H[qq];
         if (hq < 0) continue;
@@ -899,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, S
         // reverse residual of p's own lateral arcs into q's reached prefix
         const int top = min(K - 1, hq + dl);
         for (int z = top; z > h; --z) {
-            if (lat_arc(z, dl) && st.fl[(size_t)k * N + base + z] > 0) {
+            if (lat_arc(z, dl) && st.fl[(size_t)k * Ntot + base + z] > 0) {
                 h = z;
                 break;
             }
@@ -913,95 +1123,108 @@ __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, S
     }
 }
 
-// Flow value F = sum_v (w+(v) - ts(v)): the build accumulated sum w+; here
-// the residual sink capacities are subtracted (one thread per node), and
-// E = sum_p c(p, h(p)) is added by the first P threads.
+// Flow value F = sum_v (w+(v) - ts(v)) per volume: the build accumulated
+// sum w+; here the residual sink capacities are subtracted and
+// E = sum_p c(p, h(p)) is added, one wave per column.
 __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Geom g, State st,
-                                                const int *H, Scratch *s)
+                                                const int *H)
 {
-    const int stride = gridDim.x * blockDim.x;
-    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-    long long r = 0, en = 0;
-    for (int i = i0; i < g.N; i += stride) r += st.ts[i];
-    for (int i = i0; i < g.P; i += stride) {
-        const int h = H[i];
-        if (h >= 0) en += cost[(size_t)i * g.K + h];
+    const int lane = lane_id();
+    int lo, hi;
+    wave_columns(g, lo, hi);
+    VolSum<long long> flow(&g.is[0].flow), energy(&g.is[0].energy);
+    for (int p = lo; p < hi; ++p) {
+        const Col col = column_uniform(g, p);
+        flow.to(col.ii);
+        energy.to(col.ii);
+        for (int c = 0; c < col.I.nch; ++c) {
+            const int z = c * kWave + lane;
+            if (z < col.I.K) flow.acc -= st.ts[col.base + z];
+        }
+        if (lane == 0) {
+            const int h = H[p];
+            if (h >= 0) energy.acc += cost[(size_t)col.I.cost_base + (size_t)col.pl * col.I.K + h];
+        }
     }
-    r = wave_sum64(r);
-    en = wave_sum64(en);
-    if (lane_id() == 0) {
-        if (r) atomicAdd((unsigned long long *)&s->flow, (unsigned long long)(-r));
-        if (en) atomicAdd((unsigned long long *)&s->energy, (unsigned long long)en);
-    }
+    flow.flush();
+    energy.flush();
 }
 
 // ---- launchers --------------------------------------------------------------
 
-static inline unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
-
-// Grid of the grid-stride node kernels (one reduction atomic per wave).
-static inline unsigned stride_blocks(long long n)
+static inline unsigned blocks_for(long long n)
 {
-    unsigned b = blocks_for(n);
-    return b < 4096 ? b : 4096;
+    const long long b = (n + 255) / 256;
+    return (unsigned)(b > 0 ? b : 1);
 }
 
 // Grid of the wave-per-column kernels: enough waves to fill the chip, each
-// looping over its share of the columns.
+// working through its share of the columns.
 static inline unsigned wave_blocks(const Geom &g)
 {
-    long long want = (g.P + 3) / 4;     // 4 waves per 256-thread block
+    long long want = (g.Ptot + 3) / 4;     // 4 waves per 256-thread block
     return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
 }
 
-void launch_init_scratch(Scratch *s, hipStream_t st) { hipLaunchKernelGGL(k_init_scratch, 1, 1, 0, st, s); }
+void launch_init_scratch(const Geom &g, Scratch *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_scratch, dim3(blocks_for(g.n)), dim3(256), 0, st, g, s);
+}
+
 void launch_set_int(int *p, int v, hipStream_t st) { hipLaunchKernelGGL(k_set_int, 1, 1, 0, st, p, v); }
 
-void launch_fill(int *a, int n, int v, hipStream_t st)
+void launch_fill(int *a, long long n, int v, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, st, a, n, v);
+    unsigned b = blocks_for(n);
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_fill, dim3(b), dim3(256), 0, st, a, n, v);
+}
+
+void launch_zero_field(const Geom &g, int *f0, bool only_part, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_field, dim3(blocks_for(g.n)), dim3(256), 0, st, g, f0, only_part ? 1 : 0);
 }
 
 void launch_work_init(const Geom &g, const Work &a, const Work &b, hipStream_t st)
 {
-    const int bits = (g.nch + g.cpb - 1) / g.cpb;
-    const unsigned long long full = bits >= 64 ? ~0ULL : ((1ULL << bits) - 1);
-    hipLaunchKernelGGL(k_work_init, dim3(blocks_for(g.P)), dim3(256), 0, st, a.mask, a.list,
-                       a.count, b.mask, full, g.P);
+    hipLaunchKernelGGL(k_work_init, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, a, b);
 }
 
 void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bottom_max, dim3(blocks_for(g.P)), dim3(256), 0, st, cost, g.P, g.K, s);
-    hipLaunchKernelGGL(k_build, dim3(stride_blocks(g.N)), dim3(256), 0, st, cost, g, sv, s);
+    hipLaunchKernelGGL(k_bottom_max, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, cost, g);
+    hipLaunchKernelGGL(k_build, dim3(wave_blocks(g)), dim3(256), 0, st, cost, g, sv, s);
 }
 
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, Scratch *s,
-                     hipStream_t st)
+void launch_bfs_begin(const Geom &g, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_init, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, T, LF, CH, s);
+    hipLaunchKernelGGL(k_bfs_begin, dim3(blocks_for(g.n)), dim3(256), 0, st, g);
+}
+
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bfs_init, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, T, LF, CH);
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *CHin, int *Tout, int *LFout, int *CHout, Scratch *s,
-                      hipStream_t st)
+                      const int *CHin, int *Tout, int *LFout, int *CHout, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(g.P)), dim3(256), 0, st, g, sv, L, Tin, LFin,
-                       CHin, Tout, LFout, CHout, s);
+    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv, L, Tin, LFin,
+                       CHin, Tout, LFout, CHout);
 }
 
-void launch_bfs_fixup(const Geom &g, const State &sv, int v, hipStream_t st)
+void launch_bfs_fixup(const Geom &g, const State &sv, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_fixup, dim3(stride_blocks(g.N)), dim3(256), 0, st, g, sv.d, g.N, v);
+    hipLaunchKernelGGL(k_bfs_fixup, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv.d);
 }
 
-void launch_gap_find(const Geom &g, const State &sv, Scratch *s, hipStream_t st)
+void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(g.hist_len)), dim3(256), 0, st, g.hist, g.hist_len, 0);
-    unsigned blocks = stride_blocks(g.N);
-    if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL(k_hist_build, dim3(blocks), dim3(256), sizeof(int) * g.hist_len, st, g, sv.d);
-    hipLaunchKernelGGL(k_gap_find, dim3(1), dim3(1024), 0, st, g, s);
+    launch_fill(g.hist, (long long)g.n * g.hist_len, 0, st);
+    unsigned bx = blocks_for(max_inst_nodes);
+    if (bx > 512) bx = 512;
+    hipLaunchKernelGGL(k_hist_build, dim3(bx, g.n), dim3(256), sizeof(int) * g.hist_len, st, g, sv.d);
+    hipLaunchKernelGGL(k_gap_find, dim3(g.n), dim3(1024), 0, st, g);
 }
 
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
@@ -1015,13 +1238,12 @@ void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wo
 
 void launch_compact(const Geom &g, const Work &w, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(g.P)), dim3(256), 0, st, w, g.P);
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, w, g.Ptot);
 }
 
-void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
-                    hipStream_t st)
+void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_relabel, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
+    hipLaunchKernelGGL(k_relabel, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
 }
 
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
@@ -1031,13 +1253,12 @@ void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
 
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mincut_pass, dim3(blocks_for(g.P)), dim3(256), 0, st, g, sv, H, s);
+    hipLaunchKernelGGL(k_mincut_pass, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv, H, s);
 }
 
-void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, Scratch *s,
-                   hipStream_t st)
+void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finish, dim3(stride_blocks(g.N)), dim3(256), 0, st, cost, g, sv, H, s);
+    hipLaunchKernelGGL(k_finish, dim3(wave_blocks(g)), dim3(256), 0, st, cost, g, sv, H);
 }
 
 }  // namespace smf

@@ -1,0 +1,227 @@
+// Autotuner of the solver's relabel period (include/smf.h, smf_autotune).
+//
+// The frequency of global relabelling trades the cost of one search against
+// the sweeps it saves; the paper settles it empirically (Section 3.4, the
+// relabel factor of the global-relabel sweep).  Here the period is chosen
+// per class of volume -- key (ceil log2 K, min(delta, 4), floor log2 of the
+// column count) -- by timing complete solves of the largest volume of each
+// class with every candidate period, and remembered in a process-wide cache
+// that can be saved to and loaded from a text file (one line per class:
+// "kbits delta pbits period best_ns").
+//
+// The tuner is a client of the C-ABI: it solves the representative volume
+// on a temporary handle of its own and writes the chosen periods into the
+// caller's handle with smf_batch_set_param.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/smf.h"
+
+namespace smf {
+int set_error(int code, const std::string &msg);
+void clear_error();
+}  // namespace smf
+
+namespace {
+
+using Key = std::tuple<int, int, int>;
+
+struct Choice {
+    int64_t period;
+    int64_t best_ns;
+};
+
+std::mutex g_mu;
+std::map<Key, Choice> g_cache;
+bool g_env_loaded = false;
+
+const int64_t kCandidates[] = {2, 3, 4, 6, 8, 12, 16, 24};
+
+int ceil_log2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+int floor_log2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(2) << b) <= v) ++b;
+    return b;
+}
+
+Key key_of(int32_t nx, int32_t ny, int32_t K, int32_t delta)
+{
+    return Key(ceil_log2(K), std::min<int32_t>(delta, 4), floor_log2((int64_t)nx * ny));
+}
+
+int load_locked(const char *path)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_load: cannot open ") + path);
+    int a, b, c;
+    long long p, ns;
+    while (fscanf(f, "%d %d %d %lld %lld", &a, &b, &c, &p, &ns) == 5)
+        if (p >= 1) g_cache[Key(a, b, c)] = Choice{p, ns};
+    fclose(f);
+    return SMF_OK;
+}
+
+int save_locked(const char *path)
+{
+    FILE *f = fopen(path, "w");
+    if (!f) return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_save: cannot open ") + path);
+    for (const auto &kv : g_cache)
+        fprintf(f, "%d %d %d %lld %lld\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                std::get<2>(kv.first), (long long)kv.second.period, (long long)kv.second.best_ns);
+    if (fclose(f) != 0)
+        return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_save: cannot write ") + path);
+    return SMF_OK;
+}
+
+void load_env_locked()
+{
+    if (g_env_loaded) return;
+    g_env_loaded = true;
+    const char *path = getenv("SMF_TUNE_CACHE");
+    if (path && *path) (void)load_locked(path);
+}
+
+// Shapes of the handle's volumes via the C-ABI.
+int shapes_of(smf_handle *h, std::vector<int64_t> s[4])
+{
+    int64_t n = 0;
+    int rc = smf_get_stat(h, "volumes", &n);
+    if (rc) return rc;
+    const char *keys[4] = {"nx", "ny", "K", "delta"};
+    for (int j = 0; j < 4; ++j) {
+        s[j].assign((size_t)n, 0);
+        rc = smf_batch_get_stat(h, keys[j], s[j].data());
+        if (rc) return rc;
+    }
+    return SMF_OK;
+}
+
+// Periods for the handle's volumes from the cache (0 where no entry).
+std::vector<int64_t> periods_locked(const std::vector<int64_t> s[4])
+{
+    std::vector<int64_t> out(s[0].size(), 0);
+    for (size_t i = 0; i < out.size(); ++i) {
+        auto it = g_cache.find(key_of((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i],
+                                      (int32_t)s[3][i]));
+        if (it != g_cache.end()) out[i] = it->second.period;
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
+                            const int64_t *offsets_host, void *stream)
+{
+    smf::clear_error();
+    if (!h || !packed_cost_dev) return smf::set_error(SMF_ERR_ARG, "smf_autotune: NULL handle or cost");
+    std::vector<int64_t> s[4];
+    int rc = shapes_of(h, s);
+    if (rc) return rc;
+    const size_t n = s[0].size();
+    std::vector<int64_t> off(n);
+    for (size_t i = 0, acc = 0; i < n; ++i) {
+        off[i] = offsets_host ? offsets_host[i] : (int64_t)acc;
+        acc += (size_t)(s[0][i] * s[1][i] * s[2][i]);
+    }
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_env_locked();
+    // the largest volume of every class that the cache does not know yet
+    std::map<Key, size_t> todo;
+    for (size_t i = 0; i < n; ++i) {
+        const Key k = key_of((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i], (int32_t)s[3][i]);
+        if (g_cache.count(k)) continue;
+        auto it = todo.find(k);
+        const int64_t size = s[0][i] * s[1][i] * s[2][i];
+        if (it == todo.end() || size > s[0][it->second] * s[1][it->second] * s[2][it->second])
+            todo[k] = i;
+    }
+    for (const auto &kv : todo) {
+        const size_t i = kv.second;
+        smf_handle *t = smf_create((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i], (int32_t)s[3][i]);
+        if (!t) return SMF_ERR_NOMEM;   // smf_create described the failure
+        const int32_t *cost = packed_cost_dev + off[i];
+        rc = smf_solve(t, cost, stream);   // warm-up
+        Choice best{0, 0};
+        for (int64_t p : kCandidates) {
+            if (rc) break;
+            rc = smf_set_param(t, "relabel_period", p);
+            if (rc) break;
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = smf_solve(t, cost, stream);   // returns once the result is complete
+            const auto t1 = std::chrono::steady_clock::now();
+            const int64_t ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count();
+            if (!rc && (best.period == 0 || ns < best.best_ns)) best = Choice{p, ns};
+        }
+        smf_destroy(t);
+        if (rc) return rc;
+        g_cache[kv.first] = best;
+    }
+    const char *path = getenv("SMF_TUNE_CACHE");
+    if (path && *path && !todo.empty()) (void)save_locked(path);
+    const std::vector<int64_t> per = periods_locked(s);
+    return smf_batch_set_param(h, "relabel_period", per.data());
+}
+
+extern "C" int smf_tune_apply(smf_handle *h)
+{
+    smf::clear_error();
+    if (!h) return smf::set_error(SMF_ERR_ARG, "smf_tune_apply: NULL handle");
+    std::vector<int64_t> s[4];
+    int rc = shapes_of(h, s);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_env_locked();
+    const std::vector<int64_t> per = periods_locked(s);
+    return smf_batch_set_param(h, "relabel_period", per.data());
+}
+
+extern "C" int smf_tune_cache_load(const char *path)
+{
+    smf::clear_error();
+    if (!path) return smf::set_error(SMF_ERR_ARG, "smf_tune_cache_load: NULL path");
+    std::lock_guard<std::mutex> lock(g_mu);
+    return load_locked(path);
+}
+
+extern "C" int smf_tune_cache_save(const char *path)
+{
+    smf::clear_error();
+    if (!path) return smf::set_error(SMF_ERR_ARG, "smf_tune_cache_save: NULL path");
+    std::lock_guard<std::mutex> lock(g_mu);
+    return save_locked(path);
+}
+
+extern "C" int smf_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_cache.clear();
+    g_env_loaded = true;   // an explicit clear also forgets the environment's file
+    return SMF_OK;
+}
+
+extern "C" int smf_tune_lookup(int32_t nx, int32_t ny, int32_t K, int32_t delta, int64_t *period)
+{
+    smf::clear_error();
+    if (!period || nx < 1 || ny < 1 || K < 1 || delta < 0)
+        return smf::set_error(SMF_ERR_ARG, "smf_tune_lookup: bad shape or NULL output");
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_env_locked();
+    auto it = g_cache.find(key_of(nx, ny, K, delta));
+    *period = it == g_cache.end() ? 0 : it->second.period;
+    return SMF_OK;
+}

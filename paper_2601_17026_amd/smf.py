@@ -49,13 +49,37 @@ _lib.smf_onehot_backward.argtypes = [_P, _P, _P, _I32, _I32, _I32, _I32, _P]
 _lib.smf_onehot_backward.restype = ctypes.c_int
 _lib.smf_last_error.argtypes = []
 _lib.smf_last_error.restype = ctypes.c_char_p
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_lib.smf_batch_create.argtypes = [_I32, _PI32, _PI32, _PI32, _PI32]
+_lib.smf_batch_create.restype = _P
+_lib.smf_batch_solve.argtypes = [_P, _P, _PI64, _P]
+_lib.smf_batch_flow_values.argtypes = [_P, _PI64]
+_lib.smf_batch_energies.argtypes = [_P, _PI64]
+_lib.smf_batch_surfaces.argtypes = [_P, _P, _P]
+_lib.smf_batch_set_param.argtypes = [_P, ctypes.c_char_p, _PI64]
+_lib.smf_batch_get_stat.argtypes = [_P, ctypes.c_char_p, _PI64]
+_lib.smf_autotune.argtypes = [_P, _P, _PI64, _P]
+_lib.smf_tune_apply.argtypes = [_P]
+_lib.smf_tune_cache_load.argtypes = [ctypes.c_char_p]
+_lib.smf_tune_cache_save.argtypes = [ctypes.c_char_p]
+_lib.smf_tune_cache_clear.argtypes = []
+_lib.smf_tune_lookup.argtypes = [_I32, _I32, _I32, _I32, _PI64]
+for _name in ("smf_autotune", "smf_tune_apply", "smf_tune_cache_load", "smf_tune_cache_save",
+              "smf_tune_cache_clear", "smf_tune_lookup"):
+    getattr(_lib, _name).restype = ctypes.c_int
 for _name in ("smf_solve", "smf_flow_value", "smf_energy", "smf_surface",
-              "smf_export_state", "smf_set_param", "smf_get_stat"):
+              "smf_export_state", "smf_set_param", "smf_get_stat", "smf_batch_solve",
+              "smf_batch_flow_values", "smf_batch_energies", "smf_batch_surfaces",
+              "smf_batch_set_param", "smf_batch_get_stat"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 EXPORTED = ("smf_create", "smf_destroy", "smf_solve", "smf_flow_value", "smf_energy",
             "smf_surface", "smf_export_state", "smf_set_param", "smf_get_stat",
-            "smf_status_string", "smf_last_error", "smf_onehot_backward")
+            "smf_status_string", "smf_last_error", "smf_onehot_backward",
+            "smf_batch_create", "smf_batch_solve", "smf_batch_flow_values",
+            "smf_batch_energies", "smf_batch_surfaces", "smf_batch_set_param",
+            "smf_batch_get_stat", "smf_autotune", "smf_tune_apply", "smf_tune_cache_load",
+            "smf_tune_cache_save", "smf_tune_cache_clear", "smf_tune_lookup")
 
 
 class SmfError(RuntimeError):
@@ -90,6 +114,7 @@ class Solver:
     def __init__(self, nx: int, ny: int, K: int, delta: int):
         self.shape = (int(nx), int(ny), int(K))
         self.delta = int(delta)
+        self.n = 1
         h = _lib.smf_create(int(nx), int(ny), int(K), int(delta))
         if not h:
             raise SmfError(ERR_NOMEM, "smf_create")
@@ -121,6 +146,17 @@ class Solver:
     def stats(self) -> dict:
         return {k: self.stat(k) for k in
                 ("sweeps", "global_relabels", "bfs_passes", "mincut_passes", "gap_relabels")}
+
+    def set_param_per_volume(self, key: str, values) -> None:
+        if len(values) != self.n:
+            raise ValueError(f"expected {self.n} values, got {len(values)}")
+        arr = (ctypes.c_int64 * self.n)(*[int(v) for v in values])
+        _check(_lib.smf_batch_set_param(self._h, key.encode(), arr), f"smf_batch_set_param({key})")
+
+    def stat_per_volume(self, key: str) -> list:
+        arr = (ctypes.c_int64 * self.n)()
+        _check(_lib.smf_batch_get_stat(self._h, key.encode(), arr), f"smf_batch_get_stat({key})")
+        return list(arr)
 
     def solve(self, cost: torch.Tensor, stream=None) -> None:
         _dev_i32(cost, self.shape, "cost")
@@ -154,6 +190,135 @@ class Solver:
         _check(_lib.smf_export_state(self._h, e.data_ptr(), ts.data_ptr(), fd.data_ptr(),
                                      fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
         return e, ts, fd, fl
+
+
+class BatchSolver:
+    """One handle for a batch of volumes of uneven shapes (nx, ny, K, delta),
+    solved together: every launch covers all volumes."""
+
+    def __init__(self, shapes):
+        shapes = [tuple(int(v) for v in sh) for sh in shapes]
+        if not shapes or any(len(sh) != 4 for sh in shapes):
+            raise ValueError("shapes must be a non-empty list of (nx, ny, K, delta)")
+        self.shapes = shapes
+        self.n = len(shapes)
+        arr = [(ctypes.c_int32 * self.n)(*[sh[j] for sh in shapes]) for j in range(4)]
+        h = _lib.smf_batch_create(self.n, *[ctypes.cast(a, _PI32) for a in arr])
+        if not h:
+            raise SmfError(ERR_NOMEM, "smf_batch_create")
+        self._h = h
+        self.sizes = [nx * ny * K for nx, ny, K, _ in shapes]
+        self.columns = [nx * ny for nx, ny, _, _ in shapes]
+        self.offsets = [0]
+        for v in self.sizes[:-1]:
+            self.offsets.append(self.offsets[-1] + v)
+        self.col_offsets = [0]
+        for v in self.columns[:-1]:
+            self.col_offsets.append(self.col_offsets[-1] + v)
+
+    close = Solver.close
+    __del__ = Solver.__del__
+    __enter__ = Solver.__enter__
+    __exit__ = Solver.__exit__
+    set_param = Solver.set_param
+    stat = Solver.stat
+    stats = Solver.stats
+
+    set_param_per_volume = Solver.set_param_per_volume
+    stat_per_volume = Solver.stat_per_volume
+
+    def pack(self, costs) -> torch.Tensor:
+        """Packs a list of (nx, ny, K) int32 CUDA volumes into one buffer."""
+        if len(costs) != self.n:
+            raise ValueError(f"expected {self.n} volumes, got {len(costs)}")
+        for c, (nx, ny, K, _) in zip(costs, self.shapes):
+            _dev_i32(c, (nx, ny, K), "cost")
+        return torch.cat([c.reshape(-1) for c in costs])
+
+    def solve(self, packed: torch.Tensor, offsets=None, stream=None) -> None:
+        """Solves every volume; volume i's costs start at packed[offsets[i]]
+        (default: densely packed in order)."""
+        if packed.device.type != "cuda" or packed.dtype != torch.int32 or not packed.is_contiguous():
+            raise ValueError("packed costs must be a contiguous int32 CUDA tensor")
+        offs = self.offsets if offsets is None else [int(o) for o in offsets]
+        if len(offs) != self.n or any(o < 0 or o + n > packed.numel() for o, n in zip(offs, self.sizes)):
+            raise ValueError("cost offsets do not fit the packed buffer")
+        arr = (ctypes.c_int64 * self.n)(*offs)
+        _check(_lib.smf_batch_solve(self._h, packed.data_ptr(), arr, _stream_ptr(stream)),
+               "smf_batch_solve")
+
+    def flow_values(self) -> list:
+        arr = (ctypes.c_int64 * self.n)()
+        _check(_lib.smf_batch_flow_values(self._h, arr), "smf_batch_flow_values")
+        return list(arr)
+
+    def energies(self) -> list:
+        arr = (ctypes.c_int64 * self.n)()
+        _check(_lib.smf_batch_energies(self._h, arr), "smf_batch_energies")
+        return list(arr)
+
+    def surfaces(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Packed surfaces: volume i's (nx, ny) heights at col_offsets[i]."""
+        total = sum(self.columns)
+        if out is None:
+            out = torch.empty((total,), dtype=torch.int32, device="cuda")
+        _dev_i32(out, (total,), "out")
+        _check(_lib.smf_batch_surfaces(self._h, out.data_ptr(), _stream_ptr(stream)),
+               "smf_batch_surfaces")
+        return out
+
+    def unpack_surfaces(self, packed: torch.Tensor) -> list:
+        return [packed[o:o + nx * ny].view(nx, ny)
+                for o, (nx, ny, _, _) in zip(self.col_offsets, self.shapes)]
+
+    def export_state(self, stream=None):
+        """Final packed preflow as flat (excess, sink_res, flow_down, flow_lat)
+        device tensors; flow_lat is (4, total nodes)."""
+        total = sum(self.sizes)
+        e = torch.empty((total,), dtype=torch.int32, device="cuda")
+        ts = torch.empty_like(e)
+        fd = torch.empty_like(e)
+        fl = torch.empty((4, total), dtype=torch.int32, device="cuda")
+        _check(_lib.smf_export_state(self._h, e.data_ptr(), ts.data_ptr(), fd.data_ptr(),
+                                     fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
+        return e, ts, fd, fl
+
+
+def autotune(solver, packed: torch.Tensor, offsets=None, stream=None) -> None:
+    """Times candidate relabel periods per volume class (smf_autotune) and
+    gives every volume of `solver` (a Solver or BatchSolver) its class's
+    period.  `packed` is the volume (Solver) or the packed batch costs."""
+    if packed.device.type != "cuda" or packed.dtype != torch.int32 or not packed.is_contiguous():
+        raise ValueError("costs must be a contiguous int32 CUDA tensor")
+    arr = None
+    if offsets is not None:
+        arr = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
+    elif isinstance(solver, BatchSolver):
+        arr = (ctypes.c_int64 * solver.n)(*solver.offsets)
+    _check(_lib.smf_autotune(solver._h, packed.data_ptr(), arr, _stream_ptr(stream)), "smf_autotune")
+
+
+def tune_apply(solver) -> None:
+    _check(_lib.smf_tune_apply(solver._h), "smf_tune_apply")
+
+
+def tune_cache_load(path: str) -> None:
+    _check(_lib.smf_tune_cache_load(os.fsencode(path)), "smf_tune_cache_load")
+
+
+def tune_cache_save(path: str) -> None:
+    _check(_lib.smf_tune_cache_save(os.fsencode(path)), "smf_tune_cache_save")
+
+
+def tune_cache_clear() -> None:
+    _check(_lib.smf_tune_cache_clear(), "smf_tune_cache_clear")
+
+
+def tune_lookup(nx: int, ny: int, K: int, delta: int) -> int:
+    out = ctypes.c_int64()
+    _check(_lib.smf_tune_lookup(int(nx), int(ny), int(K), int(delta), ctypes.byref(out)),
+           "smf_tune_lookup")
+    return out.value
 
 
 def onehot_backward(surface: torch.Tensor, grad_energy: torch.Tensor, K: int,

@@ -1,0 +1,203 @@
+"""GPU parity of the batched solve (smf_batch_*): every volume of a batch of
+uneven shapes against the CPU oracle, against its max-flow/min-cut
+certificate, and against the same volume solved on its own.  All results are
+integers and must match bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from paper_2601_17026_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_17026_amd import smf as mod
+    return mod
+
+
+# uneven shapes: tiny, single-row, ragged K (not a multiple of 64), K > 128,
+# delta from 0 to 5
+SHAPES = [
+    (1, 1, 1, 0), (32, 32, 64, 2), (37, 29, 70, 1), (5, 3, 9, 3), (1, 300, 40, 3),
+    (16, 16, 130, 4), (2, 2, 2, 0), (70, 9, 33, 2), (4, 1, 6, 5), (48, 40, 96, 2),
+]
+
+
+def _volumes(shapes, seed0=700):
+    vols = []
+    for i, (nx, ny, K, _) in enumerate(shapes):
+        if nx * ny * K <= 64:
+            vols.append(synth.random_cost(nx, ny, K, -20, 20, seed=seed0 + i))
+        else:
+            vols.append(synth.layered_cost(nx, ny, K, 2, 0.4, 255, 0.05, seed0 + i))
+    return vols
+
+
+def _solve_batch(smf, shapes, vols, params=None, per_volume=None, offsets=None, packed=None,
+                 certify=False):
+    with smf.BatchSolver(shapes) as b:
+        for k, v in (params or {}).items():
+            b.set_param(k, v)
+        for k, v in (per_volume or {}).items():
+            b.set_param_per_volume(k, v)
+        if packed is None:
+            packed = b.pack([torch.from_numpy(v).cuda() for v in vols])
+        b.solve(packed, offsets=offsets)
+        surf = b.surfaces()
+        out = dict(flow=b.flow_values(), energy=b.energies(),
+                   surface=[s.cpu().numpy() for s in b.unpack_surfaces(surf)],
+                   sweeps=b.stat_per_volume("sweeps"),
+                   relabels=b.stat_per_volume("global_relabels"),
+                   periods=b.stat_per_volume("relabel_period"), batch_sweeps=b.stat("sweeps"))
+        if certify:
+            e, ts, fd, fl = (t.cpu().numpy() for t in b.export_state())
+            certs = []
+            for o, n, (nx, ny, K, dl), v, s in zip(b.offsets, b.sizes, shapes, vols, out["surface"]):
+                sl = slice(o, o + n)
+                certs.append(oracle.certify(v, dl, e[sl].reshape(nx, ny, K), ts[sl].reshape(nx, ny, K),
+                                            fd[sl].reshape(nx, ny, K), fl[:, sl].reshape(4, nx, ny, K), s))
+            out["cert"] = certs
+    return out
+
+
+def _check_oracle(shapes, vols, g):
+    for i, ((nx, ny, K, dl), v) in enumerate(zip(shapes, vols)):
+        r = oracle.solve(v, dl)
+        assert g["flow"][i] == r.flow, i
+        assert g["energy"][i] == r.energy, i
+        np.testing.assert_array_equal(g["surface"][i], r.hmin, err_msg=f"volume {i}")
+
+
+def test_batch_matches_oracle(smf):
+    vols = _volumes(SHAPES)
+    print("case: batch of", len(SHAPES), "uneven volumes", flush=True)
+    g = _solve_batch(smf, SHAPES, vols, certify=True)
+    _check_oracle(SHAPES, vols, g)
+    for i, c in enumerate(g["cert"]):
+        assert c.ok, (i, c)
+        assert c.flow == g["flow"][i] and c.energy == g["energy"][i]
+    # a volume stops sweeping once it has no active node
+    assert max(g["sweeps"]) == g["batch_sweeps"]
+    assert all(1 <= r for r in g["relabels"])
+
+
+def test_batch_equals_plain_solves(smf):
+    vols = _volumes(SHAPES, seed0=800)
+    g = _solve_batch(smf, SHAPES, vols)
+    for i, ((nx, ny, K, dl), v) in enumerate(zip(SHAPES, vols)):
+        print(f"case: plain solve of batch volume {i} {(nx, ny, K)} delta {dl}", flush=True)
+        with smf.Solver(nx, ny, K, dl) as s:
+            s.solve(torch.from_numpy(v).cuda())
+            assert s.flow_value() == g["flow"][i]
+            assert s.energy() == g["energy"][i]
+            np.testing.assert_array_equal(s.surface().cpu().numpy(), g["surface"][i])
+
+
+def test_batch_offsets_with_gaps(smf):
+    # volumes stored in reverse order with padding between them
+    shapes = SHAPES[:6]
+    vols = _volumes(shapes, seed0=900)
+    pieces, offsets, pos = [], [0] * len(shapes), 0
+    for i in reversed(range(len(shapes))):
+        pad = np.full(17 + 5 * i, 12345, dtype=np.int32)
+        pieces += [pad, vols[i].reshape(-1)]
+        offsets[i] = pos + pad.size
+        pos += pad.size + vols[i].size
+    packed = torch.from_numpy(np.concatenate(pieces + [np.zeros(3, np.int32)])).cuda()
+    print("case: batch with offsets and gaps", flush=True)
+    g = _solve_batch(smf, shapes, vols, offsets=offsets, packed=packed)
+    _check_oracle(shapes, vols, g)
+
+
+def test_batch_per_volume_periods(smf):
+    vols = _volumes(SHAPES, seed0=1000)
+    periods = [1, 3, 0, 40, 2, 7, 1, 5, 0, 12]
+    print("case: per-volume relabel periods", flush=True)
+    g = _solve_batch(smf, SHAPES, vols, params={"relabel_period": 6},
+                     per_volume={"relabel_period": periods})
+    assert g["periods"] == [p if p else 6 for p in periods]
+    _check_oracle(SHAPES, vols, g)
+
+
+@pytest.mark.parametrize("params", [
+    {"gap_every": 1},
+    {"bfs_early_stop": 0},
+    {"poll_every": 3, "bfs_poll_every": 2},
+    {"relabel_period": 1},
+])
+def test_batch_parameter_variants(smf, params):
+    vols = _volumes(SHAPES, seed0=1100)
+    print(f"case: batch params {params}", flush=True)
+    g = _solve_batch(smf, SHAPES, vols, params=params, certify=True)
+    _check_oracle(SHAPES, vols, g)
+    assert all(c.ok for c in g["cert"])
+
+
+def test_batch_handle_reuse(smf):
+    # one handle, two solves with different costs: no state leaks between them
+    shapes = SHAPES[1:5]
+    with smf.BatchSolver(shapes) as b:
+        for seed0 in (1200, 1300):
+            vols = _volumes(shapes, seed0=seed0)
+            b.solve(b.pack([torch.from_numpy(v).cuda() for v in vols]))
+            g = dict(flow=b.flow_values(), energy=b.energies(),
+                     surface=[s.cpu().numpy() for s in b.unpack_surfaces(b.surfaces())])
+            _check_oracle(shapes, vols, g)
+
+
+def test_batch_of_one_is_plain(smf):
+    cost, delta = synth.config_small()
+    g = _solve_batch(smf, [cost.shape + (delta,)], [cost])
+    r = oracle.solve(cost, delta)
+    assert g["flow"] == [r.flow] and g["energy"] == [r.energy]
+    np.testing.assert_array_equal(g["surface"][0], r.hmin)
+
+
+def test_batch_error_paths(smf):
+    with pytest.raises(smf.SmfError):
+        smf.BatchSolver([(4, 4, 4, 1), (0, 4, 4, 1)])
+    shapes = [(6, 5, 8, 1), (3, 3, 3, 0)]
+    vols = [synth.random_cost(6, 5, 8, 0, 50, seed=51), synth.random_cost(3, 3, 3, 0, 9, seed=52)]
+    vols[1][1, 1, 1] = -(1 << 30)
+    with smf.BatchSolver(shapes) as b:
+        packed = b.pack([torch.from_numpy(v).cuda() for v in vols])
+        with pytest.raises(smf.SmfError) as ei:
+            b.solve(packed)
+        assert ei.value.status == smf.ERR_RANGE
+        with pytest.raises(smf.SmfError) as ei:
+            b.flow_values()
+        assert ei.value.status == smf.ERR_NOT_SOLVED
+        with pytest.raises(ValueError):
+            b.solve(packed, offsets=[0, packed.numel()])
+        with pytest.raises(smf.SmfError):
+            b.set_param_per_volume("relabel_period", [1, -1])
+        # the plain single-volume calls refuse a batch of two
+        with pytest.raises(smf.SmfError):
+            smf._check(smf._lib.smf_solve(b._h, packed.data_ptr(), None), "smf_solve")
+
+
+def test_batch_workload_64_volumes(smf):
+    # the 64-volume batch workload at full size: every volume is certified
+    # optimal (and its flow checked against the closed form), and volumes
+    # sampled from it are compared with plain solves
+    shapes = [(nx, ny, K, dl) for nx, ny, K, dl in synth.batch_shapes()]
+    vols = [synth.batch_instance(i, sh)[0] for i, sh in enumerate(shapes)]
+    print("case: 64-volume batch workload", flush=True)
+    g = _solve_batch(smf, shapes, vols, certify=True)
+    for i, c in enumerate(g["cert"]):
+        assert c.ok, (i, c)
+        assert c.flow == g["flow"][i] and c.energy == g["energy"][i]
+        assert g["flow"][i] == pins.flow_closed_form(vols[i], g["energy"][i])
+    for i in (0, 17, 40, 63):
+        nx, ny, K, dl = shapes[i]
+        with smf.Solver(nx, ny, K, dl) as s:
+            s.solve(torch.from_numpy(vols[i]).cuda())
+            assert s.flow_value() == g["flow"][i]
+            np.testing.assert_array_equal(s.surface().cpu().numpy(), g["surface"][i])

@@ -1,0 +1,71 @@
+"""GPU checks of the relabel-period autotuner (smf_autotune): it picks a
+candidate period per volume class, applies it to every volume of the class,
+the cache round-trips through a file, and tuned solves stay exact."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_17026_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CANDIDATES = {2, 3, 4, 6, 8, 12, 16, 24}
+
+
+@pytest.fixture(scope="module")
+def smf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_17026_amd import smf as mod
+    return mod
+
+
+def test_autotune_batch(smf, tmp_path):
+    # two volumes share a class (same K bucket, delta, column bucket), one differs
+    shapes = [(40, 40, 100, 2), (36, 44, 120, 2), (20, 30, 60, 1)]
+    vols = [synth.layered_cost(nx, ny, K, 2, 0.4, 255, 0.05, 1500 + i)
+            for i, (nx, ny, K, _) in enumerate(shapes)]
+    smf.tune_cache_clear()
+    with smf.BatchSolver(shapes) as b:
+        packed = b.pack([torch.from_numpy(v).cuda() for v in vols])
+        print("case: autotune of a 3-volume batch", flush=True)
+        smf.autotune(b, packed)
+        periods = b.stat_per_volume("relabel_period")
+        assert set(periods) <= CANDIDATES
+        assert periods[0] == periods[1]
+        assert periods == [smf.tune_lookup(*sh) for sh in shapes]
+        b.solve(packed)
+        flows, energies = b.flow_values(), b.energies()
+        surfs = [s.cpu().numpy() for s in b.unpack_surfaces(b.surfaces())]
+    for (nx, ny, K, dl), v, f, e, s in zip(shapes, vols, flows, energies, surfs):
+        r = oracle.solve(v, dl)
+        assert (f, e) == (r.flow, r.energy)
+        np.testing.assert_array_equal(s, r.hmin)
+    # the cache survives a save / clear / load round trip and is applied
+    # to a new handle without timing
+    path = str(tmp_path / "tune.txt")
+    smf.tune_cache_save(path)
+    smf.tune_cache_clear()
+    assert smf.tune_lookup(*shapes[0]) == 0
+    smf.tune_cache_load(path)
+    with smf.Solver(*shapes[2]) as s:
+        smf.tune_apply(s)
+        assert s.stat_per_volume("relabel_period") == [periods[2]]
+    with smf.BatchSolver(shapes[:1]) as b1:
+        smf.tune_apply(b1)
+        assert b1.stat_per_volume("relabel_period") == [periods[0]]
+
+
+def test_autotune_plain_handle(smf):
+    cost, delta = synth.config_small()
+    smf.tune_cache_clear()
+    c = torch.from_numpy(cost).cuda()
+    with smf.Solver(*cost.shape, delta) as s:
+        print("case: autotune of a plain handle", flush=True)
+        smf.autotune(s, c)
+        assert smf.tune_lookup(*cost.shape, delta) in CANDIDATES
+        s.solve(c)
+        r = oracle.solve(cost, delta)
+        assert s.flow_value() == r.flow and s.energy() == r.energy
+        np.testing.assert_array_equal(s.surface().cpu().numpy(), r.hmin)

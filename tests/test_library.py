@@ -37,13 +37,90 @@ def test_status_strings_and_arg_errors_without_gpu():
     # argument checks happen before any device call
     assert not lib.smf_create(0, 1, 1, 0)
     assert b"nx, ny, K" in lib.smf_last_error()
-    assert not lib.smf_create(1 << 16, 1 << 16, 2, 0)
-    assert b"2^31" in lib.smf_last_error()
+    assert not lib.smf_create(1 << 15, 1 << 15, 1, 0)   # 2^30 nodes
+    assert b"2^30 - 2" in lib.smf_last_error()
     lib.smf_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.smf_solve(None, None, None) == -1
+
+
+def test_batch_arg_errors_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.smf_last_error.restype = ctypes.c_char_p
+    lib.smf_batch_create.restype = ctypes.c_void_p
+    arr = lambda *v: (ctypes.c_int32 * len(v))(*v)
+    assert not lib.smf_batch_create(0, arr(1), arr(1), arr(1), arr(0))
+    assert b"n >= 1" in lib.smf_last_error()
+    assert not lib.smf_batch_create(2, arr(4, 4), arr(4, 0), arr(8, 8), arr(1, 1))
+    assert b"volume 1" in lib.smf_last_error()
+    assert not lib.smf_batch_create(2, arr(4, 4), arr(4, 4), arr(8, 8), arr(1, -1))
+    assert b"volume 1" in lib.smf_last_error()
+    # three volumes of 32767^2 columns each: every volume fits, the batch does not
+    big = 32767
+    assert not lib.smf_batch_create(3, arr(big, big, big), arr(big, big, big), arr(1, 1, 1),
+                                    arr(0, 0, 0))
+    assert b"2^31 - 1 columns" in lib.smf_last_error()
+    for name in ("smf_batch_solve", "smf_batch_flow_values", "smf_batch_energies",
+                 "smf_batch_surfaces", "smf_batch_set_param", "smf_batch_get_stat"):
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_void_p] * (4 if name == "smf_batch_solve" else
+                                           3 if name in ("smf_batch_surfaces", "smf_batch_set_param",
+                                                         "smf_batch_get_stat") else 2)
+        assert fn(*([None] * len(fn.argtypes))) == -1, name
 
 
 def test_python_binding_lists_header_symbols():
     src = open(os.path.join(ROOT, "paper_2601_17026_amd", "smf.py")).read()
     for n in declared():
         assert n in src, n
+
+
+def test_tune_cache_roundtrip_without_gpu(tmp_path):
+    # the autotuner's cache: classes keyed by (ceil log2 K, min(delta, 4),
+    # floor log2 columns); file load, lookup, save and clear need no device
+    lib = ctypes.CDLL(LIB)
+    lib.smf_tune_lookup.argtypes = [ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_int64)]
+    lib.smf_tune_cache_load.argtypes = [ctypes.c_char_p]
+    lib.smf_tune_cache_save.argtypes = [ctypes.c_char_p]
+    lib.smf_last_error.restype = ctypes.c_char_p
+
+    def look(nx, ny, K, d):
+        out = ctypes.c_int64(-1)
+        assert lib.smf_tune_lookup(nx, ny, K, d, ctypes.byref(out)) == 0
+        return out.value
+
+    assert lib.smf_tune_cache_clear() == 0
+    assert look(128, 128, 100, 2) == 0
+    src = tmp_path / "tune.txt"
+    src.write_text("7 2 14 8 12345\n9 4 18 3 999\n")
+    assert lib.smf_tune_cache_load(str(src).encode()) == 0
+    assert look(128, 128, 100, 2) == 8      # K 100 -> 7 bits, 16384 columns -> 14
+    assert look(128, 128, 128, 2) == 8
+    assert look(128, 128, 129, 2) == 0      # K 129 -> 8 bits
+    assert look(128, 255, 100, 2) == 8      # 32640 columns -> 14
+    assert look(128, 256, 100, 2) == 0      # 32768 columns -> 15
+    assert look(512, 512, 384, 7) == 3      # delta above 4 shares the class of 4
+    dst = tmp_path / "out.txt"
+    assert lib.smf_tune_cache_save(str(dst).encode()) == 0
+    assert sorted(dst.read_text().split("\n")) == sorted(src.read_text().split("\n"))
+    assert lib.smf_tune_cache_load(str(tmp_path / "missing.txt").encode()) == -1
+    assert b"cannot open" in lib.smf_last_error()
+    out = ctypes.c_int64()
+    assert lib.smf_tune_lookup(0, 1, 1, 0, ctypes.byref(out)) == -1
+    assert lib.smf_tune_cache_clear() == 0
+    assert look(128, 128, 100, 2) == 0
+
+
+def test_tune_cache_env_file_without_gpu(tmp_path):
+    # SMF_TUNE_CACHE names a cache file that is read on first use
+    import subprocess
+    import sys
+    src = tmp_path / "tune.txt"
+    src.write_text("6 1 10 12 777\n")
+    code = ("import ctypes; lib = ctypes.CDLL(%r); out = ctypes.c_int64();"
+            "lib.smf_tune_lookup.argtypes = [ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_int64)];"
+            "assert lib.smf_tune_lookup(32, 32, 64, 1, ctypes.byref(out)) == 0;"
+            "print(out.value)") % LIB
+    env = dict(os.environ, SMF_TUNE_CACHE=str(src))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    assert r.stdout.strip() == "12"
