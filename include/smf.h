@@ -55,7 +55,8 @@ typedef struct smf_handle smf_handle;
 
 /* Allocates all solver state for one nx x ny x K volume with smoothness
  * bound delta (Section 1.2, the "edge interval") on the current device:
- * 32 bytes per node plus O(nx*ny).  Returns NULL on failure (see
+ * 32 bytes per node, 6 bits per node (rounded up to 64 heights) of
+ * breadth-first-search bit masks, plus O(nx*ny).  Returns NULL on failure (see
  * smf_last_error).  Requires nx, ny, K >= 1, delta >= 0,
  * nx*ny*K <= 2^30 - 2 (every finite distance label then stays below the
  * solver's reserved label values).  The handle is a batch of one volume:

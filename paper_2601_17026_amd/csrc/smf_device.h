@@ -67,7 +67,15 @@ struct Geom {
     unsigned long long *work;
     int *hist;              // n x hist_len: nodes per finite label, labels < hist_len
     int hist_len;
+    // Per-column bit masks of the running global relabel, one bit per node,
+    // word-major: word w (heights 64w..64w+63) of mask m of column p is
+    // bits[(m * max_nch + w) * Ptot + p], so that the columns of a wave read
+    // adjacent words.  Masks: kMaskFl + k (lateral arc in direction k carries
+    // flow), kMaskFd (down arc carries flow), kMaskAct (node holds excess).
+    unsigned long long *bits;
+    int max_nch;
 };
+constexpr int kMaskFl = 0, kMaskFd = 4, kMaskAct = 5, kMasks = 6;
 constexpr int kWorkSlots = 64, kWorkStride = 16;
 
 // Per-node solver state; each array holds Ntot int32, packed as above.

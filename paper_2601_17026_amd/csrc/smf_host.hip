@@ -36,6 +36,7 @@ void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, h
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
                       const int *CHin, int *Tout, int *LFout, int *CHout, hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, hipStream_t st);
+void launch_bfs_count(const Geom &g, const int *T, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st);
@@ -160,6 +161,7 @@ struct smf_handle {
     int *state = nullptr;         // 8 * Ntot int32
     int *H = nullptr;             // Ptot int32 surfaces
     int *bfs = nullptr;           // 12 * Ptot int32: two per-column BFS records (T, LF[4], changed)
+    unsigned long long *bits = nullptr;   // kMasks * max_nch * Ptot BFS bit-mask words
     unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
     int *hist = nullptr;                  // n x kHistLen label histograms (Geom::hist)
     unsigned long long *wmask = nullptr;  // 2 * Ptot work masks
@@ -198,7 +200,7 @@ static void release(smf_handle *h)
 {
     if (!h) return;
     void *dev[] = {h->inst_dev, h->col_inst, h->is_dev, h->part_dev, h->fill_dev, h->state, h->H,
-                   h->bfs, h->wcount, h->hist, h->wmask, h->wlist, h->scr};
+                   h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist, h->scr};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *pinned[] = {h->host, h->is_host, h->inst_up, h->part_up, h->fill_up};
@@ -229,6 +231,7 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     }
     std::vector<Inst> inst((size_t)n);
     long long Ptot = 0, Ntot = 0, max_nodes = 0;
+    int max_nch = 1;
     for (int i = 0; i < n; ++i) {
         if (nx[i] < 1 || ny[i] < 1 || K[i] < 1 || delta[i] < 0) {
             fail(SMF_ERR_ARG, "smf_batch_create: volume " + std::to_string(i) +
@@ -256,6 +259,7 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
         Ptot += P;
         Ntot += N;
         max_nodes = std::max(max_nodes, N);
+        max_nch = std::max(max_nch, I.nch);
         if (Ptot >= (1LL << 31)) {
             fail(SMF_ERR_RANGE, "smf_batch_create: more than 2^31 - 1 columns in the batch");
             return nullptr;
@@ -274,7 +278,8 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     if (hipGetDevice(&h->device) != hipSuccess || !dev_alloc(h->inst_dev, n) ||
         !dev_alloc(h->col_inst, P) || !dev_alloc(h->is_dev, n) || !dev_alloc(h->part_dev, n) ||
         !dev_alloc(h->fill_dev, n) || !dev_alloc(h->state, 8 * N) || !dev_alloc(h->H, P) ||
-        !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->wcount, 3 * kWorkSlots * kWorkStride) ||
+        !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||
+        !dev_alloc(h->wcount, 3 * kWorkSlots * kWorkStride) ||
         !dev_alloc(h->hist, (size_t)n * kHistLen) || !dev_alloc(h->wmask, 2 * P) ||
         !dev_alloc(h->wlist, 2 * P) || !dev_alloc(h->scr, 1) || !host_alloc(h->host, 1) ||
         !host_alloc(h->is_host, n) || !host_alloc(h->inst_up, n) || !host_alloc(h->part_up, n) ||
@@ -309,6 +314,8 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     g.work = h->wcount;
     g.hist = h->hist;
     g.hist_len = kHistLen;
+    g.bits = h->bits;
+    g.max_nch = max_nch;
     int *b = h->state;
     h->st.e = b;
     h->st.d = b + N;
@@ -380,6 +387,8 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
                 h->bfs_passes++;
             }
         }
+        // buffer L & 1 holds every column's threshold of level L
+        if (h->bfs_early_stop) launch_bfs_count(h->g, T[L & 1], s);
         HIP_TRY(hipGetLastError());
         int rc = sync_scratch(h, s);
         if (rc) return rc;

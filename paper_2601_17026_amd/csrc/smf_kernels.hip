@@ -188,6 +188,19 @@ __device__ __forceinline__ Col column_of(const Geom &g, int p, int ii)
 
 __device__ __forceinline__ Col column(const Geom &g, int p) { return column_of(g, p, g.col_inst[p]); }
 
+// Column of the volume `I` (already loaded) of index ii.
+__device__ __forceinline__ Col column_in(const Inst &I, int ii, int p)
+{
+    Col c;
+    c.ii = ii;
+    c.I = I;
+    c.pl = p - I.col_base;
+    c.x = c.pl / I.ny;
+    c.y = c.pl - c.x * I.ny;
+    c.base = (size_t)I.node_base + (size_t)c.pl * I.K;
+    return c;
+}
+
 // Same for a wave-uniform column: the volume table is read with scalar loads.
 __device__ __forceinline__ Col column_uniform(const Geom &g, int p)
 {
@@ -551,6 +564,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     long long worst = 0;   // largest excess word produced by an atomic add
     long long bytes = 0;   // algorithmic bytes moved by this lane
     int err = 0;
+    Inst cur;              // volume of the previous column (reloaded on a change)
+    int cur_ii = -1;
     // batches of up to 64 list entries per wave, sized so that every wave of
     // the grid gets one: lane i fetches entry i, then the wave works through
     // the batch one column at a time
@@ -558,6 +573,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int b0 = wave * bs; b0 < count; b0 += nwaves * bs) {
       const int myp = (lane < bs && b0 + lane < count) ? win.list[b0 + lane] : -1;
       const unsigned long long mym = myp >= 0 ? win.mask[myp] : 0ULL;
+      const int myii = myp >= 0 ? g.col_inst[myp] : 0;
       if (myp >= 0) win.mask[myp] = 0;
       unsigned long long myown = 0;
       unsigned long long todo = __ballot(mym != 0);
@@ -566,7 +582,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         todo &= todo - 1;
         const int p = uniform(__shfl(myp, src, kWave));
         const unsigned long long m = (unsigned long long)shfl64((long long)mym, src);
-        const Col col = column_uniform(g, p);
+        const int ii = uniform(__shfl(myii, src, kWave));
+        if (ii != cur_ii) {
+            cur = g.inst[ii];
+            cur_ii = ii;
+        }
+        const Col col = column_in(cur, ii, p);
         const int K = col.I.K, dl = col.I.delta, nch = col.I.nch, cpb = col.I.cpb;
         int q[4], dq[4];
         bool has[4];
@@ -736,10 +757,13 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
     VolSum<int> cnt(&g.is[0].active);
     VolSum<int> frozen(&g.is[0].gap_frozen);
     long long bytes = 0;
+    Inst cur;              // volume of the previous column (reloaded on a change)
+    int cur_ii = -1, gap = kInf;
     const int bs = min(kWave, max(1, (count + nwaves - 1) / nwaves));
     for (int b0 = wave * bs; b0 < count; b0 += nwaves * bs) {
       const int myp = (lane < bs && b0 + lane < count) ? win.list[b0 + lane] : -1;
       const unsigned long long mym = myp >= 0 ? win.mask[myp] : 0ULL;
+      const int myii = myp >= 0 ? g.col_inst[myp] : 0;
       if (myp >= 0) win.mask[myp] = 0;
       unsigned long long mynm = 0;
       unsigned long long todo = __ballot(mym != 0);
@@ -748,11 +772,16 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
         todo &= todo - 1;
         const int p = uniform(__shfl(myp, src, kWave));
         const unsigned long long m = (unsigned long long)shfl64((long long)mym, src);
-        const Col col = column_uniform(g, p);
+        const int ii = uniform(__shfl(myii, src, kWave));
+        if (ii != cur_ii) {
+            cur = g.inst[ii];
+            gap = g.is[ii].gap;
+            cur_ii = ii;
+        }
+        const Col col = column_in(cur, ii, p);
         const int K = col.I.K, dl = col.I.delta, nch = col.I.nch, cpb = col.I.cpb;
         cnt.to(col.ii);
         frozen.to(col.ii);
-        const int gap = g.is[col.ii].gap;
         int q[4], dq[4];
         bool has[4];
         neighbours(col, p, q, dq, has);
@@ -836,6 +865,20 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
 
 __device__ __forceinline__ int lat_head_of(int zp, int dl) { return zp == 0 ? 0 : zp - dl; }
 
+// Word w of bit mask m of column p.
+__device__ __forceinline__ unsigned long long mask_word(const Geom &g, int m, int w, int p)
+{
+    return g.bits[((size_t)m * g.max_nch + w) * g.Ptot + p];
+}
+
+// Bits [lo, hi) of the heights 64w..64w+63 (lo < 64(w+1), hi > 64w).
+__device__ __forceinline__ unsigned long long range_bits(int w, int lo, int hi)
+{
+    const int a = max(lo - kWave * w, 0), b = min(hi - kWave * w, kWave);
+    const unsigned long long upto = b >= kWave ? ~0ULL : ((1ULL << b) - 1ULL);
+    return upto & ~((1ULL << a) - 1ULL);
+}
+
 // Before level 1: clears the early-stop counters and the level-1 flag of
 // the volumes that take part, and forgets their known gap.
 __global__ void k_bfs_begin(Geom g)
@@ -852,7 +895,9 @@ __global__ void k_bfs_begin(Geom g)
 // Level 1, one wave per column.  Nodes that could not reach t before keep
 // kInf: new residual arcs only ever join nodes that reach t, so a node cut
 // off from t stays cut off.  Counts per volume the nodes with excess and a
-// finite label, and those of them labelled 1, for the early stop.
+// finite label, and those of them labelled 1, for the early stop, and
+// writes the column's bit masks (flows and excess do not change during the
+// search).
 __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *CH)
 {
     const int lane = lane_id();
@@ -860,7 +905,7 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
     const int Ptot = g.Ptot;
     int lo, hi;
     wave_columns(g, lo, hi);
-    VolSum<int> act(&g.is[0].bfs_active), lab_act(&g.is[0].bfs_labelled);
+    VolSum<int> act(&g.is[0].bfs_active);
     for (int p = lo; p < hi; ++p) {
         const Col col = column_uniform(g, p);
         if (!g.part[col.ii]) {
@@ -868,7 +913,6 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
             continue;
         }
         act.to(col.ii);
-        lab_act.to(col.ii);
         const int K = col.I.K;
         int t1 = K;
         int lf[4] = {K, K, K, K};
@@ -876,25 +920,34 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
             const int z = c * kWave + lane;
             const bool in = z < K;
             const size_t v = col.base + z;
-            int tsv = 0, ev = 0, dv = kInf;
+            int tsv = 0, ev = 0, dv = kInf, fdv = 0;
             int fv[4] = {0, 0, 0, 0};
             if (in) {
                 tsv = st.ts[v];
                 ev = st.e[v];
                 dv = st.d[v];
+                fdv = st.fd[v];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * Ntot + v];
             }
+            // the chunk's words of the bit masks, one mask per lane 0..5
+            unsigned long long wm[kMasks];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) wm[kMaskFl + k] = __ballot(in && fv[k] > 0);
+            wm[kMaskFd] = __ballot(in && fdv > 0);
+            wm[kMaskAct] = __ballot(in && ev > 0);
+            unsigned long long mine = 0;
+#pragma unroll
+            for (int m = 0; m < kMasks; ++m)
+                if (lane == m) mine = wm[m];
+            if (lane < kMasks) g.bits[((size_t)lane * g.max_nch + c) * Ptot + p] = mine;
             if (t1 == K) {
                 const unsigned long long sm = __ballot(in && tsv > 0);
                 if (sm) t1 = c * kWave + __ffsll((long long)sm) - 1;
             }
             const bool lab = in && z >= t1;
             if (in) st.d[v] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
-            if (in && ev > 0 && dv < kInf) {
-                ++act.acc;
-                if (lab) ++lab_act.acc;
-            }
+            if (in && ev > 0 && dv < kInf) ++act.acc;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (lf[k] < K) continue;
@@ -910,16 +963,37 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
         }
     }
     act.flush();
-    lab_act.flush();
 }
 
-// Level L -> L+1, one lane per column for the threshold arithmetic.  The
-// newly reached heights [cand, T) of the wave's 64 columns are then
-// labelled L+1 as one flattened list of (column, height) items, 64 per
+// Early-stop count: the nodes with excess among the heights [T(p), K) that
+// the search has labelled so far, per taking-part volume, from the excess
+// masks (one lane per column; bfs_labelled is cleared before).
+__global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict__ T)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int ii = 0, cnt = 0;
+    if (p < g.Ptot) {
+        ii = g.col_inst[p];
+        if (g.part[ii]) {
+            const Inst I = g.inst[ii];
+            const int t = T[p];
+            for (int w = t >> 6; w < I.nch; ++w)
+                cnt += __popcll(mask_word(g, kMaskAct, w, p) & range_bits(w, t, I.K));
+        }
+    }
+    wave_add_keyed(&g.is[0].bfs_labelled, ii, cnt, cnt > 0);
+}
+
+// Level L -> L+1, one lane per column.  The threshold arithmetic reads the
+// records of the column and its neighbours; the lowest flow-carrying
+// lateral arcs among the newly reached heights [cand, T) come from the
+// column's bit masks, so no per-node word is read.  The new ranges are then
+// labelled L+1: long ones by the whole wave, one column at a time, the
+// others as one flattened list of (column, height) items, 64 stores per
 // step, so a wave's time follows the number of nodes it labels rather than
-// its longest range.  Flow-carrying lateral arcs among them lower the
-// column's record with atomicMin.
-__global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, const int *__restrict__ Tin,
+// its longest range.
+__global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, int L,
+                                                   const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin,
                                                    const int *__restrict__ CHin, int *__restrict__ Tout,
                                                    int *__restrict__ LFout, int *__restrict__ CHout)
@@ -930,19 +1004,17 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
     // before every write of level L+1
     if (p < g.n) g.is[p].lvl_changed[(L + 1) % kLvlSlots] = 0;
     const int P = g.Ptot;
-    const size_t Ntot = (size_t)g.Ntot;
     const bool valid = p < P;
     bool self = false, near = false;
-    int T = 0, cand = 0, ii = 0, K = 0;
+    int T = 0, cand = 0, ii = 0;
     long long base = 0;
     int lf[4] = {0, 0, 0, 0};
     long long bytes = 0;
     if (valid) {
         const Col col = column(g, p);
         ii = col.ii;
-        K = col.I.K;
+        const int K = col.I.K, dl = col.I.delta;
         base = (long long)col.base;
-        const int dl = col.I.delta;
         int q[4];
         self = CHin[p] != 0;
         near = self;
@@ -970,10 +1042,24 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
                 const int lq = LFin[(size_t)(k ^ 1) * P + q[k]];
                 if (lq < K) cand = min(cand, lat_head_of(lq, dl));
             }
-            if (T >= 1 && T < K && st.fd[(size_t)base + T] > 0) cand = min(cand, T - 1);
+            if (T >= 1 && T < K && ((mask_word(g, kMaskFd, T >> 6, p) >> (T & 63)) & 1ULL))
+                cand = min(cand, T - 1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) lf[k] = LFin[(size_t)k * P + p];
-            bytes += 4 * 14;
+            bytes += 4 * 14 + (T >= 1 && T < K ? 8 : 0);
+            // lowest flow-carrying lateral arc per direction among the newly
+            // reached heights (an lf below T was found in an earlier word)
+            for (int w = cand >> 6; cand < T && w <= (T - 1) >> 6; ++w) {
+                if (lf[0] < T && lf[1] < T && lf[2] < T && lf[3] < T) break;
+                const unsigned long long r = range_bits(w, cand, T);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (lf[k] < T) continue;
+                    const unsigned long long fm = mask_word(g, kMaskFl + k, w, p) & r;
+                    if (fm) lf[k] = w * kWave + __ffsll((long long)fm) - 1;
+                }
+                bytes += 4 * 8;
+            }
         }
     }
     const bool need = valid && near && cand < T;
@@ -998,8 +1084,18 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
             if (pending && ii == k) pending = false;
         }
     }
-    // flattened labelling of the wave's new ranges
-    const int len = need ? T - cand : 0;
+    // labelling: ranges of 64 or more heights one column at a time by the
+    // whole wave (coalesced stores), the others as one flattened list
+    const int lab = L + 1;
+    const bool whole = need && T - cand >= kWave;
+    for (unsigned long long lm = __ballot(whole); lm; lm &= lm - 1) {
+        const int src = __ffsll((long long)lm) - 1;
+        const int lo = __shfl(cand, src, kWave), hi = __shfl(T, src, kWave);
+        const long long pbase = shfl64(base, src);
+        for (int z = lo + lane; z < hi; z += kWave) d[(size_t)pbase + z] = lab;
+        bytes += lane == 0 ? 4LL * (hi - lo) : 0;
+    }
+    const int len = need && !whole ? T - cand : 0;
     int incl = len;
     for (int off = 1; off < kWave; off <<= 1) {
         const int t = __shfl_up(incl, off, kWave);
@@ -1007,38 +1103,21 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, State st, int L, cons
     }
     const int excl = incl - len;
     const int total = __shfl(incl, kWave - 1, kWave);
-    const int lab = L + 1;
-    if (total > 0) {
-        __threadfence_block();   // the record stores above precede the atomicMin below
-        for (int i0 = 0; i0 < total; i0 += kWave) {
-            const int item = i0 + lane;
-            // owner: the last lane whose exclusive prefix is <= item
-            int o = 0;
-            for (int step = 32; step > 0; step >>= 1) {
-                const int c = o + step;
-                const int ex = __shfl(excl, c < kWave ? c : kWave - 1, kWave);
-                if (c < kWave && ex <= item) o = c;
-            }
-            const int pp = __shfl(p, o, kWave);
-            const int hi = __shfl(T, o, kWave);
-            const long long pbase = shfl64(base, o);
-            const int pii = __shfl(ii, o, kWave);
-            const int z = hi - 1 - (item - __shfl(excl, o, kWave));
-            bool act = false;
-            if (item < total) {
-                const size_t v = (size_t)pbase + z;
-                const int ev = st.e[v];
-                int fv[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * Ntot + v];
-                st.d[v] = lab;
-                act = ev > 0;
-                bytes += 24;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (fv[k] > 0) atomicMin(LFout + (size_t)k * P + pp, z);
-            }
-            wave_add_keyed(&g.is[0].bfs_labelled, pii, 1, act);
+    for (int i0 = 0; i0 < total; i0 += kWave) {
+        const int item = i0 + lane;
+        // owner: the last lane whose exclusive prefix is <= item
+        int o = 0;
+        for (int step = 32; step > 0; step >>= 1) {
+            const int c = o + step;
+            const int ex = __shfl(excl, c < kWave ? c : kWave - 1, kWave);
+            if (c < kWave && ex <= item) o = c;
+        }
+        const int hi = __shfl(T, o, kWave);
+        const long long pbase = shfl64(base, o);
+        const int z = hi - 1 - (item - __shfl(excl, o, kWave));
+        if (item < total) {
+            d[(size_t)pbase + z] = lab;
+            bytes += 4;
         }
     }
     if (g.count_work) count_bytes(g, 0, bytes);
@@ -1206,10 +1285,16 @@ void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, h
     hipLaunchKernelGGL(k_bfs_init, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, T, LF, CH);
 }
 
+void launch_bfs_count(const Geom &g, const int *T, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_field, dim3(blocks_for(g.n)), dim3(256), 0, st, g, &g.is[0].bfs_labelled, 1);
+    hipLaunchKernelGGL(k_bfs_count, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, T);
+}
+
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
                       const int *CHin, int *Tout, int *LFout, int *CHout, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv, L, Tin, LFin,
+    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv.d, L, Tin, LFin,
                        CHin, Tout, LFout, CHout);
 }
 
