@@ -138,6 +138,41 @@ struct VolSum {
     }
 };
 
+// Ends a per-volume sum in a kernel of 256-thread blocks that every thread
+// reaches: the four waves' last partial sums are combined in LDS and added
+// with one atomic per distinct volume of the block, so a counter takes a
+// few atomics per block rather than one per wave (atomics on one address
+// from many waves serialise).
+template <typename T>
+__device__ void block_flush(VolSum<T> &vs)
+{
+    __shared__ int vol[4];
+    __shared__ T sum[4];
+    const T part = wave_sum(vs.acc);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();   // an earlier call may still read the arrays
+    if (lane_id() == 0) {
+        vol[w] = (vs.cur >= 0 && part != 0) ? vs.cur : -1;
+        sum[w] = part;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / kWave;
+        for (int i = 0; i < nw; ++i) {
+            if (vol[i] < 0) continue;
+            T tot = sum[i];
+            for (int j = i + 1; j < nw; ++j)
+                if (vol[j] == vol[i]) {
+                    tot += sum[j];
+                    vol[j] = -1;
+                }
+            atomic_add(inst_field(vs.f0, vol[i]), tot);
+        }
+    }
+    vs.acc = 0;
+    vs.cur = -1;
+}
+
 // Adds a wave's algorithmic bytes (state words read or written, each access
 // counted once) to the solve counter of kernel class `cls`.
 __device__ __forceinline__ void count_bytes(const Geom &g, int cls, long long lane_bytes)
@@ -429,7 +464,7 @@ __global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geo
             for (int k = 0; k < 4; ++k) st.fl[(size_t)k * g.Ntot + v] = 0;
         }
     }
-    ts_sum.flush();
+    block_flush(ts_sum);
     if (bad) atomicOr(&s->err, kErrCostRange);
 }
 
@@ -832,8 +867,8 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
       wave_append(wout.list, wout.count, mynm != 0, myp);
     }
     if (g.count_work) count_bytes(g, 2, bytes);
-    cnt.flush();
-    frozen.flush();
+    block_flush(cnt);
+    block_flush(frozen);
 }
 
 // ---- global relabel: level-synchronous reverse breadth-first search -------
@@ -962,26 +997,43 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
             for (int k = 0; k < 4; ++k) LF[(size_t)k * Ptot + p] = lf[k];
         }
     }
-    act.flush();
+    block_flush(act);
 }
 
 // Early-stop count: the nodes with excess among the heights [T(p), K) that
 // the search has labelled so far, per taking-part volume, from the excess
-// masks (one lane per column; bfs_labelled is cleared before).
+// masks (bfs_labelled is cleared before).  A block takes a contiguous range
+// of columns, one lane per column per step, and adds per volume once.
 __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict__ T)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    int ii = 0, cnt = 0;
-    if (p < g.Ptot) {
-        ii = g.col_inst[p];
-        if (g.part[ii]) {
-            const Inst I = g.inst[ii];
-            const int t = T[p];
-            for (int w = t >> 6; w < I.nch; ++w)
-                cnt += __popcll(mask_word(g, kMaskAct, w, p) & range_bits(w, t, I.K));
+    const int per = (g.Ptot + gridDim.x - 1) / gridDim.x;
+    const int lo = min(g.Ptot, (int)blockIdx.x * per), hi = min(g.Ptot, lo + per);
+    VolSum<int> lab(&g.is[0].bfs_labelled);
+    for (int p0 = lo; p0 < hi; p0 += blockDim.x) {
+        const int p = p0 + threadIdx.x;
+        int ii = -1, cnt = 0;
+        if (p < hi) {
+            ii = g.col_inst[p];
+            if (g.part[ii]) {
+                const Inst I = g.inst[ii];
+                const int t = T[p];
+                for (int w = t >> 6; w < I.nch; ++w)
+                    cnt += __popcll(mask_word(g, kMaskAct, w, p) & range_bits(w, t, I.K));
+            }
+        }
+        // the lanes nearly always share one volume: keep a running sum, else
+        // add per volume now
+        const int first = uniform(ii);
+        if (__ballot(ii >= 0 && ii != first) == 0) {
+            if (first >= 0) {
+                lab.to(first);
+                lab.acc += cnt;
+            }
+        } else {
+            wave_add_keyed(&g.is[0].bfs_labelled, ii, cnt, ii >= 0 && cnt > 0);
         }
     }
-    wave_add_keyed(&g.is[0].bfs_labelled, ii, cnt, cnt > 0);
+    block_flush(lab);
 }
 
 // Level L -> L+1, one lane per column.  The threshold arithmetic reads the
@@ -1225,8 +1277,8 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Ge
             if (h >= 0) energy.acc += cost[(size_t)col.I.cost_base + (size_t)col.pl * col.I.K + h];
         }
     }
-    flow.flush();
-    energy.flush();
+    block_flush(flow);
+    block_flush(energy);
 }
 
 // ---- launchers --------------------------------------------------------------
@@ -1288,7 +1340,9 @@ void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, h
 void launch_bfs_count(const Geom &g, const int *T, hipStream_t st)
 {
     hipLaunchKernelGGL(k_zero_field, dim3(blocks_for(g.n)), dim3(256), 0, st, g, &g.is[0].bfs_labelled, 1);
-    hipLaunchKernelGGL(k_bfs_count, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, T);
+    unsigned b = blocks_for(g.Ptot);
+    if (b > 512) b = 512;
+    hipLaunchKernelGGL(k_bfs_count, dim3(b), dim3(256), 0, st, g, T);
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
