@@ -99,10 +99,16 @@ struct KernelTimer {
     {
         for (int i = 0; i < KC_COUNT; ++i) { ns[i] = 0; launches[i] = 0; }
     }
-    // Called after the stream has been synchronised.
+    // Adds the brackets whose end event has completed; the others stay
+    // pending (work may still be in flight behind a host poll).
     void collect()
     {
+        size_t keep = 0;
         for (auto &p : pending) {
+            if (hipEventQuery(p.b) != hipSuccess) {
+                pending[keep++] = p;
+                continue;
+            }
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
                 ns[p.kc] += 1e6 * (double)ms;
@@ -111,7 +117,7 @@ struct KernelTimer {
             pool.push_back(p.a);
             pool.push_back(p.b);
         }
-        pending.clear();
+        pending.resize(keep);
     }
     ~KernelTimer()
     {
@@ -144,6 +150,7 @@ struct TimedScope {
 };
 
 constexpr int kHistLen = 4096;            // labels tracked by the gap heuristic (LDS bins)
+constexpr int kSlotSweep = 0, kSlotBfs = 2, kSlotSync = 4, kSnapSlots = 5;
 constexpr long long kMaxInstNodes = (1LL << 30) - 2;   // finite labels stay below kUnl
 
 struct smf_handle {
@@ -168,7 +175,14 @@ struct smf_handle {
     int *wlist = nullptr;                 // 2 * Ptot work-list entries
     Scratch *scr = nullptr;
     // pinned host memory; each upload area is rewritten only after a stream
-    // synchronisation that follows its previous upload
+    // synchronisation that follows its previous upload.  Counter snapshots
+    // go to five slots: the sweep loop and the BFS loop each alternate
+    // between two (kSlotSweep, kSlotBfs) while the host polls one batch of
+    // work behind the device, and kSlotSync serves blocking reads; `host`
+    // and `is_host` point at the slot read last.
+    Scratch *host_buf[kSnapSlots] = {};
+    InstScratch *is_buf[kSnapSlots] = {};
+    hipEvent_t snap_ev[kSnapSlots] = {};
     Scratch *host = nullptr;
     InstScratch *is_host = nullptr;
     Inst *inst_up = nullptr;      // volume table upload
@@ -203,7 +217,14 @@ static void release(smf_handle *h)
                    h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist, h->scr};
     for (void *p : dev)
         if (p) (void)hipFree(p);
-    void *pinned[] = {h->host, h->is_host, h->inst_up, h->part_up, h->fill_up};
+    for (int i = 0; i < kSnapSlots; ++i)
+        if (h->snap_ev[i]) (void)hipEventSynchronize(h->snap_ev[i]);
+    for (int i = 0; i < kSnapSlots; ++i) {
+        if (h->host_buf[i]) (void)hipHostFree(h->host_buf[i]);
+        if (h->is_buf[i]) (void)hipHostFree(h->is_buf[i]);
+        if (h->snap_ev[i]) (void)hipEventDestroy(h->snap_ev[i]);
+    }
+    void *pinned[] = {h->inst_up, h->part_up, h->fill_up};
     for (void *p : pinned)
         if (p) (void)hipHostFree(p);
     delete h;
@@ -219,6 +240,15 @@ template <typename T>
 static bool host_alloc(T *&p, size_t count)
 {
     return hipHostMalloc((void **)&p, sizeof(T) * (count ? count : 1), hipHostMallocDefault) == hipSuccess;
+}
+
+static bool alloc_snapshots(smf_handle *h)
+{
+    for (int i = 0; i < kSnapSlots; ++i)
+        if (!host_alloc(h->host_buf[i], 1) || !host_alloc(h->is_buf[i], (size_t)h->n) ||
+            hipEventCreateWithFlags(&h->snap_ev[i], hipEventDisableTiming) != hipSuccess)
+            return false;
+    return true;
 }
 
 extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int32_t *ny,
@@ -281,9 +311,8 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
         !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||
         !dev_alloc(h->wcount, 3 * kWorkSlots * kWorkStride) ||
         !dev_alloc(h->hist, (size_t)n * kHistLen) || !dev_alloc(h->wmask, 2 * P) ||
-        !dev_alloc(h->wlist, 2 * P) || !dev_alloc(h->scr, 1) || !host_alloc(h->host, 1) ||
-        !host_alloc(h->is_host, n) || !host_alloc(h->inst_up, n) || !host_alloc(h->part_up, n) ||
-        !host_alloc(h->fill_up, n)) {
+        !dev_alloc(h->wlist, 2 * P) || !dev_alloc(h->scr, 1) || !host_alloc(h->inst_up, n) ||
+        !host_alloc(h->part_up, n) || !host_alloc(h->fill_up, n) || !alloc_snapshots(h)) {
         (void)hipGetLastError();
         release(h);
         fail(SMF_ERR_NOMEM, "smf_batch_create: device allocation of " +
@@ -337,19 +366,37 @@ extern "C" smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t del
 
 extern "C" void smf_destroy(smf_handle *h) { release(h); }
 
-// Copies the batch-wide and per-volume counters to the pinned mirrors and
-// waits for the stream.
-static int sync_scratch(smf_handle *h, hipStream_t s)
+// Enqueues a snapshot of the batch-wide and per-volume counters into pinned
+// slot `slot`, taken in stream order after the work enqueued so far.
+static int post_snapshot(smf_handle *h, hipStream_t s, int slot)
 {
-    HIP_TRY(hipMemcpyAsync(h->host, h->scr, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h->is_host, h->is_dev, sizeof(InstScratch) * h->n, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpyAsync(h->host_buf[slot], h->scr, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->is_buf[slot], h->is_dev, sizeof(InstScratch) * h->n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(h->snap_ev[slot], s));
+    return SMF_OK;
+}
+
+// Waits for the snapshot in `slot` and makes it the one `host` / `is_host`
+// show; reports the error flags it carries.
+static int wait_snapshot(smf_handle *h, int slot)
+{
+    HIP_TRY(hipEventSynchronize(h->snap_ev[slot]));
+    h->host = h->host_buf[slot];
+    h->is_host = h->is_buf[slot];
     h->timer.collect();
     if (h->host->err & kErrCostRange)
         return fail(SMF_ERR_RANGE, "smf_solve: a cost lies outside (-2^30, 2^30)");
     if (h->host->err & kErrOverflow)
         return fail(SMF_ERR_RANGE, "smf_solve: an int32 excess or flow counter overflowed");
     return SMF_OK;
+}
+
+// Blocking read of the counters after all work enqueued so far.
+static int sync_scratch(smf_handle *h, hipStream_t s)
+{
+    int rc = post_snapshot(h, s, kSlotSync);
+    return rc ? rc : wait_snapshot(h, kSlotSync);
 }
 
 // Global relabel of the volumes with part[i]: level 1 from the sink arcs,
@@ -377,7 +424,12 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         TimedScope ts(h->timer, KC_BFS_RESET, s);
         launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], s);   // level 1 lives in buffer 1
     }
-    int L = 1;
+    // The host reads the counters one batch of levels behind the device:
+    // batch k+1 is enqueued before batch k's snapshot is examined, so the
+    // device never waits for the host.  Levels after a volume's search has
+    // ended are no-ops for it, or label more nodes exactly.
+    int L = 1, slot = 0, Lsnap[2] = {0, 0};   // slot: 0 or 1 of this loop's pair
+    bool inflight = false;
     for (;;) {
         {
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
@@ -390,26 +442,35 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         // buffer L & 1 holds every column's threshold of level L
         if (h->bfs_early_stop) launch_bfs_count(h->g, T[L & 1], s);
         HIP_TRY(hipGetLastError());
-        int rc = sync_scratch(h, s);
+        int rc = post_snapshot(h, s, kSlotBfs + slot);
         if (rc) return rc;
-        // the last level launched produced level L
-        bool all = true;
-        for (int i = 0; i < n && all; ++i) {
-            if (!part[i]) continue;
-            const InstScratch &r = h->is_host[i];
-            const bool complete = !r.lvl_changed[(L - 1) % kLvlSlots];
-            const bool labelled = h->bfs_early_stop && r.bfs_labelled >= r.bfs_active;
-            all = complete || labelled;
-        }
-        if (all) {
-            for (int i = 0; i < n; ++i) {
-                const bool complete = !h->is_host[i].lvl_changed[(L - 1) % kLvlSlots];
-                h->fill_up[i] = !part[i] ? -1 : (complete ? kInf : L + 1);
+        Lsnap[slot] = L;
+        if (inflight) {
+            rc = wait_snapshot(h, kSlotBfs + (slot ^ 1));
+            if (rc) return rc;
+            // at that snapshot the last level launched had produced level Lp
+            const int Lp = Lsnap[slot ^ 1];
+            bool all = true;
+            for (int i = 0; i < n && all; ++i) {
+                if (!part[i]) continue;
+                const InstScratch &r = h->is_host[i];
+                const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
+                const bool labelled = h->bfs_early_stop && r.bfs_labelled >= r.bfs_active;
+                all = complete || labelled;
             }
-            break;
+            if (all) {
+                // levels <= L are complete now (the batch after the snapshot included)
+                for (int i = 0; i < n; ++i) {
+                    const bool complete = !h->is_host[i].lvl_changed[(Lp - 1) % kLvlSlots];
+                    h->fill_up[i] = !part[i] ? -1 : (complete ? kInf : L + 1);
+                }
+                break;
+            }
         }
+        inflight = true;
+        slot ^= 1;
         // every productive level lowers at least one threshold by >= 1
-        if ((int64_t)L > h->max_inst_nodes + 2 + h->bfs_poll_every)
+        if ((int64_t)L > h->max_inst_nodes + 2 + 2 * h->bfs_poll_every)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: breadth-first search did not settle");
     }
     HIP_TRY(hipMemcpyAsync(h->fill_dev, h->fill_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
@@ -461,16 +522,18 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
         launch_build(cost_dev, h->g, h->st, h->scr, s);
     }
     HIP_TRY(hipGetLastError());
-    int rc = sync_scratch(h, s);
-    if (rc) return rc;
     std::vector<char> all((size_t)n, 1), part((size_t)n, 0), done((size_t)n, 0);
-    rc = global_relabel(h, s, all);
+    int rc = global_relabel(h, s, all);
     if (rc) return rc;
 
     std::vector<int64_t> since((size_t)n, 0), period((size_t)n);
     for (int i = 0; i < n; ++i) period[i] = h->inst_period[i] > 0 ? h->inst_period[i] : h->relabel_period;
     // work lists: every column may hold excess anywhere before the first sweep
     launch_work_init(h->g, h->work[0], h->work[1], s);
+    // Sweeps are polled one batch behind, like the BFS levels: a batch
+    // enqueued after the volumes have finished finds empty work lists.
+    int slot = 0;
+    bool inflight = false;
     for (;;) {
         if (h->sweeps >= h->max_sweeps)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: sweep cap reached");
@@ -507,19 +570,25 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
             }
         }
         HIP_TRY(hipGetLastError());
-        rc = sync_scratch(h, s);
+        rc = post_snapshot(h, s, kSlotSweep + slot);
         if (rc) return rc;
-        bool finished = true;
-        int left = 0;
-        for (int i = 0; i < n; ++i) {
-            done[i] = h->is_host[i].active == 0;
-            finished = finished && done[i];
-            left += h->is_host[i].active;
+        if (inflight) {
+            rc = wait_snapshot(h, kSlotSweep + (slot ^ 1));
+            if (rc) return rc;
+            bool finished = true;
+            int left = 0;
+            for (int i = 0; i < n; ++i) {
+                done[i] = h->is_host[i].active == 0;
+                finished = finished && done[i];
+                left += h->is_host[i].active;
+            }
+            if (h->verbose)
+                fprintf(stderr, "smf: sweep %lld active %d columns %d\n", (long long)h->sweeps, left,
+                        h->host->count[0]);
+            if (finished) break;
         }
-        if (h->verbose)
-            fprintf(stderr, "smf: sweep %lld active %d columns %d\n", (long long)h->sweeps, left,
-                    h->host->count[0]);
-        if (finished) break;
+        inflight = true;
+        slot ^= 1;
     }
 
     {
@@ -567,12 +636,21 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     return SMF_OK;
 }
 
+// A failed solve may leave work and counter copies in flight; they are
+// drained before the call returns, so the handle can be reused or freed.
+static int solve_checked(smf_handle *h, const int32_t *cost_dev, const int64_t *off, hipStream_t s)
+{
+    const int rc = solve_batch(h, cost_dev, off, s);
+    if (rc != SMF_OK) (void)hipStreamSynchronize(s);
+    return rc;
+}
+
 extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
 {
     g_last_error.clear();
     if (!h || !cost_dev) return fail(SMF_ERR_ARG, "smf_solve: NULL handle or cost");
     if (h->n != 1) return fail(SMF_ERR_ARG, "smf_solve: the handle holds a batch; use smf_batch_solve");
-    return solve_batch(h, cost_dev, nullptr, (hipStream_t)stream);
+    return solve_checked(h, cost_dev, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int smf_batch_solve(smf_handle *h, const int32_t *packed_cost_dev,
@@ -584,7 +662,7 @@ extern "C" int smf_batch_solve(smf_handle *h, const int32_t *packed_cost_dev,
         for (int i = 0; i < h->n; ++i)
             if (offsets_host[i] < 0)
                 return fail(SMF_ERR_ARG, "smf_batch_solve: negative cost offset");
-    return solve_batch(h, packed_cost_dev, offsets_host, (hipStream_t)stream);
+    return solve_checked(h, packed_cost_dev, offsets_host, (hipStream_t)stream);
 }
 
 extern "C" int smf_flow_value(const smf_handle *h, int64_t *out)
