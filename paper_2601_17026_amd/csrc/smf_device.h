@@ -45,10 +45,11 @@ struct InstScratch {
     int bmax;            // max_p c(p, 0)
     int active;          // active nodes after the last relabel phase
     int bfs_active;      // nodes with excess and a finite label when the BFS starts
-    int bfs_labelled;    // ... of which the running BFS has labelled so far
+    int bfs_labelled[2]; // ... of which the running BFS has labelled so far, counted
+                         // at alternate host polls into alternate slots
     int gap;             // labels above `gap` cannot reach t (kInf: no gap known)
     int gap_frozen;      // active nodes cut off by the gap heuristic
-    int pad[6];
+    int pad[5];
     int lvl_changed[kLvlSlots];   // BFS level L labelled something: slot L % 64
 };
 
@@ -96,12 +97,17 @@ struct Work {
     int *count;                 // device counter of `list`
 };
 
-// Batch-wide device counters and flags.
+// Batch-wide device counters and flags.  The per-volume counters follow
+// them in the same allocation, kScratchHead bytes after the start, so one
+// copy snapshots both.
 struct Scratch {
     int err;             // kErr* bits
     int changed;         // a min-cut pass changed something
     int count[2];        // sizes of the two column work lists
 };
+constexpr int kScratchHead = 64;
+static_assert(sizeof(Scratch) <= kScratchHead, "Scratch must fit its header");
+static_assert(sizeof(InstScratch) % 8 == 0, "InstScratch keeps 8-byte alignment");
 
 // Lateral arcs kept by the solver: (p,z) -> (q, z - delta) for z > delta,
 // and (p,0) -> (q,0).  The arcs (p,z) -> (q,0), 1 <= z <= delta, are implied

@@ -28,19 +28,20 @@ namespace smf {
 void launch_init_scratch(const Geom &g, Scratch *s, hipStream_t st);
 void launch_set_int(int *p, int v, hipStream_t st);
 void launch_fill(int *a, long long n, int v, hipStream_t st);
-void launch_zero_field(const Geom &g, int *f0, bool only_part, hipStream_t st);
 void launch_work_init(const Geom &g, const Work &a, const Work &b, hipStream_t st);
 void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st);
 void launch_bfs_begin(const Geom &g, hipStream_t st);
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, hipStream_t st);
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, int c0, int c1,
+                     hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *CHin, int *Tout, int *LFout, int *CHout, hipStream_t st);
-void launch_bfs_fixup(const Geom &g, const State &sv, hipStream_t st);
-void launch_bfs_count(const Geom &g, const int *T, hipStream_t st);
+                      const int *CHin, int *Tout, int *LFout, int *CHout, int c0, int c1,
+                      hipStream_t st);
+void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
+void launch_bfs_count(const Geom &g, const int *T, int slot, int c0, int c1, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st);
-void launch_compact(const Geom &g, const Work &w, hipStream_t st);
+void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st);
 void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
@@ -162,6 +163,7 @@ struct smf_handle {
     // device memory
     Inst *inst_dev = nullptr;
     int *col_inst = nullptr;      // Ptot
+    char *cnt_dev = nullptr;      // Scratch, then n InstScratch (kScratchHead offset)
     InstScratch *is_dev = nullptr;
     int *part_dev = nullptr;      // n: volume takes part in the running global relabel
     int *fill_dev = nullptr;      // n: fixup label of the running global relabel (-1: none)
@@ -192,7 +194,7 @@ struct smf_handle {
     Work work[2]{};               // push reads work[0] and writes work[1]; relabel the reverse
     unsigned long long work_bytes[3] = {};  // device byte counters after the last solve
     // parameters
-    int64_t relabel_period = 6;
+    int64_t relabel_period = 4;
     std::vector<int64_t> inst_period;       // per volume; 0: relabel_period
     int64_t max_sweeps = 2000000;
     int64_t poll_every = 1;
@@ -213,15 +215,14 @@ struct smf_handle {
 static void release(smf_handle *h)
 {
     if (!h) return;
-    void *dev[] = {h->inst_dev, h->col_inst, h->is_dev, h->part_dev, h->fill_dev, h->state, h->H,
-                   h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist, h->scr};
+    void *dev[] = {h->inst_dev, h->col_inst, h->cnt_dev, h->part_dev, h->fill_dev, h->state, h->H,
+                   h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     for (int i = 0; i < kSnapSlots; ++i)
         if (h->snap_ev[i]) (void)hipEventSynchronize(h->snap_ev[i]);
     for (int i = 0; i < kSnapSlots; ++i) {
         if (h->host_buf[i]) (void)hipHostFree(h->host_buf[i]);
-        if (h->is_buf[i]) (void)hipHostFree(h->is_buf[i]);
         if (h->snap_ev[i]) (void)hipEventDestroy(h->snap_ev[i]);
     }
     void *pinned[] = {h->inst_up, h->part_up, h->fill_up};
@@ -242,12 +243,21 @@ static bool host_alloc(T *&p, size_t count)
     return hipHostMalloc((void **)&p, sizeof(T) * (count ? count : 1), hipHostMallocDefault) == hipSuccess;
 }
 
+// Bytes of the counter block: Scratch, then the per-volume counters.
+static size_t counter_bytes(int n) { return kScratchHead + sizeof(InstScratch) * (size_t)n; }
+
 static bool alloc_snapshots(smf_handle *h)
 {
-    for (int i = 0; i < kSnapSlots; ++i)
-        if (!host_alloc(h->host_buf[i], 1) || !host_alloc(h->is_buf[i], (size_t)h->n) ||
-            hipEventCreateWithFlags(&h->snap_ev[i], hipEventDisableTiming) != hipSuccess)
+    for (int i = 0; i < kSnapSlots; ++i) {
+        char *b = nullptr;
+        if (!host_alloc(b, counter_bytes(h->n)) ||
+            hipEventCreateWithFlags(&h->snap_ev[i], hipEventDisableTiming) != hipSuccess) {
+            if (b) h->host_buf[i] = (Scratch *)b;
             return false;
+        }
+        h->host_buf[i] = (Scratch *)b;
+        h->is_buf[i] = (InstScratch *)(b + kScratchHead);
+    }
     return true;
 }
 
@@ -306,12 +316,12 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     h->inst_period.assign((size_t)n, 0);
     const size_t P = (size_t)Ptot, N = (size_t)Ntot;
     if (hipGetDevice(&h->device) != hipSuccess || !dev_alloc(h->inst_dev, n) ||
-        !dev_alloc(h->col_inst, P) || !dev_alloc(h->is_dev, n) || !dev_alloc(h->part_dev, n) ||
+        !dev_alloc(h->col_inst, P) || !dev_alloc(h->cnt_dev, counter_bytes(n)) || !dev_alloc(h->part_dev, n) ||
         !dev_alloc(h->fill_dev, n) || !dev_alloc(h->state, 8 * N) || !dev_alloc(h->H, P) ||
         !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||
         !dev_alloc(h->wcount, 3 * kWorkSlots * kWorkStride) ||
         !dev_alloc(h->hist, (size_t)n * kHistLen) || !dev_alloc(h->wmask, 2 * P) ||
-        !dev_alloc(h->wlist, 2 * P) || !dev_alloc(h->scr, 1) || !host_alloc(h->inst_up, n) ||
+        !dev_alloc(h->wlist, 2 * P) || !host_alloc(h->inst_up, n) ||
         !host_alloc(h->part_up, n) || !host_alloc(h->fill_up, n) || !alloc_snapshots(h)) {
         (void)hipGetLastError();
         release(h);
@@ -330,6 +340,8 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
         fail(SMF_ERR_HIP, "smf_batch_create: upload of the volume table failed");
         return nullptr;
     }
+    h->scr = (Scratch *)h->cnt_dev;
+    h->is_dev = (InstScratch *)(h->cnt_dev + kScratchHead);
     Geom &g = h->g;
     g.n = n;
     g.Ptot = (int)Ptot;
@@ -370,9 +382,7 @@ extern "C" void smf_destroy(smf_handle *h) { release(h); }
 // slot `slot`, taken in stream order after the work enqueued so far.
 static int post_snapshot(smf_handle *h, hipStream_t s, int slot)
 {
-    HIP_TRY(hipMemcpyAsync(h->host_buf[slot], h->scr, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h->is_buf[slot], h->is_dev, sizeof(InstScratch) * h->n,
-                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->host_buf[slot], h->cnt_dev, counter_bytes(h->n), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(h->snap_ev[slot], s));
     return SMF_OK;
 }
@@ -414,37 +424,48 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     int *T[2] = {h->bfs, h->bfs + 5 * P};
     int *LF[2] = {h->bfs + P, h->bfs + 6 * P};
     int *CH[2] = {h->bfs + 10 * P, h->bfs + 11 * P};
+    // the searches' launches cover the columns [c0, c1) spanned by the
+    // volumes that take part (volumes are packed in order)
+    int c0 = h->g.Ptot, c1 = 0;
     for (int i = 0; i < n; ++i) {
         h->part_up[i] = part[i] ? 1 : 0;
-        if (part[i]) h->reset_nodes += h->inst[i].N;
+        if (part[i]) {
+            h->reset_nodes += h->inst[i].N;
+            c0 = std::min(c0, h->inst[i].col_base);
+            c1 = std::max(c1, h->inst[i].col_base + h->inst[i].P);
+        }
     }
+    if (c0 >= c1) return SMF_OK;
     HIP_TRY(hipMemcpyAsync(h->part_dev, h->part_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
     launch_bfs_begin(h->g, s);
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], s);   // level 1 lives in buffer 1
+        launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], c0, c1, s);   // level 1 lives in buffer 1
     }
     // The host reads the counters one batch of levels behind the device:
     // batch k+1 is enqueued before batch k's snapshot is examined, so the
     // device never waits for the host.  Levels after a volume's search has
     // ended are no-ops for it, or label more nodes exactly.
-    int L = 1, slot = 0, Lsnap[2] = {0, 0};   // slot: 0 or 1 of this loop's pair
+    int L = 1, slot = 0, Lsnap[2] = {0, 0}, Csnap[2] = {0, 0};   // slot: 0 or 1 of this loop's pair
+    int npoll = 0;
     bool inflight = false;
     for (;;) {
         {
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
             for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L) {
                 launch_bfs_level(h->g, h->st, L, T[L & 1], LF[L & 1], CH[L & 1], T[(L + 1) & 1],
-                                 LF[(L + 1) & 1], CH[(L + 1) & 1], s);
+                                 LF[(L + 1) & 1], CH[(L + 1) & 1], c0, c1, s);
                 h->bfs_passes++;
             }
         }
-        // buffer L & 1 holds every column's threshold of level L
-        if (h->bfs_early_stop) launch_bfs_count(h->g, T[L & 1], s);
+        // buffer L & 1 holds every column's threshold of level L; the count
+        // of this poll goes to bfs_labelled[npoll & 1]
+        if (h->bfs_early_stop) launch_bfs_count(h->g, T[L & 1], npoll & 1, c0, c1, s);
         HIP_TRY(hipGetLastError());
         int rc = post_snapshot(h, s, kSlotBfs + slot);
         if (rc) return rc;
         Lsnap[slot] = L;
+        Csnap[slot] = npoll++ & 1;
         if (inflight) {
             rc = wait_snapshot(h, kSlotBfs + (slot ^ 1));
             if (rc) return rc;
@@ -455,7 +476,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
                 if (!part[i]) continue;
                 const InstScratch &r = h->is_host[i];
                 const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
-                const bool labelled = h->bfs_early_stop && r.bfs_labelled >= r.bfs_active;
+                const bool labelled = h->bfs_early_stop && r.bfs_labelled[Csnap[slot ^ 1]] >= r.bfs_active;
                 all = complete || labelled;
             }
             if (all) {
@@ -476,12 +497,16 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     HIP_TRY(hipMemcpyAsync(h->fill_dev, h->fill_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_fixup(h->g, h->st, s);
+        launch_bfs_fixup(h->g, h->st, c0, c1, s);
     }
     if (h->verbose) {
         int npart = 0, act = 0, lab = 0;
         for (int i = 0; i < n; ++i)
-            if (part[i]) { ++npart; act += h->is_host[i].bfs_active; lab += h->is_host[i].bfs_labelled; }
+            if (part[i]) {
+                ++npart;
+                act += h->is_host[i].bfs_active;
+                lab += std::max(h->is_host[i].bfs_labelled[0], h->is_host[i].bfs_labelled[1]);
+            }
         fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d volumes, %d levels, active %d, labelled %d\n",
                 (long long)h->global_relabels, (long long)h->sweeps, npart, L - 1, act, lab);
     }
@@ -549,14 +574,13 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
                 for (int i = 0; i < n; ++i)
                     if (part[i]) since[i] = 0;
             }
-            launch_set_int(h->work[1].count, 0, s);
+            // push clears work[1]'s list size; compaction clears work[0]'s
+            // and the active counts that the relabel phase fills
             {
                 TimedScope ts(h->timer, KC_PUSH, s);
                 launch_push(h->g, h->st, h->work[0], h->work[1], h->scr, (h->sweeps & 1) == 0, s);
             }
-            launch_compact(h->g, h->work[1], s);
-            launch_set_int(h->work[0].count, 0, s);
-            launch_zero_field(h->g, &h->is_dev[0].active, false, s);
+            launch_compact(h->g, h->work[1], h->work[0].count, s);
             {
                 TimedScope ts(h->timer, KC_RELABEL, s);
                 launch_relabel(h->g, h->st, h->work[1], h->work[0], s);

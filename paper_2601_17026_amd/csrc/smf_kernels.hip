@@ -190,15 +190,20 @@ __device__ __forceinline__ int add_flow(int f, long long a, int &err)
     return (int)r;
 }
 
-// Contiguous share [lo, hi) of the global columns for the wave-per-column
+// Contiguous share [lo, hi) of the columns [c0, c1) for the wave-per-column
 // kernels, so that a wave meets few volume boundaries.
-__device__ __forceinline__ void wave_columns(const Geom &g, int &lo, int &hi)
+__device__ __forceinline__ void wave_range(int c0, int c1, int &lo, int &hi)
 {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int nwaves = gridDim.x * blockDim.x / kWave;
-    const int per = (g.Ptot + nwaves - 1) / nwaves;
-    lo = min(g.Ptot, wave * per);
-    hi = min(g.Ptot, lo + per);
+    const int per = (c1 - c0 + nwaves - 1) / nwaves;
+    lo = min(c1, c0 + wave * per);
+    hi = min(c1, lo + per);
+}
+
+__device__ __forceinline__ void wave_columns(const Geom &g, int &lo, int &hi)
+{
+    wave_range(0, g.Ptot, lo, hi);
 }
 
 // Geometry of the column's volume, with the column's local coordinates.
@@ -359,7 +364,7 @@ __global__ void k_init_scratch(Geom g, Scratch *s)
         r.bmax = INT_MIN;
         r.active = 0;
         r.bfs_active = 0;
-        r.bfs_labelled = 0;
+        r.bfs_labelled[0] = r.bfs_labelled[1] = 0;
         r.gap = kInf;
         r.gap_frozen = 0;
     }
@@ -377,15 +382,6 @@ __global__ void k_fill(int *a, long long n, int v)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = v;
-}
-
-// Clears an int field of the per-volume counters (`f0`: the field of
-// volume 0) of every volume, or only of those that take part in the
-// running global relabel.
-__global__ void k_zero_field(Geom g, int *f0, int only_part)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < g.n && (!only_part || g.part[i])) *inst_field(f0, i) = 0;
 }
 
 // Work lists before the first sweep: every column, every chunk group.
@@ -493,11 +489,15 @@ __device__ __forceinline__ void mark_mask(const Work &w, int q, unsigned long lo
     atomicOr(w.mask + q, bits);
 }
 
-// Column list of every column with a non-empty work mask.
-__global__ __launch_bounds__(256) void k_compact(Work w, int P)
+// Column list of every column with a non-empty work mask.  Also clears the
+// counters that the relabel phase after it fills: the size of its output
+// list and the per-volume active counts.
+__global__ __launch_bounds__(256) void k_compact(Geom g, Work w, int *next_count)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool want = p < P && w.mask[p] != 0;
+    if (p == 0) *next_count = 0;
+    if (p < g.n) g.is[p].active = 0;
+    const bool want = p < g.Ptot && w.mask[p] != 0;
     wave_append(w.list, w.count, want, p);
 }
 
@@ -596,6 +596,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int nwaves = gridDim.x * blockDim.x / kWave;
     const size_t Ntot = (size_t)g.Ntot;
     const int count = *win.count;
+    // the list of wout is built by the compaction after this phase
+    if (blockIdx.x == 0 && threadIdx.x == 0) *wout.count = 0;
     long long worst = 0;   // largest excess word produced by an atomic add
     long long bytes = 0;   // algorithmic bytes moved by this lane
     int err = 0;
@@ -921,7 +923,7 @@ __global__ void k_bfs_begin(Geom g)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < g.n && g.part[i]) {
         g.is[i].bfs_active = 0;
-        g.is[i].bfs_labelled = 0;
+        g.is[i].bfs_labelled[0] = g.is[i].bfs_labelled[1] = 0;
         g.is[i].gap = kInf;
         g.is[i].lvl_changed[1] = 0;
     }
@@ -933,13 +935,14 @@ __global__ void k_bfs_begin(Geom g)
 // finite label, and those of them labelled 1, for the early stop, and
 // writes the column's bit masks (flows and excess do not change during the
 // search).
-__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *CH)
+__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *CH,
+                                                  int c0, int c1)
 {
     const int lane = lane_id();
     const size_t Ntot = (size_t)g.Ntot;
     const int Ptot = g.Ptot;
     int lo, hi;
-    wave_columns(g, lo, hi);
+    wave_range(c0, c1, lo, hi);
     VolSum<int> act(&g.is[0].bfs_active);
     for (int p = lo; p < hi; ++p) {
         const Col col = column_uniform(g, p);
@@ -1004,11 +1007,16 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
 // the search has labelled so far, per taking-part volume, from the excess
 // masks (bfs_labelled is cleared before).  A block takes a contiguous range
 // of columns, one lane per column per step, and adds per volume once.
-__global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict__ T)
+__global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict__ T, int slot,
+                                                   int c0, int c1)
 {
-    const int per = (g.Ptot + gridDim.x - 1) / gridDim.x;
-    const int lo = min(g.Ptot, (int)blockIdx.x * per), hi = min(g.Ptot, lo + per);
-    VolSum<int> lab(&g.is[0].bfs_labelled);
+    // this call adds into slot `slot`, which the previous call cleared; it
+    // clears the other one for the next call
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < g.n; i += blockDim.x) g.is[i].bfs_labelled[slot ^ 1] = 0;
+    const int per = (c1 - c0 + gridDim.x - 1) / gridDim.x;
+    const int lo = min(c1, c0 + (int)blockIdx.x * per), hi = min(c1, lo + per);
+    VolSum<int> lab(&g.is[0].bfs_labelled[slot]);
     for (int p0 = lo; p0 < hi; p0 += blockDim.x) {
         const int p = p0 + threadIdx.x;
         int ii = -1, cnt = 0;
@@ -1030,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
                 lab.acc += cnt;
             }
         } else {
-            wave_add_keyed(&g.is[0].bfs_labelled, ii, cnt, ii >= 0 && cnt > 0);
+            wave_add_keyed(&g.is[0].bfs_labelled[slot], ii, cnt, ii >= 0 && cnt > 0);
         }
     }
     block_flush(lab);
@@ -1048,15 +1056,17 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, 
                                                    const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin,
                                                    const int *__restrict__ CHin, int *__restrict__ Tout,
-                                                   int *__restrict__ LFout, int *__restrict__ CHout)
+                                                   int *__restrict__ LFout, int *__restrict__ CHout,
+                                                   int c0, int c1)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = c0 + t;
     const int lane = lane_id();
     // the flags of the next level are cleared here; stream order puts this
     // before every write of level L+1
-    if (p < g.n) g.is[p].lvl_changed[(L + 1) % kLvlSlots] = 0;
+    if (t < g.n) g.is[t].lvl_changed[(L + 1) % kLvlSlots] = 0;
     const int P = g.Ptot;
-    const bool valid = p < P;
+    const bool valid = p < c1;
     bool self = false, near = false;
     int T = 0, cand = 0, ii = 0;
     long long base = 0;
@@ -1178,11 +1188,11 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, 
 // End of a global relabel: nodes the search did not reach get the volume's
 // fill label (kInf when its search ran to completion, else the first level
 // it did not finish, which is a valid lower bound of their distance).
-__global__ __launch_bounds__(256) void k_bfs_fixup(Geom g, int *d)
+__global__ __launch_bounds__(256) void k_bfs_fixup(Geom g, int *d, int c0, int c1)
 {
     const int lane = lane_id();
     int lo, hi;
-    wave_columns(g, lo, hi);
+    wave_range(c0, c1, lo, hi);
     for (int p = lo; p < hi; ++p) {
         const Col col = column_uniform(g, p);
         const int fill = g.fill[col.ii];
@@ -1311,11 +1321,6 @@ void launch_fill(int *a, long long n, int v, hipStream_t st)
     hipLaunchKernelGGL(k_fill, dim3(b), dim3(256), 0, st, a, n, v);
 }
 
-void launch_zero_field(const Geom &g, int *f0, bool only_part, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_zero_field, dim3(blocks_for(g.n)), dim3(256), 0, st, g, f0, only_part ? 1 : 0);
-}
-
 void launch_work_init(const Geom &g, const Work &a, const Work &b, hipStream_t st)
 {
     hipLaunchKernelGGL(k_work_init, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, a, b);
@@ -1332,29 +1337,39 @@ void launch_bfs_begin(const Geom &g, hipStream_t st)
     hipLaunchKernelGGL(k_bfs_begin, dim3(blocks_for(g.n)), dim3(256), 0, st, g);
 }
 
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, hipStream_t st)
+// Grid of the wave-per-column kernels over the columns [c0, c1).
+static inline unsigned range_wave_blocks(int c0, int c1)
 {
-    hipLaunchKernelGGL(k_bfs_init, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, T, LF, CH);
+    long long want = ((long long)c1 - c0 + 3) / 4;
+    return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
 }
 
-void launch_bfs_count(const Geom &g, const int *T, hipStream_t st)
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, int c0, int c1,
+                     hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero_field, dim3(blocks_for(g.n)), dim3(256), 0, st, g, &g.is[0].bfs_labelled, 1);
-    unsigned b = blocks_for(g.Ptot);
+    hipLaunchKernelGGL(k_bfs_init, dim3(range_wave_blocks(c0, c1)), dim3(256), 0, st, g, sv, T, LF,
+                       CH, c0, c1);
+}
+
+void launch_bfs_count(const Geom &g, const int *T, int slot, int c0, int c1, hipStream_t st)
+{
+    unsigned b = blocks_for(c1 - c0);
     if (b > 512) b = 512;
-    hipLaunchKernelGGL(k_bfs_count, dim3(b), dim3(256), 0, st, g, T);
+    hipLaunchKernelGGL(k_bfs_count, dim3(b), dim3(256), 0, st, g, T, slot, c0, c1);
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *CHin, int *Tout, int *LFout, int *CHout, hipStream_t st)
+                      const int *CHin, int *Tout, int *LFout, int *CHout, int c0, int c1,
+                      hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv.d, L, Tin, LFin,
-                       CHin, Tout, LFout, CHout);
+    const long long n = (long long)c1 - c0 > g.n ? (long long)c1 - c0 : g.n;
+    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(n)), dim3(256), 0, st, g, sv.d, L, Tin, LFin,
+                       CHin, Tout, LFout, CHout, c0, c1);
 }
 
-void launch_bfs_fixup(const Geom &g, const State &sv, hipStream_t st)
+void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_fixup, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv.d);
+    hipLaunchKernelGGL(k_bfs_fixup, dim3(range_wave_blocks(c0, c1)), dim3(256), 0, st, g, sv.d, c0, c1);
 }
 
 void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st)
@@ -1375,9 +1390,10 @@ void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wo
         hipLaunchKernelGGL(k_push<false>, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
 }
 
-void launch_compact(const Geom &g, const Work &w, hipStream_t st)
+void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, w, g.Ptot);
+    const long long n = g.Ptot > g.n ? g.Ptot : g.n;
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n)), dim3(256), 0, st, g, w, next_count);
 }
 
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st)
