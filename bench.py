@@ -54,7 +54,35 @@ def parse():
                     help="columns per side of the oracle's CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default relabel period instead of running the autotuner")
+    ap.add_argument("--counters-summary", metavar="DIR",
+                    help="only summarise a rocprofv3 --pmc output directory: mean counter "
+                         "values per dispatch of every kernel, one JSON line per kernel")
     return ap.parse_args()
+
+
+def counters_summary(path):
+    """Mean per-dispatch values of every counter of a rocprofv3 --pmc run."""
+    import collections
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        sys.exit(f"bench.py: no counter_collection.csv under {path}")
+    total = collections.defaultdict(lambda: collections.defaultdict(float))
+    dispatches = collections.defaultdict(set)
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                name = r["Kernel_Name"].split("(")[0]
+                total[name][r["Counter_Name"]] += float(r["Counter_Value"])
+                dispatches[name].add(r["Dispatch_Id"])
+    for name in sorted(total, key=lambda k: -sum(total[k].values())):
+        n = len(dispatches[name])
+        print(json.dumps({"kernel": name, "dispatches": n,
+                          "per_dispatch": {c: v / n for c, v in sorted(total[name].items())}}))
 
 
 def copy_probe():
@@ -88,6 +116,7 @@ def stored_traffic(kernel: str):
     return ent.get("hbm_bytes_per_launch")
 
 
+
 def cpu_baseline(cost, delta, crop):
     import numpy as np
 
@@ -118,6 +147,16 @@ def batched_leg(args, torch, smf, synth, stream):
     plain = [smf.Solver(*sh) for sh in shapes]
     offs = batch.offsets
     views = [packed[o:o + v.size].view(v.shape) for o, v in zip(offs, vols)]
+
+    # the autotuner picks each volume class's relabel period (set-up, not
+    # timed); the batch and the plain solves both use its choices
+    t0 = time.perf_counter()
+    if not args.no_tune:
+        smf.autotune(batch, packed, stream=stream)
+        for s in plain:
+            smf.tune_apply(s)
+    t_tune = time.perf_counter() - t0
+    periods = batch.stat_per_volume("relabel_period")
 
     batch.solve(packed, stream=stream)          # warm-up
     torch.cuda.synchronize()
@@ -152,6 +191,8 @@ def batched_leg(args, torch, smf, synth, stream):
         "volumes": len(shapes),
         "voxels": V,
         "batch_sweeps": sweeps,
+        "autotune_seconds": round(t_tune, 2),
+        "relabel_periods": {str(p): periods.count(p) for p in sorted(set(periods))},
         "flows_equal_plain": same,
         "workload": "64 volumes, nx, ny, K ~ U{64..256}, delta ~ U{1,2,3}, two layered "
                     "horizons, sigma 0.4, costs 0..255 (per-volume seeds)",
@@ -160,6 +201,9 @@ def batched_leg(args, torch, smf, synth, stream):
 
 def main():
     args = parse()
+    if args.counters_summary:
+        counters_summary(args.counters_summary)
+        return
     if args.copy_probe:
         copy_probe()
         return
@@ -180,6 +224,13 @@ def main():
     c = torch.from_numpy(cost).to(dev)
     stream = torch.cuda.current_stream()
     solver = smf.Solver(nx, ny, K, delta)
+    tune_s = 0.0
+    if not args.no_tune:
+        # the autotuner times the candidate relabel periods (set-up, not timed)
+        t0 = time.perf_counter()
+        smf.autotune(solver, c, stream=stream)
+        tune_s = time.perf_counter() - t0
+    period = solver.stat_per_volume("relabel_period")[0]
 
     # warm-up solves time every kernel class; the class with the most time is
     # the dominant kernel of the roofline
@@ -258,7 +309,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "nx": nx, "ny": ny, "K": K, "delta": delta,
-                   "voxels": V, "mode": "plain"},
+                   "voxels": V, "mode": "plain", "relabel_period": period,
+                   "autotune_seconds": round(tune_s, 2)},
         "roofline": roof,
         "result": {"flow": flow, "energy": energy, "surface_sha256": surface_sha},
         "per_step": {"sweeps": sweeps / args.steps, "global_relabels": relabels / args.steps,
