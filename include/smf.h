@@ -137,7 +137,8 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
                      int32_t *flow_down_dev, int32_t *flow_lat_dev, void *stream);
 
 /* Tuning and limits.  Keys:
- *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1;
+ *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1,
+ *                        default 4;
  *                        for a batch: of every volume, replacing any per-volume
  *                        periods)
  *   "max_sweeps"      -- sweep cap before SMF_ERR_NOT_CONVERGED (>= 1)
@@ -148,6 +149,10 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *                        tracked); 0 turns it off (default 0)
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
+ *   "bfs_stop_permille" -- with bfs_early_stop, end a global relabel once
+ *                        this many thousandths of the nodes with excess are
+ *                        labelled (1..1000, default 1000); the others keep
+ *                        the first unfinished level, a valid lower bound
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
  *   "count_work"      -- 1: kernels count their algorithmic bytes ("bytes.<class>"
  *                        statistics of bfs, push, relabel; one atomic per wave
@@ -161,8 +166,10 @@ int smf_set_param(smf_handle *h, const char *key, int64_t value);
 
 /* Per-volume tuning of a batch: `values` is a host array of n int64.
  * Key "relabel_period": sweeps between global relabels of each volume
- * (0: the handle's relabel_period).  SMF_ERR_ARG for other keys or
- * negative values. */
+ * (0: the handle's relabel_period).  A search starts once some volume's
+ * period has come round, and every volume at least halfway through its own
+ * period joins it, so volumes of different periods share searches.
+ * SMF_ERR_ARG for other keys or negative values. */
 int smf_batch_set_param(smf_handle *h, const char *key, const int64_t *values);
 
 /* Counters of the last solve.  Keys: "sweeps", "global_relabels",

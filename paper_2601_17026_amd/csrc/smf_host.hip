@@ -200,6 +200,7 @@ struct smf_handle {
     int64_t poll_every = 1;
     int64_t bfs_poll_every = 16;
     int64_t bfs_early_stop = 1;
+    int64_t bfs_stop_permille = 1000;   // early stop once this share of the excess nodes is labelled
     int64_t verbose = 0;           // 1: progress lines on stderr
     int64_t gap_every = 0;         // sweeps between gap searches (0: off)
 
@@ -209,6 +210,7 @@ struct smf_handle {
     int64_t sweeps = 0, global_relabels = 0, bfs_passes = 0, mincut_passes = 0, gap_relabels = 0;
     int64_t gap_searches = 0;
     int64_t reset_nodes = 0;       // nodes swept by level-1 passes and fixups
+    int64_t reset_chunks = 0;      // their 64-height chunks (one mask word each, six masks)
     KernelTimer timer;
 };
 
@@ -431,6 +433,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         h->part_up[i] = part[i] ? 1 : 0;
         if (part[i]) {
             h->reset_nodes += h->inst[i].N;
+            h->reset_chunks += (int64_t)h->inst[i].P * h->inst[i].nch;
             c0 = std::min(c0, h->inst[i].col_base);
             c1 = std::max(c1, h->inst[i].col_base + h->inst[i].P);
         }
@@ -476,7 +479,9 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
                 if (!part[i]) continue;
                 const InstScratch &r = h->is_host[i];
                 const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
-                const bool labelled = h->bfs_early_stop && r.bfs_labelled[Csnap[slot ^ 1]] >= r.bfs_active;
+                const bool labelled =
+                    h->bfs_early_stop &&
+                    1000LL * r.bfs_labelled[Csnap[slot ^ 1]] >= h->bfs_stop_permille * (int64_t)r.bfs_active;
                 all = complete || labelled;
             }
             if (all) {
@@ -523,7 +528,7 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     const int n = h->n;
     h->solved = false;
     h->sweeps = h->global_relabels = h->bfs_passes = h->mincut_passes = h->gap_relabels = 0;
-    h->gap_searches = h->reset_nodes = 0;
+    h->gap_searches = h->reset_nodes = h->reset_chunks = 0;
     h->flow.assign(n, 0);
     h->energy.assign(n, 0);
     h->inst_sweeps.assign(n, 0);
@@ -563,11 +568,13 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
         if (h->sweeps >= h->max_sweeps)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: sweep cap reached");
         for (int64_t it = 0; it < h->poll_every; ++it) {
+            // a search runs once some volume's period has come round; volumes
+            // at least halfway through their own period join it, so that
+            // volumes of different periods share searches (a level costs
+            // one launch however many volumes take part)
             bool any = false;
-            for (int i = 0; i < n; ++i) {
-                part[i] = !done[i] && since[i] >= period[i];
-                any = any || part[i];
-            }
+            for (int i = 0; i < n; ++i) any = any || (!done[i] && since[i] >= period[i]);
+            for (int i = 0; i < n; ++i) part[i] = any && !done[i] && 2 * since[i] >= period[i];
             if (any) {
                 rc = global_relabel(h, s, part);
                 if (rc) return rc;
@@ -792,6 +799,12 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
         h->verbose = value;
         return SMF_OK;
     }
+    else if (!strcmp(key, "bfs_stop_permille")) {
+        if (value < 1 || value > 1000)
+            return fail(SMF_ERR_ARG, "smf_set_param: bfs_stop_permille must lie in [1, 1000]");
+        h->bfs_stop_permille = value;
+        return SMF_OK;
+    }
     else if (!strcmp(key, "bfs_early_stop")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: bfs_early_stop is 0 or 1");
         h->bfs_early_stop = value;
@@ -842,7 +855,7 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
         else if (!strcmp(name, "push")) *out = (int64_t)h->work_bytes[1];
         else if (!strcmp(name, "relabel")) *out = (int64_t)h->work_bytes[2];
         else if (!strcmp(name, "build")) *out = 36 * N + 4 * P;
-        else if (!strcmp(name, "bfs_reset")) *out = 36 * h->reset_nodes;
+        else if (!strcmp(name, "bfs_reset")) *out = 40 * h->reset_nodes + 48 * h->reset_chunks;
         else if (!strcmp(name, "finish")) *out = 4 * N + 8 * P;
         else if (!strcmp(name, "mincut")) *out = 4 * N + h->mincut_passes * 24 * P;
         else return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown kernel class in ") + key);

@@ -256,44 +256,77 @@ __device__ __forceinline__ Col column_uniform(const Geom &g, int p)
 // wave-wide scan instead of a 64-step dependency chain.
 constexpr long long kBig = 1LL << 60;
 
-struct Clamp {
-    long long A, L, U;
+template <typename V>
+struct ClampT {
+    V A, L, U;
 };
+using Clamp = ClampT<long long>;
 
-__device__ __forceinline__ long long clampv(long long x, long long l, long long u)
+template <typename V>
+__device__ __forceinline__ V clampv(V x, V l, V u)
 {
     return x < l ? l : (x > u ? u : x);
 }
 
-__device__ __forceinline__ long long apply(const Clamp &f, long long c)
+template <typename V>
+__device__ __forceinline__ V apply(const ClampT<V> &f, V c)
 {
-    return clampv(c + f.A, f.L, f.U);
+    return clampv<V>(c + f.A, f.L, f.U);
 }
 
 // s o t: apply t first, then s.
-__device__ __forceinline__ Clamp compose(const Clamp &s, const Clamp &t)
+template <typename V>
+__device__ __forceinline__ ClampT<V> compose(const ClampT<V> &s, const ClampT<V> &t)
 {
-    Clamp r;
+    ClampT<V> r;
     r.A = t.A + s.A;
-    r.L = clampv(t.L + s.A, s.L, s.U);
-    r.U = clampv(t.U + s.A, s.L, s.U);
+    r.L = clampv<V>(t.L + s.A, s.L, s.U);
+    r.U = clampv<V>(t.U + s.A, s.L, s.U);
     return r;
 }
 
-__device__ __forceinline__ Clamp shfl_clamp_down(const Clamp &f, int off)
+__device__ __forceinline__ int shflv(int v, int src) { return __shfl(v, src, kWave); }
+__device__ __forceinline__ int shflv_down(int v, int off) { return __shfl_down(v, off, kWave); }
+__device__ __forceinline__ int shflv_up(int v, int off) { return __shfl_up(v, off, kWave); }
+__device__ __forceinline__ long long shflv(long long v, int src) { return shfl64(v, src); }
+__device__ __forceinline__ long long shflv_down(long long v, int off) { return shfl64_down(v, off); }
+__device__ __forceinline__ long long shflv_up(long long v, int off) { return shfl64_up(v, off); }
+
+// Carry into every lane of a 64-height chunk and out of it, for the clamp
+// function f of each lane and the carry c entering the chunk: a suffix scan
+// (walking down, the carry enters at lane 63) or a prefix scan (walking up).
+template <bool kDown, typename V>
+__device__ __forceinline__ void chunk_carry(const ClampT<V> &f, long long c, int lane, long long &cin,
+                                            long long &cout)
 {
-    return {shfl64_down(f.A, off), shfl64_down(f.L, off), shfl64_down(f.U, off)};
+    ClampT<V> sc = f;
+    const V cv = (V)c;
+    if (kDown) {
+        for (int off = 1; off < kWave; off <<= 1) {
+            const ClampT<V> o = {shflv_down(sc.A, off), shflv_down(sc.L, off), shflv_down(sc.U, off)};
+            if (lane + off < kWave) sc = compose(sc, o);
+        }
+        const ClampT<V> prev = {shflv_down(sc.A, 1), shflv_down(sc.L, 1), shflv_down(sc.U, 1)};
+        cin = lane + 1 < kWave ? (long long)apply(prev, cv) : c;
+        const ClampT<V> all = {shflv(sc.A, 0), shflv(sc.L, 0), shflv(sc.U, 0)};
+        cout = (long long)apply(all, cv);
+    } else {
+        for (int off = 1; off < kWave; off <<= 1) {
+            const ClampT<V> o = {shflv_up(sc.A, off), shflv_up(sc.L, off), shflv_up(sc.U, off)};
+            if (lane >= off) sc = compose(sc, o);
+        }
+        const ClampT<V> prev = {shflv_up(sc.A, 1), shflv_up(sc.L, 1), shflv_up(sc.U, 1)};
+        cin = lane > 0 ? (long long)apply(prev, cv) : c;
+        const ClampT<V> all = {shflv(sc.A, kWave - 1), shflv(sc.L, kWave - 1), shflv(sc.U, kWave - 1)};
+        cout = (long long)apply(all, cv);
+    }
 }
 
-__device__ __forceinline__ Clamp shfl_clamp_up(const Clamp &f, int off)
-{
-    return {shfl64_up(f.A, off), shfl64_up(f.L, off), shfl64_up(f.U, off)};
-}
-
-__device__ __forceinline__ Clamp shfl_clamp(const Clamp &f, int src)
-{
-    return {shfl64(f.A, src), shfl64(f.L, src), shfl64(f.U, src)};
-}
+// The scan runs in 32-bit arithmetic when every lane's |A| is at most
+// kSmallA and the entering carry at most kSmallCarry: then every partial
+// composition and every carry stays below 2^27, so capping U at kCapU
+// (> 2^27) changes no result and nothing overflows.
+constexpr long long kSmallA = 1LL << 20, kSmallCarry = 1LL << 26, kCapU = 1LL << 29;
 
 // ---- label histogram (gap heuristic) ---------------------------------------------
 //
@@ -657,25 +690,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             Clamp f = {0, 0, 0};
             if (kDown && adm_down) f = {taken - sink_cap, 0, kBig};
             if (!kDown && adm_up) f = {taken - sink_cap, 0, (long long)ci.fd_above};
-            // inclusive scan in the walking direction, then shift by one lane
-            Clamp sc = f;
-            long long cin;
-            if (kDown) {
-                for (int off = 1; off < kWave; off <<= 1) {
-                    Clamp o = shfl_clamp_down(sc, off);
-                    if (lane + off < kWave) sc = compose(sc, o);
+            // carries into the lanes and out of the chunk: nothing moves when
+            // no carry enters and no lane has excess to pass on
+            long long cin = 0;
+            if (carry != 0 || __ballot(f.A > 0)) {
+                long long cout;
+                if (carry <= kSmallCarry && !__ballot(f.A < -kSmallA || f.A > kSmallA)) {
+                    const ClampT<int> f32 = {(int)f.A, (int)f.L, (int)min(f.U, kCapU)};
+                    chunk_carry<kDown, int>(f32, carry, lane, cin, cout);
+                } else {
+                    chunk_carry<kDown, long long>(f, carry, lane, cin, cout);
                 }
-                Clamp prev = shfl_clamp_down(sc, 1);
-                cin = lane + 1 < kWave ? apply(prev, carry) : carry;
-                carry = apply(shfl_clamp(sc, 0), carry);
-            } else {
-                for (int off = 1; off < kWave; off <<= 1) {
-                    Clamp o = shfl_clamp_up(sc, off);
-                    if (lane >= off) sc = compose(sc, o);
-                }
-                Clamp prev = shfl_clamp_up(sc, 1);
-                cin = lane > 0 ? apply(prev, carry) : carry;
-                carry = apply(shfl_clamp(sc, kWave - 1), carry);
+                carry = cout;
             }
             long long rem = live ? taken + cin : 0;
             if (rem > 0 && sink_cap > 0) {
