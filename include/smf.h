@@ -55,7 +55,7 @@ typedef struct smf_handle smf_handle;
 
 /* Allocates all solver state for one nx x ny x K volume with smoothness
  * bound delta (Section 1.2, the "edge interval") on the current device:
- * 32 bytes per node, 6 bits per node (rounded up to 64 heights) of
+ * 32 bytes per node, 5 bits per node (rounded up to 64 heights) of
  * breadth-first-search bit masks, plus O(nx*ny).  Returns NULL on failure (see
  * smf_last_error).  Requires nx, ny, K >= 1, delta >= 0,
  * nx*ny*K <= 2^30 - 2 (every finite distance label then stays below the
@@ -149,10 +149,6 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *                        tracked); 0 turns it off (default 0)
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
- *   "bfs_stop_permille" -- with bfs_early_stop, end a global relabel once
- *                        this many thousandths of the nodes with excess are
- *                        labelled (1..1000, default 1000); the others keep
- *                        the first unfinished level, a valid lower bound
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
  *   "count_work"      -- 1: kernels count their algorithmic bytes ("bytes.<class>"
  *                        statistics of bfs, push, relabel; one atomic per wave
@@ -196,8 +192,9 @@ int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
  * (ceil log2 K, min(delta, 4), floor log2 (nx*ny)).  For every class of the
  * handle's volumes that the process-wide tuning cache does not hold yet,
  * the largest volume of that class is solved on a temporary handle with
- * each candidate period (2, 3, 4, 6, 8, 12, 16, 24), timed on the host
- * clock, and the fastest period is cached; then every volume of `h` gets
+ * each candidate period (2, 3, 4, 6, 8, 12), timed on the host clock (the
+ * fastest of three runs when a solve takes under 50 ms), and the fastest
+ * period is cached; then every volume of `h` gets
  * its class's period (smf_batch_set_param).  `packed_cost_dev` and
  * `offsets_host` are as for smf_batch_solve (a plain handle: the volume,
  * NULL offsets).  Allocates and frees the temporary handles; work runs on

@@ -45,8 +45,9 @@ struct InstScratch {
     int bmax;            // max_p c(p, 0)
     int active;          // active nodes after the last relabel phase
     int bfs_active;      // nodes with excess and a finite label when the BFS starts
-    int bfs_labelled[2]; // ... of which the running BFS has labelled so far, counted
-                         // at alternate host polls into alternate slots
+    int bfs_unsat[2];    // columns holding such a node that the running BFS has not
+                         // labelled yet (the early stop waits for 0), counted at
+                         // alternate host polls into alternate slots
     int gap;             // labels above `gap` cannot reach t (kInf: no gap known)
     int gap_frozen;      // active nodes cut off by the gap heuristic
     int pad[5];
@@ -72,11 +73,17 @@ struct Geom {
     // word-major: word w (heights 64w..64w+63) of mask m of column p is
     // bits[(m * max_nch + w) * Ptot + p], so that the columns of a wave read
     // adjacent words.  Masks: kMaskFl + k (lateral arc in direction k carries
-    // flow), kMaskFd (down arc carries flow), kMaskAct (node holds excess).
+    // flow), kMaskFd (down arc carries flow).
     unsigned long long *bits;
     int max_nch;
+    // Per column, the lowest height of a node with excess and a finite label
+    // when the running global relabel started (K if none), and the list of
+    // the columns whose lowest such node lies below the level-1 suffix.
+    int *low_act;
+    int *short_list;
+    int *short_count;
 };
-constexpr int kMaskFl = 0, kMaskFd = 4, kMaskAct = 5, kMasks = 6;
+constexpr int kMaskFl = 0, kMaskFd = 4, kMasks = 5;
 constexpr int kWorkSlots = 64, kWorkStride = 16;
 
 // Per-node solver state; each array holds Ntot int32, packed as above.
@@ -104,6 +111,7 @@ struct Scratch {
     int err;             // kErr* bits
     int changed;         // a min-cut pass changed something
     int count[2];        // sizes of the two column work lists
+    int short_count;     // size of the running global relabel's short-column list
 };
 constexpr int kScratchHead = 64;
 static_assert(sizeof(Scratch) <= kScratchHead, "Scratch must fit its header");

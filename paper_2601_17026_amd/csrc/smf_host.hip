@@ -37,7 +37,7 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
                       const int *CHin, int *Tout, int *LFout, int *CHout, int c0, int c1,
                       hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
-void launch_bfs_count(const Geom &g, const int *T, int slot, int c0, int c1, hipStream_t st);
+void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st);
@@ -169,7 +169,8 @@ struct smf_handle {
     int *fill_dev = nullptr;      // n: fixup label of the running global relabel (-1: none)
     int *state = nullptr;         // 8 * Ntot int32
     int *H = nullptr;             // Ptot int32 surfaces
-    int *bfs = nullptr;           // 12 * Ptot int32: two per-column BFS records (T, LF[4], changed)
+    int *bfs = nullptr;           // 14 * Ptot int32: two per-column BFS records (T, LF[4], changed),
+                                  // the lowest active heights and the short-column list
     unsigned long long *bits = nullptr;   // kMasks * max_nch * Ptot BFS bit-mask words
     unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
     int *hist = nullptr;                  // n x kHistLen label histograms (Geom::hist)
@@ -200,7 +201,6 @@ struct smf_handle {
     int64_t poll_every = 1;
     int64_t bfs_poll_every = 16;
     int64_t bfs_early_stop = 1;
-    int64_t bfs_stop_permille = 1000;   // early stop once this share of the excess nodes is labelled
     int64_t verbose = 0;           // 1: progress lines on stderr
     int64_t gap_every = 0;         // sweeps between gap searches (0: off)
 
@@ -210,7 +210,7 @@ struct smf_handle {
     int64_t sweeps = 0, global_relabels = 0, bfs_passes = 0, mincut_passes = 0, gap_relabels = 0;
     int64_t gap_searches = 0;
     int64_t reset_nodes = 0;       // nodes swept by level-1 passes and fixups
-    int64_t reset_chunks = 0;      // their 64-height chunks (one mask word each, six masks)
+    int64_t reset_chunks = 0;      // their 64-height chunks (five mask words, one low-active word per column)
     KernelTimer timer;
 };
 
@@ -320,7 +320,7 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     if (hipGetDevice(&h->device) != hipSuccess || !dev_alloc(h->inst_dev, n) ||
         !dev_alloc(h->col_inst, P) || !dev_alloc(h->cnt_dev, counter_bytes(n)) || !dev_alloc(h->part_dev, n) ||
         !dev_alloc(h->fill_dev, n) || !dev_alloc(h->state, 8 * N) || !dev_alloc(h->H, P) ||
-        !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||
+        !dev_alloc(h->bfs, 14 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||
         !dev_alloc(h->wcount, 3 * kWorkSlots * kWorkStride) ||
         !dev_alloc(h->hist, (size_t)n * kHistLen) || !dev_alloc(h->wmask, 2 * P) ||
         !dev_alloc(h->wlist, 2 * P) || !host_alloc(h->inst_up, n) ||
@@ -359,6 +359,9 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     g.hist_len = kHistLen;
     g.bits = h->bits;
     g.max_nch = max_nch;
+    g.low_act = h->bfs + 12 * P;
+    g.short_list = h->bfs + 13 * P;
+    g.short_count = &h->scr->short_count;
     int *b = h->state;
     h->st.e = b;
     h->st.d = b + N;
@@ -441,6 +444,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     if (c0 >= c1) return SMF_OK;
     HIP_TRY(hipMemcpyAsync(h->part_dev, h->part_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
     launch_bfs_begin(h->g, s);
+    launch_set_int(&h->scr->short_count, 0, s);
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
         launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], c0, c1, s);   // level 1 lives in buffer 1
@@ -461,9 +465,9 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
                 h->bfs_passes++;
             }
         }
-        // buffer L & 1 holds every column's threshold of level L; the count
-        // of this poll goes to bfs_labelled[npoll & 1]
-        if (h->bfs_early_stop) launch_bfs_count(h->g, T[L & 1], npoll & 1, c0, c1, s);
+        // buffer L & 1 holds every column's threshold of level L; this
+        // poll's count goes to bfs_unsat[npoll & 1]
+        if (h->bfs_early_stop) launch_bfs_count(h->g, T[L & 1], npoll & 1, s);
         HIP_TRY(hipGetLastError());
         int rc = post_snapshot(h, s, kSlotBfs + slot);
         if (rc) return rc;
@@ -479,9 +483,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
                 if (!part[i]) continue;
                 const InstScratch &r = h->is_host[i];
                 const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
-                const bool labelled =
-                    h->bfs_early_stop &&
-                    1000LL * r.bfs_labelled[Csnap[slot ^ 1]] >= h->bfs_stop_permille * (int64_t)r.bfs_active;
+                const bool labelled = h->bfs_early_stop && r.bfs_unsat[Csnap[slot ^ 1]] == 0;
                 all = complete || labelled;
             }
             if (all) {
@@ -510,9 +512,9 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
             if (part[i]) {
                 ++npart;
                 act += h->is_host[i].bfs_active;
-                lab += std::max(h->is_host[i].bfs_labelled[0], h->is_host[i].bfs_labelled[1]);
+                lab += std::min(h->is_host[i].bfs_unsat[0], h->is_host[i].bfs_unsat[1]);
             }
-        fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d volumes, %d levels, active %d, labelled %d\n",
+        fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d volumes, %d levels, active %d, columns short %d\n",
                 (long long)h->global_relabels, (long long)h->sweeps, npart, L - 1, act, lab);
     }
     for (int i = 0; i < n; ++i)
@@ -799,12 +801,6 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
         h->verbose = value;
         return SMF_OK;
     }
-    else if (!strcmp(key, "bfs_stop_permille")) {
-        if (value < 1 || value > 1000)
-            return fail(SMF_ERR_ARG, "smf_set_param: bfs_stop_permille must lie in [1, 1000]");
-        h->bfs_stop_permille = value;
-        return SMF_OK;
-    }
     else if (!strcmp(key, "bfs_early_stop")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: bfs_early_stop is 0 or 1");
         h->bfs_early_stop = value;
@@ -855,7 +851,7 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
         else if (!strcmp(name, "push")) *out = (int64_t)h->work_bytes[1];
         else if (!strcmp(name, "relabel")) *out = (int64_t)h->work_bytes[2];
         else if (!strcmp(name, "build")) *out = 36 * N + 4 * P;
-        else if (!strcmp(name, "bfs_reset")) *out = 40 * h->reset_nodes + 48 * h->reset_chunks;
+        else if (!strcmp(name, "bfs_reset")) *out = 40 * h->reset_nodes + 44 * h->reset_chunks;
         else if (!strcmp(name, "finish")) *out = 4 * N + 8 * P;
         else if (!strcmp(name, "mincut")) *out = 4 * N + h->mincut_passes * 24 * P;
         else return fail(SMF_ERR_ARG, std::string("smf_get_stat: unknown kernel class in ") + key);

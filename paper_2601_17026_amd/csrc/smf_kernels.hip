@@ -397,7 +397,7 @@ __global__ void k_init_scratch(Geom g, Scratch *s)
         r.bmax = INT_MIN;
         r.active = 0;
         r.bfs_active = 0;
-        r.bfs_labelled[0] = r.bfs_labelled[1] = 0;
+        r.bfs_unsat[0] = r.bfs_unsat[1] = 0;
         r.gap = kInf;
         r.gap_frozen = 0;
     }
@@ -949,7 +949,7 @@ __global__ void k_bfs_begin(Geom g)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < g.n && g.part[i]) {
         g.is[i].bfs_active = 0;
-        g.is[i].bfs_labelled[0] = g.is[i].bfs_labelled[1] = 0;
+        g.is[i].bfs_unsat[0] = g.is[i].bfs_unsat[1] = 0;
         g.is[i].gap = kInf;
         g.is[i].lvl_changed[1] = 0;
     }
@@ -970,7 +970,26 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
     int lo, hi;
     wave_range(c0, c1, lo, hi);
     VolSum<int> act(&g.is[0].bfs_active);
+    // short columns of up to 64 consecutive columns, appended to the list
+    // with one counter atomic
+    unsigned long long shortm = 0;
+    int sbase = lo;
+    auto flush_short = [&]() {
+        const int cnt = __popcll(shortm);
+        if (cnt) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(g.short_count, cnt);
+            base = __shfl(base, 0, kWave);
+            if ((shortm >> lane) & 1ULL)
+                g.short_list[base + __popcll(shortm & ((1ULL << lane) - 1ULL))] = sbase + lane;
+        }
+        shortm = 0;
+    };
     for (int p = lo; p < hi; ++p) {
+        if (p - sbase == kWave) {
+            flush_short();
+            sbase = p;
+        }
         const Col col = column_uniform(g, p);
         if (!g.part[col.ii]) {
             if (lane == 0) CH[p] = 0;
@@ -978,7 +997,7 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
         }
         act.to(col.ii);
         const int K = col.I.K;
-        int t1 = K;
+        int t1 = K, la = K;
         int lf[4] = {K, K, K, K};
         for (int c = 0; c < col.I.nch; ++c) {
             const int z = c * kWave + lane;
@@ -999,7 +1018,6 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
 #pragma unroll
             for (int k = 0; k < 4; ++k) wm[kMaskFl + k] = __ballot(in && fv[k] > 0);
             wm[kMaskFd] = __ballot(in && fdv > 0);
-            wm[kMaskAct] = __ballot(in && ev > 0);
             unsigned long long mine = 0;
 #pragma unroll
             for (int m = 0; m < kMasks; ++m)
@@ -1011,7 +1029,12 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
             }
             const bool lab = in && z >= t1;
             if (in) st.d[v] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
-            if (in && ev > 0 && dv < kInf) ++act.acc;
+            const bool isact = in && ev > 0 && dv < kInf;
+            if (isact) ++act.acc;
+            if (la == K) {
+                const unsigned long long am = __ballot(isact);
+                if (am) la = c * kWave + __ffsll((long long)am) - 1;
+            }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (lf[k] < K) continue;
@@ -1019,55 +1042,53 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
                 if (fm) lf[k] = c * kWave + __ffsll((long long)fm) - 1;
             }
         }
+        // a column whose lowest active node lies below the level-1 suffix
+        // keeps the search from stopping early until a level reaches it
+        if (la < t1) shortm |= 1ULL << (p - sbase);
         if (lane == 0) {
             T[p] = t1;
             CH[p] = 1;
+            g.low_act[p] = la;
 #pragma unroll
             for (int k = 0; k < 4; ++k) LF[(size_t)k * Ptot + p] = lf[k];
         }
     }
+    flush_short();
     block_flush(act);
 }
 
-// Early-stop count: the nodes with excess among the heights [T(p), K) that
-// the search has labelled so far, per taking-part volume, from the excess
-// masks (bfs_labelled is cleared before).  A block takes a contiguous range
-// of columns, one lane per column per step, and adds per volume once.
-__global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict__ T, int slot,
-                                                   int c0, int c1)
+// Early-stop count at a host poll: the columns of the short list whose
+// threshold has not yet reached their lowest active node, per volume, into
+// bfs_unsat[slot] (cleared by the previous call, which clears the other slot
+// for the next one).
+__global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict__ T, int slot)
 {
-    // this call adds into slot `slot`, which the previous call cleared; it
-    // clears the other one for the next call
     if (blockIdx.x == 0)
-        for (int i = threadIdx.x; i < g.n; i += blockDim.x) g.is[i].bfs_labelled[slot ^ 1] = 0;
-    const int per = (c1 - c0 + gridDim.x - 1) / gridDim.x;
-    const int lo = min(c1, c0 + (int)blockIdx.x * per), hi = min(c1, lo + per);
-    VolSum<int> lab(&g.is[0].bfs_labelled[slot]);
-    for (int p0 = lo; p0 < hi; p0 += blockDim.x) {
-        const int p = p0 + threadIdx.x;
-        int ii = -1, cnt = 0;
-        if (p < hi) {
+        for (int i = threadIdx.x; i < g.n; i += blockDim.x) g.is[i].bfs_unsat[slot ^ 1] = 0;
+    const int n = *g.short_count;
+    VolSum<int> cnt(&g.is[0].bfs_unsat[slot]);
+    const int stride = gridDim.x * blockDim.x;
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+        const int i = i0 + threadIdx.x;
+        int ii = -1;
+        bool unsat = false;
+        if (i < n) {
+            const int p = g.short_list[i];
             ii = g.col_inst[p];
-            if (g.part[ii]) {
-                const Inst I = g.inst[ii];
-                const int t = T[p];
-                for (int w = t >> 6; w < I.nch; ++w)
-                    cnt += __popcll(mask_word(g, kMaskAct, w, p) & range_bits(w, t, I.K));
-            }
+            unsat = T[p] > g.low_act[p];
         }
-        // the lanes nearly always share one volume: keep a running sum, else
-        // add per volume now
+        // list entries come in wave-sized runs of one volume's columns
         const int first = uniform(ii);
         if (__ballot(ii >= 0 && ii != first) == 0) {
             if (first >= 0) {
-                lab.to(first);
-                lab.acc += cnt;
+                cnt.to(first);
+                cnt.acc += unsat ? 1 : 0;
             }
         } else {
-            wave_add_keyed(&g.is[0].bfs_labelled[slot], ii, cnt, ii >= 0 && cnt > 0);
+            wave_add_keyed(&g.is[0].bfs_unsat[slot], ii, 1, unsat);
         }
     }
-    block_flush(lab);
+    block_flush(cnt);
 }
 
 // Level L -> L+1, one lane per column.  The threshold arithmetic reads the
@@ -1377,11 +1398,9 @@ void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, i
                        CH, c0, c1);
 }
 
-void launch_bfs_count(const Geom &g, const int *T, int slot, int c0, int c1, hipStream_t st)
+void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
 {
-    unsigned b = blocks_for(c1 - c0);
-    if (b > 512) b = 512;
-    hipLaunchKernelGGL(k_bfs_count, dim3(b), dim3(256), 0, st, g, T, slot, c0, c1);
+    hipLaunchKernelGGL(k_bfs_count, dim3(64), dim3(256), 0, st, g, T, slot);
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
