@@ -453,21 +453,21 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     // batch k+1 is enqueued before batch k's snapshot is examined, so the
     // device never waits for the host.  Levels after a volume's search has
     // ended are no-ops for it, or label more nodes exactly.
-    int L = 1, slot = 0, Lsnap[2] = {0, 0}, Csnap[2] = {0, 0};   // slot: 0 or 1 of this loop's pair
+    int L = 1, cur = 1, slot = 0, Lsnap[2] = {0, 0}, Csnap[2] = {0, 0};   // slot: 0 or 1 of this loop's pair
     int npoll = 0;
     bool inflight = false;
     for (;;) {
+        // cur: the record buffer that holds every column's record of level L
         {
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
-            for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L) {
-                launch_bfs_level(h->g, h->st, L, T[L & 1], LF[L & 1], CH[L & 1], T[(L + 1) & 1],
-                                 LF[(L + 1) & 1], CH[(L + 1) & 1], c0, c1, s);
+            for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L, cur ^= 1) {
+                launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], CH[cur], T[cur ^ 1], LF[cur ^ 1],
+                                 CH[cur ^ 1], c0, c1, s);
                 h->bfs_passes++;
             }
         }
-        // buffer L & 1 holds every column's threshold of level L; this
-        // poll's count goes to bfs_unsat[npoll & 1]
-        if (h->bfs_early_stop) launch_bfs_count(h->g, T[L & 1], npoll & 1, s);
+        // this poll's count goes to bfs_unsat[npoll & 1]
+        if (h->bfs_early_stop) launch_bfs_count(h->g, T[cur], npoll & 1, s);
         HIP_TRY(hipGetLastError());
         int rc = post_snapshot(h, s, kSlotBfs + slot);
         if (rc) return rc;

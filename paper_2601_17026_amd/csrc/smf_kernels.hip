@@ -942,16 +942,16 @@ __device__ __forceinline__ unsigned long long range_bits(int w, int lo, int hi)
     return upto & ~((1ULL << a) - 1ULL);
 }
 
-// Before level 1: clears the early-stop counters and the level-1 flag of
-// the volumes that take part, and forgets their known gap.
+// Before level 1: clears the level flags and early-stop counters of the
+// volumes that take part, and forgets their known gap.
 __global__ void k_bfs_begin(Geom g)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < g.n && g.part[i]) {
+        for (int l = 0; l < kLvlSlots; ++l) g.is[i].lvl_changed[l] = 0;
         g.is[i].bfs_active = 0;
         g.is[i].bfs_unsat[0] = g.is[i].bfs_unsat[1] = 0;
         g.is[i].gap = kInf;
-        g.is[i].lvl_changed[1] = 0;
     }
 }
 
@@ -1091,14 +1091,108 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
     block_flush(cnt);
 }
 
+// One level for one column: the new threshold cand from the column's
+// threshold T and its neighbours' thresholds tq[k] (-1: no neighbour in
+// direction k) and lowest flow-carrying arcs into the column lq[k]; lf[]
+// (the column's lowest flow-carrying lateral arc per direction at or above
+// its threshold) is lowered over the newly reached heights [cand, T) from
+// the bit masks.  Returns the mask words read.
+__device__ __forceinline__ int level_update(const Geom &g, int p, int K, int dl, int T, const int tq[4],
+                                           const int lq[4], int lf[4], int &cand)
+{
+    cand = T;
+    int words = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (tq[k] < 0) continue;
+        if (tq[k] == 0) cand = 0;
+        else if (tq[k] + dl < K) cand = min(cand, tq[k] + dl);
+        if (lq[k] < K) cand = min(cand, lat_head_of(lq[k], dl));
+    }
+    if (T >= 1 && T < K) {
+        ++words;
+        if ((mask_word(g, kMaskFd, T >> 6, p) >> (T & 63)) & 1ULL) cand = min(cand, T - 1);
+    }
+    // an lf below T was found in an earlier word
+    for (int w = cand >> 6; cand < T && w <= (T - 1) >> 6; ++w) {
+        if (lf[0] < T && lf[1] < T && lf[2] < T && lf[3] < T) break;
+        const unsigned long long r = range_bits(w, cand, T);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (lf[k] < T) continue;
+            const unsigned long long fm = mask_word(g, kMaskFl + k, w, p) & r;
+            if (fm) lf[k] = w * kWave + __ffsll((long long)fm) - 1;
+        }
+        words += 4;
+    }
+    return words;
+}
+
+// Writes d = lab on the heights [lo, hi) of every lane's column (node (p, 0)
+// at base): ranges of 64 or more heights one column at a time by the whole
+// wave (coalesced stores), the others as one flattened list of (column,
+// height) items, 64 stores per step, so a wave's time follows the number of
+// nodes it labels rather than its longest range.  Called by all lanes;
+// returns the lane's bytes written.
+__device__ __forceinline__ long long label_ranges(int *d, int lab, int lo, int hi, long long base)
+{
+    const int lane = lane_id();
+    long long bytes = 0;
+    const bool whole = hi - lo >= kWave;
+    for (unsigned long long lm = __ballot(whole); lm; lm &= lm - 1) {
+        const int src = __ffsll((long long)lm) - 1;
+        const int a = __shfl(lo, src, kWave), b = __shfl(hi, src, kWave);
+        const long long pbase = shfl64(base, src);
+        for (int z = a + lane; z < b; z += kWave) d[(size_t)pbase + z] = lab;
+        bytes += lane == 0 ? 4LL * (b - a) : 0;
+    }
+    const int len = !whole && hi > lo ? hi - lo : 0;
+    int incl = len;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
+    }
+    const int excl = incl - len;
+    const int total = __shfl(incl, kWave - 1, kWave);
+    for (int i0 = 0; i0 < total; i0 += kWave) {
+        const int item = i0 + lane;
+        // owner: the last lane whose exclusive prefix is <= item
+        int o = 0;
+        for (int step = 32; step > 0; step >>= 1) {
+            const int c = o + step;
+            const int ex = __shfl(excl, c < kWave ? c : kWave - 1, kWave);
+            if (c < kWave && ex <= item) o = c;
+        }
+        const int top = __shfl(hi, o, kWave);
+        const long long pbase = shfl64(base, o);
+        const int z = top - 1 - (item - __shfl(excl, o, kWave));
+        if (item < total) {
+            d[(size_t)pbase + z] = lab;
+            bytes += 4;
+        }
+    }
+    return bytes;
+}
+
+// Sets the level flag `slot` of the volumes of the lanes with `flag`.
+__device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag, int slot)
+{
+    const int lane = lane_id();
+    bool pending = flag;
+    for (;;) {
+        const unsigned long long b = __ballot(pending);
+        if (!b) break;
+        const int leader = __ffsll((long long)b) - 1;
+        const int k = __shfl(ii, leader, kWave);
+        if (lane == leader) g.is[k].lvl_changed[slot] = 1;
+        if (pending && ii == k) pending = false;
+    }
+}
+
 // Level L -> L+1, one lane per column.  The threshold arithmetic reads the
 // records of the column and its neighbours; the lowest flow-carrying
 // lateral arcs among the newly reached heights [cand, T) come from the
-// column's bit masks, so no per-node word is read.  The new ranges are then
-// labelled L+1: long ones by the whole wave, one column at a time, the
-// others as one flattened list of (column, height) items, 64 stores per
-// step, so a wave's time follows the number of nodes it labels rather than
-// its longest range.
+// column's bit masks, so no per-node word is read.
 __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, int L,
                                                    const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin,
@@ -1108,7 +1202,6 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, 
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = c0 + t;
-    const int lane = lane_id();
     // the flags of the next level are cleared here; stream order puts this
     // before every write of level L+1
     if (t < g.n) g.is[t].lvl_changed[(L + 1) % kLvlSlots] = 0;
@@ -1141,34 +1234,14 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, 
         // moved, and both record buffers already hold p's record.
         if (near) {
             T = Tin[p];
-            cand = T;
+            int tq[4], lq[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (q[k] < 0) continue;
-                const int tq = Tin[q[k]];
-                if (tq == 0) cand = 0;
-                else if (tq + dl < K) cand = min(cand, tq + dl);
-                const int lq = LFin[(size_t)(k ^ 1) * P + q[k]];
-                if (lq < K) cand = min(cand, lat_head_of(lq, dl));
+                tq[k] = q[k] >= 0 ? Tin[q[k]] : -1;
+                lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
+                lf[k] = LFin[(size_t)k * P + p];
             }
-            if (T >= 1 && T < K && ((mask_word(g, kMaskFd, T >> 6, p) >> (T & 63)) & 1ULL))
-                cand = min(cand, T - 1);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) lf[k] = LFin[(size_t)k * P + p];
-            bytes += 4 * 14 + (T >= 1 && T < K ? 8 : 0);
-            // lowest flow-carrying lateral arc per direction among the newly
-            // reached heights (an lf below T was found in an earlier word)
-            for (int w = cand >> 6; cand < T && w <= (T - 1) >> 6; ++w) {
-                if (lf[0] < T && lf[1] < T && lf[2] < T && lf[3] < T) break;
-                const unsigned long long r = range_bits(w, cand, T);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (lf[k] < T) continue;
-                    const unsigned long long fm = mask_word(g, kMaskFl + k, w, p) & r;
-                    if (fm) lf[k] = w * kWave + __ffsll((long long)fm) - 1;
-                }
-                bytes += 4 * 8;
-            }
+            bytes += 4 * 14 + 8 * level_update(g, p, K, dl, T, tq, lq, lf, cand);
         }
     }
     const bool need = valid && near && cand < T;
@@ -1182,53 +1255,8 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, 
         CHout[p] = need;
     }
     // level L labelled something in the volumes of the lanes with `need`
-    {
-        bool pending = need;
-        for (;;) {
-            const unsigned long long b = __ballot(pending);
-            if (!b) break;
-            const int leader = __ffsll((long long)b) - 1;
-            const int k = __shfl(ii, leader, kWave);
-            if (lane == leader) g.is[k].lvl_changed[L % kLvlSlots] = 1;
-            if (pending && ii == k) pending = false;
-        }
-    }
-    // labelling: ranges of 64 or more heights one column at a time by the
-    // whole wave (coalesced stores), the others as one flattened list
-    const int lab = L + 1;
-    const bool whole = need && T - cand >= kWave;
-    for (unsigned long long lm = __ballot(whole); lm; lm &= lm - 1) {
-        const int src = __ffsll((long long)lm) - 1;
-        const int lo = __shfl(cand, src, kWave), hi = __shfl(T, src, kWave);
-        const long long pbase = shfl64(base, src);
-        for (int z = lo + lane; z < hi; z += kWave) d[(size_t)pbase + z] = lab;
-        bytes += lane == 0 ? 4LL * (hi - lo) : 0;
-    }
-    const int len = need && !whole ? T - cand : 0;
-    int incl = len;
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int t = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += t;
-    }
-    const int excl = incl - len;
-    const int total = __shfl(incl, kWave - 1, kWave);
-    for (int i0 = 0; i0 < total; i0 += kWave) {
-        const int item = i0 + lane;
-        // owner: the last lane whose exclusive prefix is <= item
-        int o = 0;
-        for (int step = 32; step > 0; step >>= 1) {
-            const int c = o + step;
-            const int ex = __shfl(excl, c < kWave ? c : kWave - 1, kWave);
-            if (c < kWave && ex <= item) o = c;
-        }
-        const int hi = __shfl(T, o, kWave);
-        const long long pbase = shfl64(base, o);
-        const int z = hi - 1 - (item - __shfl(excl, o, kWave));
-        if (item < total) {
-            d[(size_t)pbase + z] = lab;
-            bytes += 4;
-        }
-    }
+    set_level_flag(g, ii, need, L % kLvlSlots);
+    bytes += label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, base);
     if (g.count_work) count_bytes(g, 0, bytes);
 }
 

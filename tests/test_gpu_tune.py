@@ -10,7 +10,7 @@ from paper_2601_17026_amd import synth
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-CANDIDATES = {2, 3, 4, 6, 8, 12, 16, 24}
+CANDIDATES = {2, 3, 4, 6, 8, 12}
 
 
 @pytest.fixture(scope="module")
