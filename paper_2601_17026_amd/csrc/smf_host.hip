@@ -31,11 +31,9 @@ void launch_fill(int *a, long long n, int v, hipStream_t st);
 void launch_work_init(const Geom &g, const Work &a, const Work &b, hipStream_t st);
 void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, hipStream_t st);
 void launch_bfs_begin(const Geom &g, hipStream_t st);
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, int c0, int c1,
-                     hipStream_t st);
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, int c1, hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *CHin, int *Tout, int *LFout, int *CHout, int c0, int c1,
-                      hipStream_t st);
+                      int *Tout, int *LFout, int c0, int c1, hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
@@ -169,8 +167,8 @@ struct smf_handle {
     int *fill_dev = nullptr;      // n: fixup label of the running global relabel (-1: none)
     int *state = nullptr;         // 8 * Ntot int32
     int *H = nullptr;             // Ptot int32 surfaces
-    int *bfs = nullptr;           // 14 * Ptot int32: two per-column BFS records (T, LF[4], changed),
-                                  // the lowest active heights and the short-column list
+    int *bfs = nullptr;           // 12 * Ptot int32: two per-column BFS records (threshold word,
+                                  // LF[4]), the lowest active heights and the short-column list
     unsigned long long *bits = nullptr;   // kMasks * max_nch * Ptot BFS bit-mask words
     unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
     int *hist = nullptr;                  // n x kHistLen label histograms (Geom::hist)
@@ -320,7 +318,7 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     if (hipGetDevice(&h->device) != hipSuccess || !dev_alloc(h->inst_dev, n) ||
         !dev_alloc(h->col_inst, P) || !dev_alloc(h->cnt_dev, counter_bytes(n)) || !dev_alloc(h->part_dev, n) ||
         !dev_alloc(h->fill_dev, n) || !dev_alloc(h->state, 8 * N) || !dev_alloc(h->H, P) ||
-        !dev_alloc(h->bfs, 14 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||
+        !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||
         !dev_alloc(h->wcount, 3 * kWorkSlots * kWorkStride) ||
         !dev_alloc(h->hist, (size_t)n * kHistLen) || !dev_alloc(h->wmask, 2 * P) ||
         !dev_alloc(h->wlist, 2 * P) || !host_alloc(h->inst_up, n) ||
@@ -359,8 +357,8 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     g.hist_len = kHistLen;
     g.bits = h->bits;
     g.max_nch = max_nch;
-    g.low_act = h->bfs + 12 * P;
-    g.short_list = h->bfs + 13 * P;
+    g.low_act = h->bfs + 10 * P;
+    g.short_list = h->bfs + 11 * P;
     g.short_count = &h->scr->short_count;
     int *b = h->state;
     h->st.e = b;
@@ -428,7 +426,6 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     const size_t P = (size_t)h->g.Ptot;
     int *T[2] = {h->bfs, h->bfs + 5 * P};
     int *LF[2] = {h->bfs + P, h->bfs + 6 * P};
-    int *CH[2] = {h->bfs + 10 * P, h->bfs + 11 * P};
     // the searches' launches cover the columns [c0, c1) spanned by the
     // volumes that take part (volumes are packed in order)
     int c0 = h->g.Ptot, c1 = 0;
@@ -447,7 +444,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     launch_set_int(&h->scr->short_count, 0, s);
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_init(h->g, h->st, T[1], LF[1], CH[1], c0, c1, s);   // level 1 lives in buffer 1
+        launch_bfs_init(h->g, h->st, T[1], LF[1], c0, c1, s);   // level 1 lives in buffer 1
     }
     // The host reads the counters one batch of levels behind the device:
     // batch k+1 is enqueued before batch k's snapshot is examined, so the
@@ -461,8 +458,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         {
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
             for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L, cur ^= 1) {
-                launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], CH[cur], T[cur ^ 1], LF[cur ^ 1],
-                                 CH[cur ^ 1], c0, c1, s);
+                launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], T[cur ^ 1], LF[cur ^ 1], c0, c1, s);
                 h->bfs_passes++;
             }
         }

@@ -919,14 +919,17 @@ __global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Wor
 // the thresholds of columns next to a change plus the nodes it labels.
 //
 // Per-column BFS record, double-buffered by level parity (global columns):
-//   T[p]      threshold T_L(p) (K when no node of the column is labelled);
+//   T[p]      threshold T_L(p) (K when no node of the column is labelled) in
+//             bits 0-30, and in bit 31 whether the record changed when
+//             level L was produced (so one load gives both);
 //   LF[k][p]  lowest z' >= T_L(p) whose lateral arc in direction k carries
 //             flow (K if none) -- the reverse-arc term seen by neighbour k;
-//   CH[p]     the record changed when level L was produced.
 // Volumes that do not take part in a search keep CH = 0 on all their
 // columns, so every level skips them.
 
 __device__ __forceinline__ int lat_head_of(int zp, int dl) { return zp == 0 ? 0 : zp - dl; }
+
+constexpr int kChanged = (int)0x80000000u;   // change flag of a threshold word
 
 // Word w of bit mask m of column p.
 __device__ __forceinline__ unsigned long long mask_word(const Geom &g, int m, int w, int p)
@@ -961,8 +964,7 @@ __global__ void k_bfs_begin(Geom g)
 // finite label, and those of them labelled 1, for the early stop, and
 // writes the column's bit masks (flows and excess do not change during the
 // search).
-__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int *CH,
-                                                  int c0, int c1)
+__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int c0, int c1)
 {
     const int lane = lane_id();
     const size_t Ntot = (size_t)g.Ntot;
@@ -992,7 +994,7 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
         }
         const Col col = column_uniform(g, p);
         if (!g.part[col.ii]) {
-            if (lane == 0) CH[p] = 0;
+            if (lane == 0) T[p] = 0;   // no change flag: every level skips it
             continue;
         }
         act.to(col.ii);
@@ -1046,8 +1048,7 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
         // keeps the search from stopping early until a level reaches it
         if (la < t1) shortm |= 1ULL << (p - sbase);
         if (lane == 0) {
-            T[p] = t1;
-            CH[p] = 1;
+            T[p] = t1 | kChanged;
             g.low_act[p] = la;
 #pragma unroll
             for (int k = 0; k < 4; ++k) LF[(size_t)k * Ptot + p] = lf[k];
@@ -1075,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
         if (i < n) {
             const int p = g.short_list[i];
             ii = g.col_inst[p];
-            unsat = T[p] > g.low_act[p];
+            unsat = (T[p] & ~kChanged) > g.low_act[p];
         }
         // list entries come in wave-sized runs of one volume's columns
         const int first = uniform(ii);
@@ -1195,10 +1196,8 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
 // column's bit masks, so no per-node word is read.
 __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, int L,
                                                    const int *__restrict__ Tin,
-                                                   const int *__restrict__ LFin,
-                                                   const int *__restrict__ CHin, int *__restrict__ Tout,
-                                                   int *__restrict__ LFout, int *__restrict__ CHout,
-                                                   int c0, int c1)
+                                                   const int *__restrict__ LFin, int *__restrict__ Tout,
+                                                   int *__restrict__ LFout, int c0, int c1)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = c0 + t;
@@ -1217,42 +1216,37 @@ __global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, 
         ii = col.ii;
         const int K = col.I.K, dl = col.I.delta;
         base = (long long)col.base;
-        int q[4];
-        self = CHin[p] != 0;
+        // the column's and its neighbours' records in one round of loads;
+        // the change flags in them give the frontier: with no change at level
+        // L-1 around p none of p's inputs moved, and both record buffers
+        // already hold p's record
+        int q[4], tq[4], lq[4];
+        const int tw = Tin[p];
+        self = tw < 0;
+        T = tw & ~kChanged;
         near = self;
         int nq = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             q[k] = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
-            if (q[k] >= 0) {
-                ++nq;
-                if (CHin[q[k]]) near = true;
-            }
+            const int w = q[k] >= 0 ? Tin[q[k]] : -1;
+            lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
+            lf[k] = LFin[(size_t)k * P + p];
+            near = near || (q[k] >= 0 && w < 0);
+            tq[k] = q[k] >= 0 ? (w & ~kChanged) : -1;
+            nq += q[k] >= 0;
         }
-        bytes = 4 * (1 + nq) + 4;
-        // Frontier: with no change at level L-1 around p none of p's inputs
-        // moved, and both record buffers already hold p's record.
-        if (near) {
-            T = Tin[p];
-            int tq[4], lq[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                tq[k] = q[k] >= 0 ? Tin[q[k]] : -1;
-                lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
-                lf[k] = LFin[(size_t)k * P + p];
-            }
-            bytes += 4 * 14 + 8 * level_update(g, p, K, dl, T, tq, lq, lf, cand);
-        }
+        bytes = 4 * (1 + nq) + 4 * (4 + nq) + 4;
+        if (near) bytes += 8 * level_update(g, p, K, dl, T, tq, lq, lf, cand);
     }
     const bool need = valid && near && cand < T;
-    if (valid && (need || self)) bytes += 20;
     if (valid) {
+        Tout[p] = need ? (cand | kChanged) : T;
         if (need || self) {
-            Tout[p] = need ? cand : T;
 #pragma unroll
             for (int k = 0; k < 4; ++k) LFout[(size_t)k * P + p] = lf[k];
+            bytes += 16;
         }
-        CHout[p] = need;
     }
     // level L labelled something in the volumes of the lanes with `need`
     set_level_flag(g, ii, need, L % kLvlSlots);
@@ -1419,11 +1413,10 @@ static inline unsigned range_wave_blocks(int c0, int c1)
     return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
 }
 
-void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int *CH, int c0, int c1,
-                     hipStream_t st)
+void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, int c1, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bfs_init, dim3(range_wave_blocks(c0, c1)), dim3(256), 0, st, g, sv, T, LF,
-                       CH, c0, c1);
+                       c0, c1);
 }
 
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
@@ -1432,12 +1425,11 @@ void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      const int *CHin, int *Tout, int *LFout, int *CHout, int c0, int c1,
-                      hipStream_t st)
+                      int *Tout, int *LFout, int c0, int c1, hipStream_t st)
 {
     const long long n = (long long)c1 - c0 > g.n ? (long long)c1 - c0 : g.n;
     hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(n)), dim3(256), 0, st, g, sv.d, L, Tin, LFin,
-                       CHin, Tout, LFout, CHout, c0, c1);
+                       Tout, LFout, c0, c1);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)
