@@ -147,6 +147,10 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *   "gap_every"       -- sweeps between searches for an empty label (gap
  *                        heuristic, Section 2.1; labels below 4096 are
  *                        tracked); 0 turns it off (default 0)
+ *   "level_block"     -- threads per block of a breadth-first-search level
+ *                        launch (power of two in [64, 1024], default 256)
+ *   "sweep_waves"     -- waves of a push or relabel launch (default 8192;
+ *                        at most one per column)
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr

@@ -82,6 +82,10 @@ struct Geom {
     int *low_act;
     int *short_list;
     int *short_count;
+    // launch geometry: threads per block of a BFS level, waves of a push or
+    // relabel phase
+    int level_block;
+    int sweep_waves;
 };
 constexpr int kMaskFl = 0, kMaskFd = 4, kMasks = 5;
 constexpr int kWorkSlots = 64, kWorkStride = 16;

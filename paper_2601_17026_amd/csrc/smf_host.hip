@@ -357,6 +357,8 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     g.hist_len = kHistLen;
     g.bits = h->bits;
     g.max_nch = max_nch;
+    g.level_block = 256;
+    g.sweep_waves = 8192;
     g.low_act = h->bfs + 10 * P;
     g.short_list = h->bfs + 11 * P;
     g.short_count = &h->scr->short_count;
@@ -795,6 +797,18 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     else if (!strcmp(key, "verbose")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: verbose is 0 or 1");
         h->verbose = value;
+        return SMF_OK;
+    }
+    else if (!strcmp(key, "level_block")) {
+        if (value < 64 || value > 1024 || (value & (value - 1)))
+            return fail(SMF_ERR_ARG, "smf_set_param: level_block is a power of two in [64, 1024]");
+        h->g.level_block = (int)value;
+        return SMF_OK;
+    }
+    else if (!strcmp(key, "sweep_waves")) {
+        if (value < 4 || value > (1 << 20))
+            return fail(SMF_ERR_ARG, "smf_set_param: sweep_waves must lie in [4, 2^20]");
+        h->g.sweep_waves = (int)value;
         return SMF_OK;
     }
     else if (!strcmp(key, "bfs_early_stop")) {

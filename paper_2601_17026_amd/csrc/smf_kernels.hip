@@ -1194,7 +1194,7 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
 // records of the column and its neighbours; the lowest flow-carrying
 // lateral arcs among the newly reached heights [cand, T) come from the
 // column's bit masks, so no per-node word is read.
-__global__ __launch_bounds__(256) void k_bfs_level(Geom g, int *__restrict__ d, int L,
+__global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d, int L,
                                                    const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin, int *__restrict__ Tout,
                                                    int *__restrict__ LFout, int c0, int c1)
@@ -1376,6 +1376,15 @@ static inline unsigned wave_blocks(const Geom &g)
     return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
 }
 
+// Grid of the push and relabel phases: sweep_waves waves (at most one per
+// column), 4 per block.
+static inline unsigned sweep_blocks(const Geom &g)
+{
+    long long want = (g.Ptot + 3) / 4, cap = g.sweep_waves / 4;
+    if (want > cap) want = cap;
+    return (unsigned)(want > 0 ? want : 1);
+}
+
 void launch_init_scratch(const Geom &g, Scratch *s, hipStream_t st)
 {
     hipLaunchKernelGGL(k_init_scratch, dim3(blocks_for(g.n)), dim3(256), 0, st, g, s);
@@ -1428,8 +1437,9 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
                       int *Tout, int *LFout, int c0, int c1, hipStream_t st)
 {
     const long long n = (long long)c1 - c0 > g.n ? (long long)c1 - c0 : g.n;
-    hipLaunchKernelGGL(k_bfs_level, dim3(blocks_for(n)), dim3(256), 0, st, g, sv.d, L, Tin, LFin,
-                       Tout, LFout, c0, c1);
+    const int b = g.level_block;
+    hipLaunchKernelGGL(k_bfs_level, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d, L, Tin,
+                       LFin, Tout, LFout, c0, c1);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)
@@ -1450,9 +1460,9 @@ void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wo
                  bool down, hipStream_t st)
 {
     if (down)
-        hipLaunchKernelGGL(k_push<true>, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
+        hipLaunchKernelGGL(k_push<true>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
     else
-        hipLaunchKernelGGL(k_push<false>, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
+        hipLaunchKernelGGL(k_push<false>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
 }
 
 void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st)
@@ -1463,7 +1473,7 @@ void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t s
 
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_relabel, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
+    hipLaunchKernelGGL(k_relabel, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
 }
 
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
