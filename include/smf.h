@@ -199,7 +199,11 @@ int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
  * each candidate period (2, 3, 4, 6, 8, 12), timed on the host clock (the
  * fastest of three runs when a solve takes under 50 ms), and the fastest
  * period is cached; then every volume of `h` gets
- * its class's period (smf_batch_set_param).  `packed_cost_dev` and
+ * its class's period (smf_batch_set_param).  For a batch of more than one
+ * volume the tuner then times whole solves of `h` with every volume's
+ * period scaled by 1, 1.5, 2 and 3 and keeps the fastest scale (the volumes
+ * of a batch share their searches, which favours longer periods than
+ * solving each volume alone); the cache keeps the unscaled class periods.  `packed_cost_dev` and
  * `offsets_host` are as for smf_batch_solve (a plain handle: the volume,
  * NULL offsets).  Allocates and frees the temporary handles; work runs on
  * `stream`.  If the environment variable SMF_TUNE_CACHE names a file, the

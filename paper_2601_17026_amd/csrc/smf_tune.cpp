@@ -12,7 +12,8 @@
 //
 // The tuner is a client of the C-ABI: it solves the representative volume
 // on a temporary handle of its own and writes the chosen periods into the
-// caller's handle with smf_batch_set_param.
+// caller's handle with smf_batch_set_param.  For a batch it then times whole
+// solves of the caller's batch with the periods scaled by a common factor.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -44,6 +45,8 @@ std::map<Key, Choice> g_cache;
 bool g_env_loaded = false;
 
 const int64_t kCandidates[] = {2, 3, 4, 6, 8, 12};
+// scale factors 1, 1.5, 2 and 3 (doubled) of the whole-batch step
+const int kBatchScale2[] = {2, 3, 4, 6};
 // a solve shorter than this is timed three times and the fastest counts
 constexpr int64_t kShortSolveNs = 50000000;
 
@@ -182,7 +185,36 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
     const char *path = getenv("SMF_TUNE_CACHE");
     if (path && *path && !todo.empty()) (void)save_locked(path);
     const std::vector<int64_t> per = periods_locked(s);
-    return smf_batch_set_param(h, "relabel_period", per.data());
+    rc = smf_batch_set_param(h, "relabel_period", per.data());
+    if (rc || n == 1) return rc;
+    // The volumes of a batch share their searches (a level costs one launch
+    // however many volumes take part), which favours longer periods than
+    // solving each volume alone: whole-batch solves with every period
+    // scaled by each factor are timed, and the fastest scale is kept.
+    std::vector<int64_t> eff(n), scaled(n);
+    rc = smf_batch_get_stat(h, "relabel_period", eff.data());
+    if (rc) return rc;
+    int64_t best_ns = -1;
+    std::vector<int64_t> best = eff;
+    for (int f2 : kBatchScale2) {   // twice the scale factor
+        for (size_t i = 0; i < n; ++i) scaled[i] = std::max<int64_t>(1, (eff[i] * f2 + 1) / 2);
+        rc = smf_batch_set_param(h, "relabel_period", scaled.data());
+        if (rc) return rc;
+        if (best_ns < 0) {
+            rc = smf_batch_solve(h, packed_cost_dev, off.data(), stream);   // warm-up
+            if (rc) return rc;
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = smf_batch_solve(h, packed_cost_dev, off.data(), stream);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (rc) return rc;
+        const int64_t ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count();
+        if (best_ns < 0 || ns < best_ns) {
+            best_ns = ns;
+            best = scaled;
+        }
+    }
+    return smf_batch_set_param(h, "relabel_period", best.data());
 }
 
 extern "C" int smf_tune_apply(smf_handle *h)
