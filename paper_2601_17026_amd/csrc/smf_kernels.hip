@@ -247,6 +247,25 @@ __device__ __forceinline__ Col column_uniform(const Geom &g, int p)
     return column_of(g, p, uniform(g.col_inst[p]));
 }
 
+// Volume of a run of wave-uniform columns: the volume table is read again
+// only when a column lies outside the volume of the previous one.
+struct VolCache {
+    int ii = -1;
+    Inst I;
+    // true when the volume changed
+    __device__ __forceinline__ bool at(const Geom &g, int p)
+    {
+        if (ii >= 0 && (unsigned)(p - I.col_base) < (unsigned)I.P) return false;
+        ii = uniform(g.col_inst[p]);
+        I = g.inst[ii];
+        return true;
+    }
+    __device__ __forceinline__ size_t base(int p) const
+    {
+        return (size_t)I.node_base + (size_t)(p - I.col_base) * I.K;
+    }
+};
+
 // ---- carries along a column as a scan of clamp functions --------------------
 //
 // Within one push phase the excess that leaves a node along its column arc
@@ -958,12 +977,40 @@ __global__ void k_bfs_begin(Geom g)
     }
 }
 
+// Node words of one 64-height chunk that level 1 reads.
+struct InitWords {
+    int ts, e, d, fd, f[4];
+};
+
+__device__ __forceinline__ void load_init_words(const State &st, size_t Ntot, size_t v, bool in,
+                                                InitWords &w)
+{
+    w.ts = 0;
+    w.e = 0;
+    w.d = kInf;
+    w.fd = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w.f[k] = 0;
+    if (in) {
+        w.ts = st.ts[v];
+        w.e = st.e[v];
+        w.d = st.d[v];
+        w.fd = st.fd[v];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w.f[k] = st.fl[(size_t)k * Ntot + v];
+    }
+}
+
+// chunks of a column whose words level 1 requests together
+constexpr int kInitGroup = 4;
+
 // Level 1, one wave per column.  Nodes that could not reach t before keep
 // kInf: new residual arcs only ever join nodes that reach t, so a node cut
 // off from t stays cut off.  Counts per volume the nodes with excess and a
 // finite label, and those of them labelled 1, for the early stop, and
 // writes the column's bit masks (flows and excess do not change during the
-// search).
+// search).  The words of kInitGroup chunks are loaded before any of them
+// is used, so that a wave keeps that many chunks' loads in flight.
 __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int c0, int c1)
 {
     const int lane = lane_id();
@@ -987,61 +1034,65 @@ __global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int 
         }
         shortm = 0;
     };
+    VolCache vc;
+    bool vpart = false;
     for (int p = lo; p < hi; ++p) {
         if (p - sbase == kWave) {
             flush_short();
             sbase = p;
         }
-        const Col col = column_uniform(g, p);
-        if (!g.part[col.ii]) {
+        if (vc.at(g, p)) vpart = g.part[vc.ii] != 0;
+        if (!vpart) {
             if (lane == 0) T[p] = 0;   // no change flag: every level skips it
             continue;
         }
-        act.to(col.ii);
-        const int K = col.I.K;
+        act.to(vc.ii);
+        const int K = vc.I.K, nch = vc.I.nch;
+        const size_t base = vc.base(p);
         int t1 = K, la = K;
         int lf[4] = {K, K, K, K};
-        for (int c = 0; c < col.I.nch; ++c) {
-            const int z = c * kWave + lane;
-            const bool in = z < K;
-            const size_t v = col.base + z;
-            int tsv = 0, ev = 0, dv = kInf, fdv = 0;
-            int fv[4] = {0, 0, 0, 0};
-            if (in) {
-                tsv = st.ts[v];
-                ev = st.e[v];
-                dv = st.d[v];
-                fdv = st.fd[v];
+        for (int cg = 0; cg < nch; cg += kInitGroup) {
+            InitWords w[kInitGroup];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) fv[k] = st.fl[(size_t)k * Ntot + v];
-            }
-            // the chunk's words of the bit masks, one mask per lane 0..5
-            unsigned long long wm[kMasks];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) wm[kMaskFl + k] = __ballot(in && fv[k] > 0);
-            wm[kMaskFd] = __ballot(in && fdv > 0);
-            unsigned long long mine = 0;
-#pragma unroll
-            for (int m = 0; m < kMasks; ++m)
-                if (lane == m) mine = wm[m];
-            if (lane < kMasks) g.bits[((size_t)lane * g.max_nch + c) * Ptot + p] = mine;
-            if (t1 == K) {
-                const unsigned long long sm = __ballot(in && tsv > 0);
-                if (sm) t1 = c * kWave + __ffsll((long long)sm) - 1;
-            }
-            const bool lab = in && z >= t1;
-            if (in) st.d[v] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
-            const bool isact = in && ev > 0 && dv < kInf;
-            if (isact) ++act.acc;
-            if (la == K) {
-                const unsigned long long am = __ballot(isact);
-                if (am) la = c * kWave + __ffsll((long long)am) - 1;
+            for (int j = 0; j < kInitGroup; ++j) {
+                const int z = (cg + j) * kWave + lane;
+                load_init_words(st, Ntot, base + z, z < K, w[j]);
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (lf[k] < K) continue;
-                const unsigned long long fm = __ballot(lab && fv[k] > 0);
-                if (fm) lf[k] = c * kWave + __ffsll((long long)fm) - 1;
+            for (int j = 0; j < kInitGroup; ++j) {
+                const int c = cg + j;
+                if (c >= nch) break;
+                const int z = c * kWave + lane;
+                const bool in = z < K;
+                // the chunk's words of the bit masks, one mask per lane 0..5
+                unsigned long long wm[kMasks];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) wm[kMaskFl + k] = __ballot(in && w[j].f[k] > 0);
+                wm[kMaskFd] = __ballot(in && w[j].fd > 0);
+                unsigned long long mine = 0;
+#pragma unroll
+                for (int m = 0; m < kMasks; ++m)
+                    if (lane == m) mine = wm[m];
+                if (lane < kMasks) g.bits[((size_t)lane * g.max_nch + c) * Ptot + p] = mine;
+                if (t1 == K) {
+                    const unsigned long long sm = __ballot(in && w[j].ts > 0);
+                    if (sm) t1 = c * kWave + __ffsll((long long)sm) - 1;
+                }
+                const bool lab = in && z >= t1;
+                const int dv = w[j].d;
+                if (in) st.d[base + z] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
+                const bool isact = in && w[j].e > 0 && dv < kInf;
+                if (isact) ++act.acc;
+                if (la == K) {
+                    const unsigned long long am = __ballot(isact);
+                    if (am) la = c * kWave + __ffsll((long long)am) - 1;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (lf[k] < K) continue;
+                    const unsigned long long fm = __ballot(lab && w[j].f[k] > 0);
+                    if (fm) lf[k] = c * kWave + __ffsll((long long)fm) - 1;
+                }
             }
         }
         // a column whose lowest active node lies below the level-1 suffix
@@ -1259,16 +1310,29 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
 // it did not finish, which is a valid lower bound of their distance).
 __global__ __launch_bounds__(256) void k_bfs_fixup(Geom g, int *d, int c0, int c1)
 {
+    constexpr int kGroup = 4;   // chunks whose labels are loaded together
     const int lane = lane_id();
     int lo, hi;
     wave_range(c0, c1, lo, hi);
+    VolCache vc;
+    int fill = -1;
     for (int p = lo; p < hi; ++p) {
-        const Col col = column_uniform(g, p);
-        const int fill = g.fill[col.ii];
+        if (vc.at(g, p)) fill = g.fill[vc.ii];
         if (fill < 0) continue;
-        for (int c = 0; c < col.I.nch; ++c) {
-            const int z = c * kWave + lane;
-            if (z < col.I.K && d[col.base + z] == kUnl) d[col.base + z] = fill;
+        const int K = vc.I.K;
+        int *dc = d + vc.base(p);
+        for (int z0 = 0; z0 < K; z0 += kGroup * kWave) {
+            int dv[kGroup];
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) {
+                const int z = z0 + j * kWave + lane;
+                dv[j] = z < K ? dc[z] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) {
+                const int z = z0 + j * kWave + lane;
+                if (z < K && dv[j] == kUnl) dc[z] = fill;
+            }
         }
     }
 }
@@ -1416,16 +1480,33 @@ void launch_bfs_begin(const Geom &g, hipStream_t st)
 }
 
 // Grid of the wave-per-column kernels over the columns [c0, c1).
-static inline unsigned range_wave_blocks(int c0, int c1)
+static inline unsigned range_wave_blocks(int c0, int c1, unsigned cap = 2048)
 {
     long long want = ((long long)c1 - c0 + 3) / 4;
-    return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+    if (want > (long long)cap) want = cap;
+    return (unsigned)(want > 0 ? want : 1);
+}
+
+// Blocks of `block` threads of kernel f that the chip holds at once (2048
+// if the runtime cannot tell).  A wave-per-column kernel whose waves each
+// take a fixed share of the columns runs in one round on such a grid, with
+// no second round of a few waves at the end.
+static unsigned resident_blocks(const void *f, int block)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, block, 0) != hipSuccess || per < 1 ||
+        cus < 1)
+        return 2048;
+    return (unsigned)per * (unsigned)cus;
 }
 
 void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, int c1, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_init, dim3(range_wave_blocks(c0, c1)), dim3(256), 0, st, g, sv, T, LF,
-                       c0, c1);
+    static const unsigned cap = resident_blocks(reinterpret_cast<const void *>(k_bfs_init), 256);
+    hipLaunchKernelGGL(k_bfs_init, dim3(range_wave_blocks(c0, c1, cap)), dim3(256), 0, st, g, sv, T,
+                       LF, c0, c1);
 }
 
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
@@ -1444,7 +1525,9 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_fixup, dim3(range_wave_blocks(c0, c1)), dim3(256), 0, st, g, sv.d, c0, c1);
+    static const unsigned cap = resident_blocks(reinterpret_cast<const void *>(k_bfs_fixup), 256);
+    hipLaunchKernelGGL(k_bfs_fixup, dim3(range_wave_blocks(c0, c1, cap)), dim3(256), 0, st, g, sv.d,
+                       c0, c1);
 }
 
 void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st)
