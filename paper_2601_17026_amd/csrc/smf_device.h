@@ -23,6 +23,7 @@ constexpr int kErrCostRange = 1;       // a cost outside (-2^30, 2^30)
 constexpr int kErrOverflow = 2;        // an int32 excess or flow would overflow
 constexpr int kWave = 64;              // CDNA wavefront width = heights per chunk
 constexpr int kLvlSlots = 64;          // BFS level flags kept per volume
+constexpr int kMaxRanges = 16;         // column ranges a BFS level launch covers
 
 // Geometry of one volume of the batch (64 bytes, read with scalar loads).
 struct Inst {
@@ -111,6 +112,14 @@ struct Work {
 // Batch-wide device counters and flags.  The per-volume counters follow
 // them in the same allocation, kScratchHead bytes after the start, so one
 // copy snapshots both.
+// Columns that a BFS level launch covers: thread t with pre[r] <= t <
+// pre[r + 1] (r < n) takes column lo[r] + t - pre[r].
+struct LevelRanges {
+    int n;
+    int lo[kMaxRanges];
+    int pre[kMaxRanges + 1];
+};
+
 struct Scratch {
     int err;             // kErr* bits
     int changed;         // a min-cut pass changed something

@@ -33,7 +33,7 @@ void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, h
 void launch_bfs_begin(const Geom &g, hipStream_t st);
 void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, int c1, hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      int *Tout, int *LFout, int c0, int c1, hipStream_t st);
+                      int *Tout, int *LFout, const LevelRanges &R, hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
@@ -422,6 +422,60 @@ static int sync_scratch(smf_handle *h, hipStream_t s)
 // unfinished level, a valid lower bound).  The host checks every
 // bfs_poll_every levels; levels launched after a volume's last productive
 // one are no-ops for it.
+// Chooses the volumes that the next levels of a search cover: every volume
+// in `live`, and of the others in `cover` only those in the smallest gaps
+// between runs of live volumes, as many as keep the covered volumes within
+// kMaxRanges runs of consecutive volumes (volumes are packed in order, so a
+// run is one column range).  `cover` only ever shrinks during a search: a
+// level may cover a column only if every earlier level covered it, since
+// the record buffers of a column that a level skipped fall behind.  Every
+// live volume lies in `cover`, and `cover` forms at most kMaxRanges runs,
+// so the gaps inside a run of `cover` always suffice.
+static void shrink_cover(const smf_handle *h, const std::vector<char> &live, std::vector<char> &cover,
+                         LevelRanges &R)
+{
+    const int n = h->n;
+    std::vector<std::pair<int, int>> runs;   // first and last volume of each run of live volumes
+    for (int i = 0; i < n; ++i) {
+        if (!live[i]) continue;
+        if (!runs.empty() && runs.back().second == i - 1) runs.back().second = i;
+        else runs.push_back({i, i});
+    }
+    // gaps between consecutive runs whose volumes are all still covered
+    std::vector<std::pair<long long, size_t>> gaps;   // (columns, run before the gap)
+    for (size_t k = 0; k + 1 < runs.size(); ++k) {
+        bool ok = true;
+        long long cols = 0;
+        for (int i = runs[k].second + 1; i < runs[k + 1].first; ++i) {
+            ok = ok && cover[i];
+            cols += h->inst[i].P;
+        }
+        if (ok) gaps.push_back({cols, k});
+    }
+    std::sort(gaps.begin(), gaps.end());
+    std::vector<char> join(runs.size(), 0);   // run k continues into run k + 1
+    size_t nruns = runs.size();
+    for (const auto &gp : gaps) {
+        if (nruns <= (size_t)kMaxRanges) break;
+        join[gp.second] = 1;
+        --nruns;
+    }
+    std::vector<char> next((size_t)n, 0);
+    R.n = 0;
+    R.pre[0] = 0;
+    for (size_t k = 0; k < runs.size();) {
+        size_t e = k;
+        while (join[e]) ++e;
+        const int a = runs[k].first, b = runs[e].second;
+        for (int i = a; i <= b; ++i) next[i] = 1;
+        R.lo[R.n] = h->inst[a].col_base;
+        R.pre[R.n + 1] = R.pre[R.n] + (h->inst[b].col_base + h->inst[b].P - h->inst[a].col_base);
+        ++R.n;
+        k = e + 1;
+    }
+    cover.swap(next);
+}
+
 static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> &part)
 {
     const int n = h->n;
@@ -441,6 +495,17 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         }
     }
     if (c0 >= c1) return SMF_OK;
+    // The levels cover the volumes of [c0, c1) that take part (others only
+    // where more than kMaxRanges column ranges would be needed); a volume
+    // whose search has ended drops out of the later levels, with its fill
+    // label fixed when it leaves (fill_out).
+    std::vector<char> live(part.begin(), part.end()), cover((size_t)n, 0);
+    std::vector<int> fill_out((size_t)n, -1);
+    for (int i = 0; i < n; ++i)
+        cover[i] = h->inst[i].col_base >= c0 && h->inst[i].col_base < c1;
+    LevelRanges R;
+    shrink_cover(h, live, cover, R);
+    if (R.n > kMaxRanges) return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
     HIP_TRY(hipMemcpyAsync(h->part_dev, h->part_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
     launch_bfs_begin(h->g, s);
     launch_set_int(&h->scr->short_count, 0, s);
@@ -460,7 +525,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         {
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
             for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L, cur ^= 1) {
-                launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], T[cur ^ 1], LF[cur ^ 1], c0, c1, s);
+                launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], T[cur ^ 1], LF[cur ^ 1], R, s);
                 h->bfs_passes++;
             }
         }
@@ -476,22 +541,31 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
             if (rc) return rc;
             // at that snapshot the last level launched had produced level Lp
             const int Lp = Lsnap[slot ^ 1];
-            bool all = true;
-            for (int i = 0; i < n && all; ++i) {
-                if (!part[i]) continue;
+            bool all = true, ended = false;
+            for (int i = 0; i < n; ++i) {
+                if (!live[i]) continue;
                 const InstScratch &r = h->is_host[i];
                 const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
                 const bool labelled = h->bfs_early_stop && r.bfs_unsat[Csnap[slot ^ 1]] == 0;
-                all = complete || labelled;
+                if (complete || labelled) {
+                    live[i] = 0;
+                    ended = true;
+                    // levels < L have run over it: unreached nodes are > L away
+                    fill_out[i] = complete ? kInf : L + 1;
+                } else {
+                    all = false;
+                }
             }
             if (all) {
-                // levels <= L are complete now (the batch after the snapshot included)
+                // levels < L are complete now (the batch after the snapshot
+                // included); a volume still covered takes the latest fill
                 for (int i = 0; i < n; ++i) {
                     const bool complete = !h->is_host[i].lvl_changed[(Lp - 1) % kLvlSlots];
-                    h->fill_up[i] = !part[i] ? -1 : (complete ? kInf : L + 1);
+                    h->fill_up[i] = !part[i] ? -1 : !cover[i] ? fill_out[i] : (complete ? kInf : L + 1);
                 }
                 break;
             }
+            if (ended) shrink_cover(h, live, cover, R);
         }
         inflight = true;
         slot ^= 1;

@@ -1241,22 +1241,24 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
     }
 }
 
-// Level L -> L+1, one lane per column.  The threshold arithmetic reads the
-// records of the column and its neighbours; the lowest flow-carrying
-// lateral arcs among the newly reached heights [cand, T) come from the
-// column's bit masks, so no per-node word is read.
+// Level L -> L+1, one lane per column of the ranges R.  The threshold
+// arithmetic reads the records of the column and its neighbours; the lowest
+// flow-carrying lateral arcs among the newly reached heights [cand, T) come
+// from the column's bit masks, so no per-node word is read.
 __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d, int L,
                                                    const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin, int *__restrict__ Tout,
-                                                   int *__restrict__ LFout, int c0, int c1)
+                                                   int *__restrict__ LFout, LevelRanges R)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int p = c0 + t;
     // the flags of the next level are cleared here; stream order puts this
     // before every write of level L+1
     if (t < g.n) g.is[t].lvl_changed[(L + 1) % kLvlSlots] = 0;
     const int P = g.Ptot;
-    const bool valid = p < c1;
+    int r = 0;
+    for (int j = 1; j < R.n; ++j) r += t >= R.pre[j];
+    const bool valid = t < R.pre[R.n];
+    const int p = valid ? R.lo[r] + (t - R.pre[r]) : 0;
     bool self = false, near = false;
     int T = 0, cand = 0, ii = 0;
     long long base = 0;
@@ -1515,12 +1517,13 @@ void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      int *Tout, int *LFout, int c0, int c1, hipStream_t st)
+                      int *Tout, int *LFout, const LevelRanges &R, hipStream_t st)
 {
-    const long long n = (long long)c1 - c0 > g.n ? (long long)c1 - c0 : g.n;
+    const long long cols = R.pre[R.n];
+    const long long n = cols > g.n ? cols : g.n;
     const int b = g.level_block;
     hipLaunchKernelGGL(k_bfs_level, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d, L, Tin,
-                       LFin, Tout, LFout, c0, c1);
+                       LFin, Tout, LFout, R);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)
