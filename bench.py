@@ -56,6 +56,12 @@ def parse():
                     help="only run a 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default relabel period instead of running the autotuner")
+    ap.add_argument("--relabel-period", type=int, default=0, metavar="N",
+                    help="use relabel period N for every volume instead of running the autotuner")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the batched leg (prints its JSON object)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the 64 plain solves that the batched leg compares against")
     ap.add_argument("--counters-summary", metavar="DIR",
                     help="only summarise a rocprofv3 --pmc output directory: mean counter "
                          "values per dispatch of every kernel, one JSON line per kernel")
@@ -151,7 +157,11 @@ def batched_leg(args, torch, smf, synth, stream):
     # the autotuner picks each volume class's relabel period (set-up, not
     # timed); the batch and the plain solves both use its choices
     t0 = time.perf_counter()
-    if not args.no_tune:
+    if args.relabel_period > 0:
+        batch.set_param("relabel_period", args.relabel_period)
+        for s in plain:
+            s.set_param("relabel_period", args.relabel_period)
+    elif not args.no_tune:
         smf.autotune(batch, packed, stream=stream)
         for s in plain:
             smf.tune_apply(s)
@@ -168,15 +178,20 @@ def batched_leg(args, torch, smf, synth, stream):
     flows = batch.flow_values()
     sweeps = batch.stat("sweeps")
 
-    for i in range(4):                           # warm-up
-        plain[i].solve(views[i], stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s, v in zip(plain, views):
-        s.solve(v, stream)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    same = all(s.flow_value() == f for s, f in zip(plain, flows))
+    seq = {}
+    if not args.no_sequential:
+        for i in range(4):                           # warm-up
+            plain[i].solve(views[i], stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, v in zip(plain, views):
+            s.solve(v, stream)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        seq = {"sequential_plain_value": round(V / t_seq / 1e6, 3),
+               "ms_sequential_plain": round(1e3 * t_seq, 2),
+               "speedup_vs_sequential": round(t_seq / t_batch, 3),
+               "flows_equal_plain": all(s.flow_value() == f for s, f in zip(plain, flows))}
     for s in plain:
         s.close()
     batch.close()
@@ -185,15 +200,12 @@ def batched_leg(args, torch, smf, synth, stream):
         "unit": "Mvoxels/s",
         "ms_per_batch": round(1e3 * t_batch, 2),
         "steps": args.batch_steps,
-        "sequential_plain_value": round(V / t_seq / 1e6, 3),
-        "ms_sequential_plain": round(1e3 * t_seq, 2),
-        "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        **seq,
         "volumes": len(shapes),
         "voxels": V,
         "batch_sweeps": sweeps,
         "autotune_seconds": round(t_tune, 2),
         "relabel_periods": {str(p): periods.count(p) for p in sorted(set(periods))},
-        "flows_equal_plain": same,
         "workload": "64 volumes, nx, ny, K ~ U{64..256}, delta ~ U{1,2,3}, two layered "
                     "horizons, sigma 0.4, costs 0..255 (per-volume seeds)",
     }
@@ -216,6 +228,11 @@ def main():
 
     from paper_2601_17026_amd import smf, synth
 
+    if args.batch_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched": batched_leg(args, torch, smf, synth, torch.cuda.current_stream())}),
+              flush=True)
+        return
     cost, delta = synth.config_seismic()
     nx, ny, K = cost.shape
     V = cost.size
@@ -225,7 +242,9 @@ def main():
     stream = torch.cuda.current_stream()
     solver = smf.Solver(nx, ny, K, delta)
     tune_s = 0.0
-    if not args.no_tune:
+    if args.relabel_period > 0:
+        solver.set_param("relabel_period", args.relabel_period)
+    elif not args.no_tune:
         # the autotuner times the candidate relabel periods (set-up, not timed)
         t0 = time.perf_counter()
         smf.autotune(solver, c, stream=stream)
