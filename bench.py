@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--batch-steps", type=int, default=2)
-    ap.add_argument("--cpu-crop", type=int, default=48,
+    ap.add_argument("--cpu-crop", type=int, default=56,
                     help="columns per side of the oracle's CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (HBM counter calibration)")

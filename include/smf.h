@@ -197,7 +197,7 @@ int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
  * handle's volumes that the process-wide tuning cache does not hold yet,
  * the largest volume of that class is solved on a temporary handle with
  * each candidate period (2, 3, 4, 6, 8, 12), timed on the host clock (the
- * fastest of three runs when a solve takes under 50 ms), and the fastest
+ * fastest of three runs when a solve takes under 2 s), and the fastest
  * period is cached; then every volume of `h` gets
  * its class's period (smf_batch_set_param).  For a batch of more than one
  * volume the tuner then times whole solves of `h` with every volume's

@@ -829,7 +829,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // d(w) + len(u, w) (kInf when that exceeds every possible distance).  The
 // column's mask is rebuilt from the nodes that stay active, which are
 // counted per volume, and the column goes on the next push phase's list.
-__global__ __launch_bounds__(256) void k_relabel(Geom g, State st, Work win, Work wout)
+// Eight waves per SIMD (64 VGPRs, a few spilled): with the sweep grid of
+// 8192 waves every wave is resident at once, and the phase is bound by
+// memory latency, which more waves in flight hide.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_relabel(Geom g, State st, Work win, Work wout)
 {
     const int lane = lane_id();
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -1002,7 +1005,7 @@ __device__ __forceinline__ void load_init_words(const State &st, size_t Ntot, si
 }
 
 // chunks of a column whose words level 1 requests together
-constexpr int kInitGroup = 4;
+constexpr int kInitGroup = 2;
 
 // Level 1, one wave per column.  Nodes that could not reach t before keep
 // kInf: new residual arcs only ever join nodes that reach t, so a node cut
@@ -1010,8 +1013,9 @@ constexpr int kInitGroup = 4;
 // finite label, and those of them labelled 1, for the early stop, and
 // writes the column's bit masks (flows and excess do not change during the
 // search).  The words of kInitGroup chunks are loaded before any of them
-// is used, so that a wave keeps that many chunks' loads in flight.
-__global__ __launch_bounds__(256) void k_bfs_init(Geom g, State st, int *T, int *LF, int c0, int c1)
+// is used, so that a wave keeps that many chunks' loads in flight; at eight
+// waves per SIMD.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_bfs_init(Geom g, State st, int *T, int *LF, int c0, int c1)
 {
     const int lane = lane_id();
     const size_t Ntot = (size_t)g.Ntot;

@@ -47,8 +47,10 @@ bool g_env_loaded = false;
 const int64_t kCandidates[] = {2, 3, 4, 6, 8, 12};
 // scale factors 1, 1.5, 2 and 3 (doubled) of the whole-batch step
 const int kBatchScale2[] = {2, 3, 4, 6};
-// a solve shorter than this is timed three times and the fastest counts
-constexpr int64_t kShortSolveNs = 50000000;
+// a solve shorter than this (2 s) is timed three times and the fastest
+// counts: run-to-run spread of a solve is a few percent, as large as the
+// differences between neighbouring periods
+constexpr int64_t kShortSolveNs = 2000000000;
 
 int ceil_log2(int64_t v)
 {
