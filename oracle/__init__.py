@@ -3,10 +3,10 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product library never calls it.
 
-`solve(cost, delta)` returns the max-flow value, the minimal and maximal
-minimum-cut surfaces and the optimal energy of an int32 cost volume
+`solve(cost, delta, alpha=0)` returns the max-flow value, the minimal and
+maximal minimum-cut surfaces and the optimal energy of an int32 cost volume
 c[x, y, z] (z fastest), computed by Dinic's method on the explicit s-t graph
-(oracle.c).  `certify(...)` checks a solver's final preflow against the
+(oracle.c); alpha > 0 adds the soft smoothness term.  `certify(...)` checks a solver's final preflow against the
 max-flow/min-cut certificate (certify.c).  Both are plain C built with gcc.
 """
 from __future__ import annotations
@@ -75,6 +75,10 @@ def _load():
         lib.oracle_solve.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, P, P, ctypes.POINTER(_Result)]
         lib.oracle_solve.restype = ctypes.c_int
+        lib.oracle_solve_soft.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, P, P,
+                                          ctypes.POINTER(_Result)]
+        lib.oracle_solve_soft.restype = ctypes.c_int
         lib.certify_preflow.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, P, P, P, P, P,
                                         ctypes.POINTER(_Cert)]
@@ -87,7 +91,7 @@ def _load():
 class OracleResult:
     flow: int          # max-flow value |f| (Eq. 5)
     cut: int           # capacity of the minimal min cut (Eq. 6)
-    energy: int        # E* = sum_p c(p, h_min(p))
+    energy: int        # E* = sum_p c(p, h_min(p)) (+ alpha * sum |h(p) - h(q)|)
     energy_hmax: int   # sum_p c(p, h_max(p)) (equal to E* when correct)
     wminus: int        # total source-arc capacity
     phases: int        # Dinic phases
@@ -98,7 +102,9 @@ class OracleResult:
     smin_in_smax: bool
 
 
-def solve(cost: np.ndarray, delta: int) -> OracleResult:
+def solve(cost: np.ndarray, delta: int, alpha: int = 0) -> OracleResult:
+    """alpha > 0 adds the soft smoothness term alpha * sum |h(p) - h(q)| over
+    4-neighbour column pairs (finite arcs (p,z) -> (q,z), z >= 1)."""
     c = np.ascontiguousarray(cost, dtype=np.int32)
     if c.ndim != 3:
         raise ValueError("cost must be (nx, ny, K)")
@@ -106,8 +112,8 @@ def solve(cost: np.ndarray, delta: int) -> OracleResult:
     hmin = np.empty((nx, ny), dtype=np.int32)
     hmax = np.empty((nx, ny), dtype=np.int32)
     r = _Result()
-    rc = _load().oracle_solve(c.ctypes.data, nx, ny, K, int(delta),
-                              hmin.ctypes.data, hmax.ctypes.data, ctypes.byref(r))
+    rc = _load().oracle_solve_soft(c.ctypes.data, nx, ny, K, int(delta), int(alpha),
+                                   hmin.ctypes.data, hmax.ctypes.data, ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"oracle_solve failed with status {rc}")
     return OracleResult(r.flow, r.cut, r.energy, r.energy_hmax, r.wminus, r.phases,

@@ -16,7 +16,8 @@
  *     reachable from s in the residual graph, its capacity (Eq. 6), and
  *     the complement of the set that reaches t (the maximal min cut);
  *   - the surfaces h_min(p) = max{z : (p,z) in S_min}, h_max likewise, and
- *     E* = sum_p c(p, h_min(p)) (Eq. 1, feature term);
+ *     E* = sum_p c(p, h_min(p)) (Eq. 1, feature term; plus the smoothness
+ *     term below when alpha > 0);
  *   - self-checks of the capacity and conservation constraints (Eqs. 2-4)
  *     and of max-flow = min-cut (Theorem 1.1).
  *
@@ -28,6 +29,14 @@
  *   z - delta)) infinite for every 4-neighbour q of p inside the grid.
  * Arcs leaving the grid do not exist (Section 3.3: boundary arcs have zero
  * capacity).
+ *
+ * Soft smoothness (the edge costs of the VCE-weight net surface, Section
+ * 1.2, with the convex cost alpha * |h(p) - h(q)| inside the edge
+ * interval): with alpha > 0 every 4-neighbour pair also gets the arcs
+ * (p,z) -> (q,z) of capacity alpha for z >= 1.  A closed set with column
+ * heights h cuts max(0, h(p) - h(q)) of them from p to q, so a cut costs
+ * alpha * sum over neighbour pairs of |h(p) - h(q)| more, and the reported
+ * energies include that term.
  *
  * Written from the definitions; shares no code with the GPU library.
  */
@@ -75,7 +84,7 @@ static void free_graph(or_graph *g)
 typedef void (*arc_fn)(void *ctx, int64_t u, int64_t v, int64_t cap);
 
 static void for_each_arc(const int32_t *c, int64_t nx, int64_t ny, int64_t K,
-                         int64_t delta, arc_fn fn, void *ctx)
+                         int64_t delta, int64_t alpha, arc_fn fn, void *ctx)
 {
     const int64_t N = nx * ny * K, s = N, t = N + 1;
     int64_t B = INT64_MIN;
@@ -100,6 +109,7 @@ static void for_each_arc(const int32_t *c, int64_t nx, int64_t ny, int64_t K,
                     int64_t qx = x + dx[d], qy = y + dy[d];
                     if (qx < 0 || qx >= nx || qy < 0 || qy >= ny) continue;
                     fn(ctx, v, node_id(qx, qy, zt, ny, K), OR_INF);
+                    if (alpha > 0 && z >= 1) fn(ctx, v, node_id(qx, qy, z, ny, K), alpha);
                 }
             }
 }
@@ -124,14 +134,14 @@ static void place_arc(void *ctx, int64_t u, int64_t v, int64_t cap)
 }
 
 static int build_graph(or_graph *g, const int32_t *c, int64_t nx, int64_t ny,
-                       int64_t K, int64_t delta)
+                       int64_t K, int64_t delta, int64_t alpha)
 {
     memset(g, 0, sizeof(*g));
     g->n = nx * ny * K + 2;
     g->first = calloc((size_t)g->n + 1, sizeof(int64_t));
     if (!g->first) return -1;
     build_ctx b = {g, NULL};
-    for_each_arc(c, nx, ny, K, delta, count_arc, &b);
+    for_each_arc(c, nx, ny, K, delta, alpha, count_arc, &b);
     for (int64_t i = 0; i < g->n; ++i) g->first[i + 1] += g->first[i];
     g->m = g->first[g->n];
     g->head = malloc((size_t)g->m * sizeof(int64_t));
@@ -143,7 +153,7 @@ static int build_graph(or_graph *g, const int32_t *c, int64_t nx, int64_t ny,
         free(b.fill); free_graph(g); return -1;
     }
     memcpy(b.fill, g->first, (size_t)g->n * sizeof(int64_t));
-    for_each_arc(c, nx, ny, K, delta, place_arc, &b);
+    for_each_arc(c, nx, ny, K, delta, alpha, place_arc, &b);
     free(b.fill);
     return 0;
 }
@@ -239,18 +249,33 @@ static void reach_to(const or_graph *g, int64_t dst, uint8_t *mark, int64_t *que
     }
 }
 
+/* alpha * sum over 4-neighbour column pairs of |h(p) - h(q)|. */
+static int64_t smooth_term(const int32_t *h, int64_t nx, int64_t ny, int64_t alpha)
+{
+    int64_t sum = 0;
+    for (int64_t x = 0; x < nx; ++x)
+        for (int64_t y = 0; y < ny; ++y) {
+            const int64_t a = h[x * ny + y];
+            if (x + 1 < nx) sum += llabs(a - h[(x + 1) * ny + y]);
+            if (y + 1 < ny) sum += llabs(a - h[x * ny + y + 1]);
+        }
+    return alpha * sum;
+}
+
 /*
- * Solve one volume.  cost: nx*ny*K int32, z fastest.  Outputs hmin, hmax
- * (nx*ny int32 each, may be NULL).  Returns 0 on success, -1 on bad
- * arguments, -2 when memory runs out.
+ * Solve one volume.  cost: nx*ny*K int32, z fastest; alpha >= 0 the soft
+ * smoothness weight (0: hard bound only).  Outputs hmin, hmax (nx*ny int32
+ * each, may be NULL).  Returns 0 on success, -1 on bad arguments, -2 when
+ * memory runs out.
  */
-int oracle_solve(const int32_t *cost, int32_t nx, int32_t ny, int32_t K,
-                 int32_t delta, int32_t *hmin, int32_t *hmax, or_result *out)
+int oracle_solve_soft(const int32_t *cost, int32_t nx, int32_t ny, int32_t K,
+                      int32_t delta, int32_t alpha, int32_t *hmin, int32_t *hmax,
+                      or_result *out)
 {
     memset(out, 0, sizeof(*out));
-    if (!cost || nx < 1 || ny < 1 || K < 1 || delta < 0) return out->status = -1;
+    if (!cost || nx < 1 || ny < 1 || K < 1 || delta < 0 || alpha < 0) return out->status = -1;
     or_graph g;
-    if (build_graph(&g, cost, nx, ny, K, delta)) return out->status = -2;
+    if (build_graph(&g, cost, nx, ny, K, delta, alpha)) return out->status = -2;
     const int64_t N = (int64_t)nx * ny * K, s = N, t = N + 1;
     int64_t *level = malloc((size_t)g.n * sizeof(int64_t));
     int64_t *cur = malloc((size_t)g.n * sizeof(int64_t));
@@ -306,6 +331,7 @@ int oracle_solve(const int32_t *cost, int32_t nx, int32_t ny, int32_t K,
             }
     }
 
+    int32_t *hlo = (int32_t *)level, *hhi = (int32_t *)cur;   /* reuse: nx*ny heights each */
     for (int64_t x = 0; x < nx; ++x)
         for (int64_t y = 0; y < ny; ++y) {
             int32_t lo = -1, hi = -1;
@@ -315,13 +341,26 @@ int oracle_solve(const int32_t *cost, int32_t nx, int32_t ny, int32_t K,
                 if (!treach[v]) hi = z;
             }
             int64_t p = x * ny + y;
+            hlo[p] = lo;
+            hhi[p] = hi;
             if (hmin) hmin[p] = lo;
             if (hmax) hmax[p] = hi;
             if (lo >= 0) out->energy += cost[node_id(x, y, lo, ny, K)];
             if (hi >= 0) out->energy_hmax += cost[node_id(x, y, hi, ny, K)];
         }
+    if (alpha > 0) {
+        out->energy += smooth_term(hlo, nx, ny, alpha);
+        out->energy_hmax += smooth_term(hhi, nx, ny, alpha);
+    }
 
     free(level); free(cur); free(buf); free(sreach); free(treach); free(orig);
     free_graph(&g);
     return 0;
+}
+
+/* The hard-bound problem (alpha = 0). */
+int oracle_solve(const int32_t *cost, int32_t nx, int32_t ny, int32_t K,
+                 int32_t delta, int32_t *hmin, int32_t *hmax, or_result *out)
+{
+    return oracle_solve_soft(cost, nx, ny, K, delta, 0, hmin, hmax, out);
 }

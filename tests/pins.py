@@ -26,12 +26,13 @@ def neighbours(nx, ny):
     return out
 
 
-def brute_force(cost: np.ndarray, delta: int):
+def brute_force(cost: np.ndarray, delta: int, alpha: int = 0):
     """E*, the pointwise-lowest and pointwise-highest optimal surfaces.
 
     Enumerates all K^(nx*ny) height maps, keeps the delta-smooth ones and
-    takes the minimum of sum_p c(p, h(p)).  The optimal surfaces form a
-    lattice under pointwise min/max, so the pointwise min (max) over all
+    takes the minimum of sum_p c(p, h(p)) + alpha * sum |h(p) - h(q)| over
+    neighbour pairs.  The optimal surfaces form a lattice under pointwise
+    min/max (the energy is submodular), so the pointwise min (max) over all
     optimal surfaces is itself optimal.
     """
     nx, ny, K = cost.shape
@@ -43,6 +44,8 @@ def brute_force(cost: np.ndarray, delta: int):
         ok &= np.abs(H[:, a] - H[:, b]) <= delta
     H = H[ok]
     E = c[np.arange(P)[None, :], H].sum(axis=1)
+    for a, b in neighbours(nx, ny):
+        E = E + alpha * np.abs(H[:, a] - H[:, b])
     best = E.min()
     opt = H[E == best]
     return int(best), opt.min(axis=0).reshape(nx, ny), opt.max(axis=0).reshape(nx, ny)
@@ -60,13 +63,26 @@ def _window_min(a: np.ndarray, delta: int) -> np.ndarray:
     return out
 
 
-def row_dp(cost: np.ndarray, delta: int):
+def _window_min_penalty(a: np.ndarray, delta: int, alpha: int) -> np.ndarray:
+    """out[z] = min over |s| <= delta of a[z + s] + alpha * |s| (inside the array)."""
+    K = a.shape[0]
+    out = a.copy()
+    for s in range(1, delta + 1):
+        if s >= K:
+            break
+        out[:-s] = np.minimum(out[:-s], a[s:] + alpha * s)
+        out[s:] = np.minimum(out[s:], a[:-s] + alpha * s)
+    return out
+
+
+def row_dp(cost: np.ndarray, delta: int, alpha: int = 0):
     """Exact optimum for a single row of columns (cost shape (n, K)).
 
     Forward and backward min-plus recurrences over the chain of columns:
-    Fw[x][z] = c(x,z) + min_{|z'-z|<=delta} Fw[x-1][z'] and the mirror
-    image Bw.  The best surface through (x, z) costs Fw + Bw - c; the lowest
-    (highest) z attaining E* at x is h_min(x) (h_max(x)).
+    Fw[x][z] = c(x,z) + min_{|z'-z|<=delta} (Fw[x-1][z'] + alpha |z - z'|)
+    and the mirror image Bw.  The best surface through (x, z) costs
+    Fw + Bw - c; the lowest (highest) z attaining E* at x is h_min(x)
+    (h_max(x)).
     """
     c = cost.astype(np.int64)
     n, K = c.shape
@@ -74,10 +90,10 @@ def row_dp(cost: np.ndarray, delta: int):
     Bw = np.empty_like(c)
     Fw[0] = c[0]
     for x in range(1, n):
-        Fw[x] = c[x] + _window_min(Fw[x - 1], delta)
+        Fw[x] = c[x] + _window_min_penalty(Fw[x - 1], delta, alpha)
     Bw[n - 1] = c[n - 1]
     for x in range(n - 2, -1, -1):
-        Bw[x] = c[x] + _window_min(Bw[x + 1], delta)
+        Bw[x] = c[x] + _window_min_penalty(Bw[x + 1], delta, alpha)
     best = int(Fw[n - 1].min())
     through = Fw + Bw - c
     hit = through == best
@@ -98,8 +114,9 @@ def flow_closed_form(cost: np.ndarray, energy: int) -> int:
     return int(energy - c[:, :, 0].sum() + drops)
 
 
-def explicit_arcs(cost: np.ndarray, delta: int, inf: int):
-    """(tail, head, capacity) triples of G(c, delta), s = N, t = N + 1."""
+def explicit_arcs(cost: np.ndarray, delta: int, inf: int, alpha: int = 0):
+    """(tail, head, capacity) triples of G(c, delta), s = N, t = N + 1; with
+    alpha > 0 also the soft arcs (p,z) -> (q,z) of capacity alpha, z >= 1."""
     nx, ny, K = cost.shape
     c = cost.astype(np.int64)
     N = nx * ny * K
@@ -121,26 +138,36 @@ def explicit_arcs(cost: np.ndarray, delta: int, inf: int):
                 for qx, qy in ((x + 1, y), (x - 1, y), (x, y + 1), (x, y - 1)):
                     if 0 <= qx < nx and 0 <= qy < ny:
                         arcs.append((v, idx(qx, qy, max(0, z - delta)), inf))
+                        if alpha > 0 and z >= 1:
+                            arcs.append((v, idx(qx, qy, z), alpha))
     return arcs, s, t, N + 2
 
 
-def scipy_flow(cost: np.ndarray, delta: int) -> int:
+def scipy_flow(cost: np.ndarray, delta: int, alpha: int = 0) -> int:
     import scipy.sparse as sp
     from scipy.sparse.csgraph import maximum_flow
 
-    arcs, s, t, n = explicit_arcs(cost, delta, inf=1 << 28)
+    arcs, s, t, n = explicit_arcs(cost, delta, inf=1 << 28, alpha=alpha)
     a = np.array(arcs, dtype=np.int64)
+    # parallel arcs (a soft and an infinite arc between the same nodes at
+    # delta = 0) add up, as the sparse constructor sums duplicates
     m = sp.csr_array((a[:, 2].astype(np.int32), (a[:, 0], a[:, 1])), shape=(n, n))
     return int(maximum_flow(m, s, t).flow_value)
 
 
-def networkx_flow(cost: np.ndarray, delta: int) -> int:
+def networkx_flow(cost: np.ndarray, delta: int, alpha: int = 0) -> int:
     import networkx as nx_
 
-    arcs, s, t, n = explicit_arcs(cost, delta, inf=-1)
+    arcs, s, t, n = explicit_arcs(cost, delta, inf=-1, alpha=alpha)
+    # parallel arcs (a soft and an infinite arc between the same nodes at
+    # delta = 0) are merged: infinite if either is, else capacities add
+    merged = {}
+    for u, v, cap in arcs:
+        old = merged.get((u, v))
+        merged[(u, v)] = cap if old is None else (-1 if old < 0 or cap < 0 else old + cap)
     g = nx_.DiGraph()
     g.add_nodes_from(range(n))
-    for u, v, cap in arcs:
+    for (u, v), cap in merged.items():
         if cap < 0:
             g.add_edge(u, v)          # no capacity attribute = infinite
         else:

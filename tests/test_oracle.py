@@ -169,3 +169,101 @@ def test_certificate_rejects_mistakes():
     ts0 = np.maximum(0, w).astype(np.int32)
     z = oracle.certify(c, delta, e0, ts0, N0, np.zeros_like(fl), r.hmin)
     assert z.bad_conservation == 0 and not z.ok
+
+
+# ---- soft smoothness: alpha * sum |h(p) - h(q)| over neighbour pairs ----------
+
+def _soft_energy(cost, h, alpha):
+    E = int(np.take_along_axis(cost.astype(np.int64), h[:, :, None].astype(np.int64), 2).sum())
+    hh = h.astype(np.int64)
+    return E + alpha * int(np.abs(np.diff(hh, axis=0)).sum() + np.abs(np.diff(hh, axis=1)).sum())
+
+
+def _check_soft_invariants(cost, delta, alpha, r):
+    assert r.conservation_ok and r.capacity_ok and r.smin_in_smax
+    assert r.flow == r.cut                                   # Theorem 1.1
+    assert r.flow == pins.flow_closed_form(cost, r.energy)   # same closed form
+    assert r.energy == r.energy_hmax
+    assert r.energy == _soft_energy(cost, r.hmin, alpha)
+    for h in (r.hmin, r.hmax):
+        assert np.abs(np.diff(h.astype(np.int64), axis=0)).max(initial=0) <= delta
+        assert np.abs(np.diff(h.astype(np.int64), axis=1)).max(initial=0) <= delta
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 4), (2, 2, 4), (2, 3, 3), (3, 2, 4), (1, 6, 3)])
+@pytest.mark.parametrize("delta", [0, 1, 2])
+@pytest.mark.parametrize("alpha", [1, 3, 25])
+def test_soft_brute_force(shape, delta, alpha):
+    for seed in range(3):
+        c = synth.random_cost(*shape, -20, 20, seed=hash((shape, delta, alpha, seed)) % 2**31)
+        r = oracle.solve(c, delta, alpha)
+        E, hmin, hmax = pins.brute_force(c, delta, alpha)
+        assert r.energy == E
+        np.testing.assert_array_equal(r.hmin, hmin)
+        np.testing.assert_array_equal(r.hmax, hmax)
+        _check_soft_invariants(c, delta, alpha, r)
+
+
+@pytest.mark.parametrize("n,K,delta,alpha", [(40, 24, 2, 3), (33, 16, 4, 7), (25, 30, 1, 1), (20, 12, 6, 20)])
+def test_soft_row_dp(n, K, delta, alpha):
+    for seed in range(2):
+        row = synth.random_cost(n, 1, K, 0, 60, seed=3000 + 11 * n + K + seed)[:, 0, :]
+        r = oracle.solve(np.ascontiguousarray(row[:, None, :]), delta, alpha)
+        E, hmin, hmax = pins.row_dp(row, delta, alpha)
+        assert r.energy == E
+        np.testing.assert_array_equal(r.hmin.reshape(-1), hmin)
+        np.testing.assert_array_equal(r.hmax.reshape(-1), hmax)
+
+
+def test_soft_row_dp_agrees_with_brute_force():
+    for seed in range(15):
+        row = synth.random_cost(5, 1, 5, -6, 6, seed=4000 + seed)[:, 0, :]
+        for delta in (0, 1, 3):
+            for alpha in (1, 4):
+                a = pins.row_dp(row, delta, alpha)
+                b = pins.brute_force(row[:, None, :], delta, alpha)
+                assert a[0] == b[0]
+                np.testing.assert_array_equal(a[1], b[1].reshape(-1))
+                np.testing.assert_array_equal(a[2], b[2].reshape(-1))
+
+
+def test_soft_alpha_zero_is_hard():
+    c = synth.layered_cost(12, 10, 30, 2, 0.4, 255, 0.05, 41)
+    a, b = oracle.solve(c, 2), oracle.solve(c, 2, 0)
+    assert (a.flow, a.energy) == (b.flow, b.energy)
+    np.testing.assert_array_equal(a.hmin, b.hmin)
+
+
+def test_soft_large_alpha_is_flat():
+    # alpha above columns * cost range: any step costs more than the feature
+    # term can gain, so the surface is flat at the lowest argmin of the summed
+    # column costs
+    c = synth.random_cost(5, 4, 9, 0, 30, seed=42)
+    alpha = 5 * 4 * 31
+    r = oracle.solve(c, 3, alpha)
+    tot = c.astype(np.int64).sum(axis=(0, 1))
+    assert (r.hmin == np.argmin(tot)).all()
+    assert r.energy == tot.min()
+
+
+@pytest.mark.parametrize("shape,delta,alpha", [((3, 4, 6), 1, 2), ((4, 3, 5), 0, 5), ((2, 5, 7), 2, 1), ((3, 3, 8), 3, 9)])
+def test_soft_library_maxflow(shape, delta, alpha):
+    for seed in range(2):
+        c = synth.random_cost(*shape, -30, 60, seed=5077 + seed)
+        r = oracle.solve(c, delta, alpha)
+        assert r.flow == pins.scipy_flow(c, delta, alpha)
+        assert r.flow == pins.networkx_flow(c, delta, alpha)
+        _check_soft_invariants(c, delta, alpha, r)
+
+
+def test_soft_planted_surface():
+    # a planted surface with steps of at most 1 whose columns have a deep
+    # minimum on it survives a small alpha exactly
+    rng = np.random.default_rng(43)
+    nx, ny, K = 8, 6, 16
+    h = np.clip(7 + np.cumsum(rng.integers(-1, 2, size=nx))[:, None] + np.zeros((1, ny), np.int64), 0, K - 1)
+    c = rng.integers(200, 300, size=(nx, ny, K)).astype(np.int32)
+    np.put_along_axis(c, h[:, :, None], 0, axis=2)
+    r = oracle.solve(c, 1, 2)
+    np.testing.assert_array_equal(r.hmin, h)
+    _check_soft_invariants(c, 1, 2, r)
