@@ -97,7 +97,9 @@ int smf_batch_solve(smf_handle *h, const int32_t *packed_cost_dev, const int64_t
  * SMF_ERR_ARG for a batch of more than one volume. */
 int smf_flow_value(const smf_handle *h, int64_t *out);
 
-/* Optimal energy E* = sum_p c(p, h(p)) of the last successful solve.
+/* Optimal energy E* = sum_p c(p, h(p)) of the last successful solve, plus
+ * alpha * sum |h(p) - h(q)| over 4-neighbour column pairs when the soft
+ * smoothness weight alpha ("smooth_weight") is positive.
  * SMF_ERR_ARG for a batch of more than one volume. */
 int smf_energy(const smf_handle *h, int64_t *out);
 
@@ -132,7 +134,8 @@ int smf_batch_surfaces(const smf_handle *h, int32_t *packed_out_dev, void *strea
  *                   are implied by (p,z) -> (p,0) -> (q,0) and change no cut.
  * Source arcs are saturated and never carry flow back.  For a batch, each
  * buffer holds the volumes' nodes packed in order (total T nodes; flow_lat
- * [4][T]).  For certificates and debugging; enqueued on `stream`. */
+ * [4][T]).  The flows on the soft smoothness arcs (smooth_weight > 0) are
+ * not exported.  For certificates and debugging; enqueued on `stream`. */
 int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res_dev,
                      int32_t *flow_down_dev, int32_t *flow_lat_dev, void *stream);
 
@@ -161,6 +164,18 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  *                        2 bfs, 3 push, 4 relabel, 5 mincut, 6 finish): every
  *                        launch of a selected class is bracketed by HIP events
  *                        on the solve stream (for benchmarks); 0: off
+ *   "smooth_weight"   -- soft smoothness weight alpha in [0, 2^29] (default 0;
+ *                        for a batch: of every volume).  The energy becomes
+ *                        sum_p c(p, h(p)) + alpha * sum |h(p) - h(q)| over
+ *                        4-neighbour column pairs, still with |h(p) - h(q)|
+ *                        <= delta (the edge costs of the VCE-weight net
+ *                        surface, Section 1.2, with the convex cost alpha|d|):
+ *                        arcs (p,z) -> (q,z) of capacity alpha for z >= 1.
+ *                        The first positive weight allocates 16 bytes and 4
+ *                        bits (rounded up to 64 heights) more per node, kept
+ *                        until smf_destroy; SMF_ERR_NOMEM if that fails.
+ *                        With every weight 0 the solver runs its kernels
+ *                        without soft arcs.
  * Returns SMF_ERR_ARG for an unknown key or an out-of-range value. */
 int smf_set_param(smf_handle *h, const char *key, int64_t value);
 
@@ -169,7 +184,9 @@ int smf_set_param(smf_handle *h, const char *key, int64_t value);
  * (0: the handle's relabel_period).  A search starts once some volume's
  * period has come round, and every volume at least halfway through its own
  * period joins it, so volumes of different periods share searches.
- * SMF_ERR_ARG for other keys or negative values. */
+ * Key "smooth_weight": the soft smoothness weight of each volume (as for
+ * smf_set_param; volumes may differ, 0 for none).
+ * SMF_ERR_ARG for other keys or out-of-range values. */
 int smf_batch_set_param(smf_handle *h, const char *key, const int64_t *values);
 
 /* Counters of the last solve.  Keys: "sweeps", "global_relabels",
@@ -187,8 +204,8 @@ int smf_get_stat(const smf_handle *h, const char *key, int64_t *out);
 /* Per-volume values into a host array of n int64.  Counters of the last
  * batch solve: "sweeps" (sweeps while the volume still had active nodes),
  * "global_relabels" (searches the volume took part in), "gap_relabels";
- * settings: "relabel_period" (the period in use) and the shape keys "nx",
- * "ny", "K", "delta". */
+ * settings: "relabel_period" (the period in use), "smooth_weight" and the
+ * shape keys "nx", "ny", "K", "delta". */
 int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
 
 /* Autotuner of the relabel period (the paper tunes its relabel factor

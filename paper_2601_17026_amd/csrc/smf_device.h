@@ -33,7 +33,7 @@ struct Inst {
     int cpb;        // chunks per work-mask bit (nch <= 64 * cpb)
     int lab_cap;    // labels >= lab_cap are unreachable (N + 1, at most kInf)
     int col_base;   // first global column
-    int pad0;
+    int alpha;      // soft smoothness weight: arcs (p,z) -> (q,z), z >= 1, capacity alpha
     long long node_base;   // first global node
     long long cost_base;   // first cost word in the caller's packed cost array
     long long N;           // nodes
@@ -77,6 +77,12 @@ struct Geom {
     // flow), kMaskFd (down arc carries flow).
     unsigned long long *bits;
     int max_nch;
+    // With soft smoothness (some volume has alpha > 0): four more masks,
+    // bit set where the soft arc (p,z) -> (q_k,z) is residual, stored like
+    // `bits` (sbits[(k * max_nch + w) * Ptot + p]); soft is 0 otherwise and
+    // the kernels without soft arcs run.
+    unsigned long long *sbits;
+    int soft;
     // Per column, the lowest height of a node with excess and a finite label
     // when the running global relabel started (K if none), and the list of
     // the columns whose lowest such node lies below the level-1 suffix.
@@ -98,6 +104,7 @@ struct State {
     int *ts;   // residual capacity of v -> t
     int *fd;   // flow on (p,z) -> (p,z-1)
     int *fl;   // 4 x Ntot: flow on (p,z) -> (q, zt(z)), q = p + (+x, -x, +y, -y)
+    int *sf;   // 4 x Ntot with soft smoothness: flow on (p,z) -> (q,z) (else NULL)
 };
 
 // Work tracking of the push/relabel sweeps: per global column a 64-bit mask

@@ -151,6 +151,7 @@ struct TimedScope {
 constexpr int kHistLen = 4096;            // labels tracked by the gap heuristic (LDS bins)
 constexpr int kSlotSweep = 0, kSlotBfs = 2, kSlotSync = 4, kSnapSlots = 5;
 constexpr long long kMaxInstNodes = (1LL << 30) - 2;   // finite labels stay below kUnl
+constexpr int64_t kMaxAlpha = 1LL << 29;   // soft residuals alpha - f + f' stay below 2^31
 
 struct smf_handle {
     Geom g{};
@@ -170,6 +171,8 @@ struct smf_handle {
     int *bfs = nullptr;           // 12 * Ptot int32: two per-column BFS records (threshold word,
                                   // LF[4]), the lowest active heights and the short-column list
     unsigned long long *bits = nullptr;   // kMasks * max_nch * Ptot BFS bit-mask words
+    int *soft_flow = nullptr;             // 4 * Ntot soft-arc flows, once some alpha > 0
+    unsigned long long *sbits = nullptr;  // 4 * max_nch * Ptot soft-arc masks, likewise
     unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
     int *hist = nullptr;                  // n x kHistLen label histograms (Geom::hist)
     unsigned long long *wmask = nullptr;  // 2 * Ptot work masks
@@ -216,7 +219,7 @@ static void release(smf_handle *h)
 {
     if (!h) return;
     void *dev[] = {h->inst_dev, h->col_inst, h->cnt_dev, h->part_dev, h->fill_dev, h->state, h->H,
-                   h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist};
+                   h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist, h->soft_flow, h->sbits};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     for (int i = 0; i < kSnapSlots; ++i)
@@ -292,7 +295,7 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
         I.cpb = (I.nch + 63) / 64;
         I.lab_cap = (int)(N + 1);
         I.col_base = (int)Ptot;
-        I.pad0 = 0;
+        I.alpha = 0;
         I.node_base = Ntot;
         I.cost_base = Ntot;
         I.N = N;
@@ -359,6 +362,9 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     g.max_nch = max_nch;
     g.level_block = 256;
     g.sweep_waves = 8192;
+    g.soft = 0;
+    g.sbits = nullptr;
+    h->st.sf = nullptr;
     g.low_act = h->bfs + 10 * P;
     g.short_list = h->bfs + 11 * P;
     g.short_count = &h->scr->short_count;
@@ -621,6 +627,7 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     if (h->g.count_work)
         launch_fill((int *)h->wcount, 2LL * 3 * kWorkSlots * kWorkStride, 0, s);
     launch_init_scratch(h->g, h->scr, s);
+    if (h->g.soft) launch_fill(h->soft_flow, 4LL * h->g.Ntot, 0, s);   // no soft-arc flow yet
     {
         TimedScope ts(h->timer, KC_BUILD, s);
         launch_build(cost_dev, h->g, h->st, h->scr, s);
@@ -840,10 +847,41 @@ extern "C" int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_
     return SMF_OK;
 }
 
+// Soft smoothness weights of the volumes (Inst::alpha): the soft-arc flows
+// and masks are allocated the first time some weight is positive, and kept.
+static int set_alpha(smf_handle *h, const int64_t *alpha, const char *who)
+{
+    for (int i = 0; i < h->n; ++i)
+        if (alpha[i] < 0 || alpha[i] > kMaxAlpha)
+            return fail(SMF_ERR_ARG, std::string(who) + ": smooth_weight must lie in [0, 2^29]");
+    bool any = false;
+    for (int i = 0; i < h->n; ++i) any = any || alpha[i] > 0;
+    if (any && !h->soft_flow) {
+        int *sf = nullptr;
+        unsigned long long *sb = nullptr;
+        if (!dev_alloc(sf, 4 * (size_t)h->g.Ntot) ||
+            !dev_alloc(sb, (size_t)4 * h->g.max_nch * (size_t)h->g.Ptot)) {
+            if (sf) (void)hipFree(sf);
+            return fail(SMF_ERR_NOMEM, std::string(who) + ": allocation of the soft-arc state failed");
+        }
+        h->soft_flow = sf;
+        h->sbits = sb;
+    }
+    for (int i = 0; i < h->n; ++i) h->inst[i].alpha = (int)alpha[i];
+    h->g.soft = any ? 1 : 0;
+    h->g.sbits = h->sbits;
+    h->st.sf = h->soft_flow;
+    return SMF_OK;
+}
+
 extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
 {
     if (!h || !key) return fail(SMF_ERR_ARG, "smf_set_param: NULL argument");
     int64_t *slot = nullptr;
+    if (!strcmp(key, "smooth_weight")) {
+        std::vector<int64_t> all((size_t)h->n, value);
+        return set_alpha(h, all.data(), "smf_set_param");
+    }
     if (!strcmp(key, "relabel_period")) {
         if (value < 1) return fail(SMF_ERR_ARG, "smf_set_param: relabel_period must be >= 1");
         h->relabel_period = value;
@@ -905,6 +943,7 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
 extern "C" int smf_batch_set_param(smf_handle *h, const char *key, const int64_t *values)
 {
     if (!h || !key || !values) return fail(SMF_ERR_ARG, "smf_batch_set_param: NULL argument");
+    if (!strcmp(key, "smooth_weight")) return set_alpha(h, values, "smf_batch_set_param");
     if (strcmp(key, "relabel_period"))
         return fail(SMF_ERR_ARG, std::string("smf_batch_set_param: unknown key ") + key);
     for (int i = 0; i < h->n; ++i)
@@ -959,6 +998,10 @@ extern "C" int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t 
     const std::vector<int64_t> *src = nullptr;
     if (!strcmp(key, "relabel_period")) {
         for (int i = 0; i < h->n; ++i) out[i] = h->inst_period[i] > 0 ? h->inst_period[i] : h->relabel_period;
+        return SMF_OK;
+    }
+    if (!strcmp(key, "smooth_weight")) {
+        for (int i = 0; i < h->n; ++i) out[i] = h->inst[i].alpha;
         return SMF_OK;
     }
     if (!strcmp(key, "nx") || !strcmp(key, "ny") || !strcmp(key, "K") || !strcmp(key, "delta")) {

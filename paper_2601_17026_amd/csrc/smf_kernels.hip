@@ -616,6 +616,32 @@ __device__ __forceinline__ void load_lateral(Lateral &l, const State &st, size_t
     }
 }
 
+// Soft smoothness arcs (p,z) -> (q,z), z >= 1, of capacity alpha in every
+// direction k: residual capacity alpha - sf[k](p,z) + sf[k^1](q,z) (flow on
+// the arc, and flow on its reverse that can be cancelled), and the label of
+// the head.  Loaded only for lanes that need them.
+struct SoftLat {
+    int d[4];      // label of (q, z) (kInf: no arc)
+    int own[4];    // flow on (p,z) -> (q,z)
+    int back[4];   // flow on (q,z) -> (p,z)
+    int r[4];      // residual capacity of (p,z) -> (q,z)
+};
+
+__device__ __forceinline__ void load_soft(SoftLat &l, const State &st, size_t base, const int dq[4],
+                                          const bool has[4], int z, size_t Ntot, int alpha, bool need)
+{
+    const size_t v = base + z;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool on = need && alpha > 0 && has[k] && z >= 1;
+        const size_t w = base + (ptrdiff_t)(on ? dq[k] + z : 0);
+        l.d[k] = on ? st.d[w] : kInf;
+        l.own[k] = on ? st.sf[(size_t)k * Ntot + v] : 0;
+        l.back[k] = on ? st.sf[(size_t)(k ^ 1) * Ntot + w] : 0;
+        l.r[k] = on ? alpha - l.own[k] + l.back[k] : 0;
+    }
+}
+
 // Global neighbour columns of a column, and the word offsets of their
 // nodes (q, 0) from the column's node (p, 0).
 __device__ __forceinline__ void neighbours(const Col &c, int p, int q[4], int dq[4], bool has[4])
@@ -640,7 +666,7 @@ __device__ __forceinline__ void neighbours(const Col &c, int p, int q[4], int dq
 // the mask while a carry is alive.  A node's excess word is read once and
 // corrected by one atomic add of the net change; other columns only add to
 // it, so the value read is a valid lower bound of what the node holds.
-template <bool kDown>
+template <bool kDown, bool kSoft>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_push(Geom g, State st, Work win, Work wout, Scratch *s)
 {
     const int lane = lane_id();
@@ -760,6 +786,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 Lateral lt;
                 load_lateral(lt, st, base, dq, has, z, K, Ntot, dl, need);
                 bytes += need ? 64 : 0;
+                SoftLat sl;
+                if constexpr (kSoft) {
+                    load_soft(sl, st, base, dq, has, z, Ntot, col.I.alpha, need);
+                    bytes += need && col.I.alpha > 0 ? 48 : 0;
+                }
                 int fown[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -778,6 +809,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         bytes += 8;
                     }
                     if (go) mark_mask(wout, q[k], 1ULL << (zt / kWave / cpb));
+                }
+                if constexpr (kSoft) {
+                    // soft arcs: cancel flow on the reverse arc first
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const bool go = rem > 0 && sl.r[k] > 0 && sl.d[k] + 1 == dv;
+                        if (go) {
+                            const long long a = min(rem, (long long)sl.r[k]);
+                            const int back = (int)min(a, (long long)sl.back[k]);
+                            const size_t w = base + (ptrdiff_t)(dq[k] + z);
+                            if (back > 0) st.sf[(size_t)(k ^ 1) * Ntot + w] = sl.back[k] - back;
+                            if (a > back) st.sf[(size_t)k * Ntot + v] = sl.own[k] + (int)(a - back);
+                            const int o = atomicAdd(st.e + w, (int)a);
+                            worst = max(worst, (long long)o + a);
+                            rem -= a;
+                            bytes += 12;
+                        }
+                        if (go) mark_mask(wout, q[k], 1ULL << (z / kWave / cpb));
+                    }
                 }
                 int fwd_k = -1;
 #pragma unroll
@@ -832,6 +882,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // Eight waves per SIMD (64 VGPRs, a few spilled): with the sweep grid of
 // 8192 waves every wave is resident at once, and the phase is bound by
 // memory latency, which more waves in flight hide.
+template <bool kSoft>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_relabel(Geom g, State st, Work win, Work wout)
 {
     const int lane = lane_id();
@@ -892,6 +943,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             Lateral lt;
             load_lateral(lt, st, base, dq, has, z, K, Ntot, dl, act);
             bytes += act ? 48 : 0;
+            SoftLat sl;
+            if constexpr (kSoft) {
+                load_soft(sl, st, base, dq, has, z, Ntot, col.I.alpha, act);
+                bytes += act && col.I.alpha > 0 ? 48 : 0;
+            }
             if (act) {
                 int b = ci.d_below;   // length-0 down arc
                 if (ci.ts > 0) b = min(b, 1);
@@ -900,6 +956,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 for (int k = 0; k < 4; ++k) {
                     b = min(b, lt.d_fwd[k] + 1);
                     if (lt.f_rev[k] > 0) b = min(b, lt.d_rev[k] + 1);
+                    if constexpr (kSoft) {
+                        if (sl.r[k] > 0) b = min(b, sl.d[k] + 1);
+                    }
                 }
                 if (b > dv) {
                     dv = b >= col.I.lab_cap ? kInf : b;
@@ -1015,6 +1074,7 @@ constexpr int kInitGroup = 2;
 // search).  The words of kInitGroup chunks are loaded before any of them
 // is used, so that a wave keeps that many chunks' loads in flight; at eight
 // waves per SIMD.
+template <bool kSoft>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_bfs_init(Geom g, State st, int *T, int *LF, int c0, int c1)
 {
     const int lane = lane_id();
@@ -1099,6 +1159,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 }
             }
         }
+        if constexpr (kSoft) {
+            // residual soft arcs (p,z) -> (q_k,z), one mask per direction
+            const int alpha = vc.I.alpha;
+            if (alpha > 0) {
+                const int pl = p - vc.I.col_base, x = pl / vc.I.ny, y = pl - x * vc.I.ny;
+                for (int c = 0; c < nch; ++c) {
+                    const int z = c * kWave + lane;
+                    unsigned long long mine = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int q = nbr(vc.I.nx, vc.I.ny, x, y, p, k);
+                        const bool on = q >= 0 && z >= 1 && z < K;
+                        const size_t v = base + z;
+                        const size_t w = base + (ptrdiff_t)(on ? (q - p) * K + z : 0);
+                        const int r = on ? alpha - st.sf[(size_t)k * Ntot + v] + st.sf[(size_t)(k ^ 1) * Ntot + w] : 0;
+                        const unsigned long long b = __ballot(r > 0);
+                        if (lane == k) mine = b;
+                    }
+                    if (lane < 4) g.sbits[((size_t)lane * g.max_nch + c) * Ptot + p] = mine;
+                }
+            }
+        }
         // a column whose lowest active node lies below the level-1 suffix
         // keeps the search from stopping early until a level reaches it
         if (la < t1) shortm |= 1ULL << (p - sbase);
@@ -1153,8 +1235,9 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
 // (the column's lowest flow-carrying lateral arc per direction at or above
 // its threshold) is lowered over the newly reached heights [cand, T) from
 // the bit masks.  Returns the mask words read.
-__device__ __forceinline__ int level_update(const Geom &g, int p, int K, int dl, int T, const int tq[4],
-                                           const int lq[4], int lf[4], int &cand)
+template <bool kSoft>
+__device__ __forceinline__ int level_update(const Geom &g, int p, int K, int dl, int alpha, int T,
+                                           const int tq[4], const int lq[4], int lf[4], int &cand)
 {
     cand = T;
     int words = 0;
@@ -1164,6 +1247,26 @@ __device__ __forceinline__ int level_update(const Geom &g, int p, int K, int dl,
         if (tq[k] == 0) cand = 0;
         else if (tq[k] + dl < K) cand = min(cand, tq[k] + dl);
         if (lq[k] < K) cand = min(cand, lat_head_of(lq[k], dl));
+    }
+    if constexpr (kSoft) {
+        // soft arcs (p,z) -> (q,z): the lowest z >= T(q) (z >= 1) whose arc
+        // is residual, when below the candidate so far
+        if (alpha > 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int lo = max(tq[k], 1);
+                if (tq[k] < 0 || lo >= cand) continue;
+                for (int w = lo >> 6; w <= (cand - 1) >> 6; ++w) {
+                    const unsigned long long b =
+                        g.sbits[((size_t)k * g.max_nch + w) * g.Ptot + p] & range_bits(w, lo, cand);
+                    ++words;
+                    if (b) {
+                        cand = w * kWave + __ffsll((long long)b) - 1;
+                        break;
+                    }
+                }
+            }
+        }
     }
     if (T >= 1 && T < K) {
         ++words;
@@ -1249,6 +1352,7 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
 // arithmetic reads the records of the column and its neighbours; the lowest
 // flow-carrying lateral arcs among the newly reached heights [cand, T) come
 // from the column's bit masks, so no per-node word is read.
+template <bool kSoft>
 __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d, int L,
                                                    const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin, int *__restrict__ Tout,
@@ -1294,7 +1398,7 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
             nq += q[k] >= 0;
         }
         bytes = 4 * (1 + nq) + 4 * (4 + nq) + 4;
-        if (near) bytes += 8 * level_update(g, p, K, dl, T, tq, lq, lf, cand);
+        if (near) bytes += 8 * level_update<kSoft>(g, p, K, dl, col.I.alpha, T, tq, lq, lf, cand);
     }
     const bool need = valid && near && cand < T;
     if (valid) {
@@ -1369,6 +1473,7 @@ __global__ __launch_bounds__(256) void k_mincut_init(Geom g, State st, int *H)
     }
 }
 
+template <bool kSoft>
 __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, Scratch *s)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1394,6 +1499,20 @@ __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, S
                 break;
             }
         }
+        if constexpr (kSoft) {
+            // residual soft arcs (q,z) -> (p,z) out of q's reached prefix:
+            // alpha - flow(q -> p) + flow(p -> q) > 0
+            const int alpha = col.I.alpha;
+            if (alpha > 0) {
+                const size_t qbase = base + (ptrdiff_t)(qq - p) * K;
+                for (int z = min(hq, K - 1); z > h && z >= 1; --z) {
+                    if (alpha - st.sf[(size_t)(k ^ 1) * Ntot + qbase + z] + st.sf[(size_t)k * Ntot + base + z] > 0) {
+                        h = z;
+                        break;
+                    }
+                }
+            }
+        }
     }
     // reverse residual of down arcs with flow: (p,h) -> (p,h+1)
     while (h >= 0 && h + 1 < K && st.fd[base + h + 1] > 0) ++h;
@@ -1405,7 +1524,10 @@ __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, S
 
 // Flow value F = sum_v (w+(v) - ts(v)) per volume: the build accumulated
 // sum w+; here the residual sink capacities are subtracted and
-// E = sum_p c(p, h(p)) is added, one wave per column.
+// E = sum_p c(p, h(p)) is added (with soft smoothness also alpha times
+// |h(p) - h(q)| for the +x and +y neighbour of every column), one wave per
+// column.
+template <bool kSoft>
 __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Geom g, State st,
                                                 const int *H)
 {
@@ -1424,6 +1546,13 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Ge
         if (lane == 0) {
             const int h = H[p];
             if (h >= 0) energy.acc += cost[(size_t)col.I.cost_base + (size_t)col.pl * col.I.K + h];
+            if constexpr (kSoft) {
+                if (col.I.alpha > 0)
+                    for (int k = 0; k < 4; k += 2) {   // +x, +y
+                        const int q = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
+                        if (q >= 0) energy.acc += (long long)col.I.alpha * abs(h - H[q]);
+                    }
+            }
         }
     }
     block_flush(flow);
@@ -1510,9 +1639,15 @@ static unsigned resident_blocks(const void *f, int block)
 
 void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, int c1, hipStream_t st)
 {
-    static const unsigned cap = resident_blocks(reinterpret_cast<const void *>(k_bfs_init), 256);
-    hipLaunchKernelGGL(k_bfs_init, dim3(range_wave_blocks(c0, c1, cap)), dim3(256), 0, st, g, sv, T,
-                       LF, c0, c1);
+    if (g.soft) {
+        static const unsigned cap = resident_blocks(reinterpret_cast<const void *>(k_bfs_init<true>), 256);
+        hipLaunchKernelGGL(k_bfs_init<true>, dim3(range_wave_blocks(c0, c1, cap)), dim3(256), 0, st, g,
+                           sv, T, LF, c0, c1);
+    } else {
+        static const unsigned cap = resident_blocks(reinterpret_cast<const void *>(k_bfs_init<false>), 256);
+        hipLaunchKernelGGL(k_bfs_init<false>, dim3(range_wave_blocks(c0, c1, cap)), dim3(256), 0, st, g,
+                           sv, T, LF, c0, c1);
+    }
 }
 
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
@@ -1526,8 +1661,12 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
     const long long cols = R.pre[R.n];
     const long long n = cols > g.n ? cols : g.n;
     const int b = g.level_block;
-    hipLaunchKernelGGL(k_bfs_level, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d, L, Tin,
-                       LFin, Tout, LFout, R);
+    if (g.soft)
+        hipLaunchKernelGGL(k_bfs_level<true>, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d,
+                           L, Tin, LFin, Tout, LFout, R);
+    else
+        hipLaunchKernelGGL(k_bfs_level<false>, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d,
+                           L, Tin, LFin, Tout, LFout, R);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)
@@ -1549,10 +1688,14 @@ void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, h
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st)
 {
-    if (down)
-        hipLaunchKernelGGL(k_push<true>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
-    else
-        hipLaunchKernelGGL(k_push<false>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout, s);
+    const dim3 grid(sweep_blocks(g)), block(256);
+    if (g.soft) {
+        if (down) hipLaunchKernelGGL((k_push<true, true>), grid, block, 0, st, g, sv, win, wout, s);
+        else hipLaunchKernelGGL((k_push<false, true>), grid, block, 0, st, g, sv, win, wout, s);
+    } else {
+        if (down) hipLaunchKernelGGL((k_push<true, false>), grid, block, 0, st, g, sv, win, wout, s);
+        else hipLaunchKernelGGL((k_push<false, false>), grid, block, 0, st, g, sv, win, wout, s);
+    }
 }
 
 void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st)
@@ -1563,7 +1706,8 @@ void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t s
 
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_relabel, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
+    if (g.soft) hipLaunchKernelGGL(k_relabel<true>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
+    else hipLaunchKernelGGL(k_relabel<false>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
 }
 
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
@@ -1573,12 +1717,14 @@ void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
 
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mincut_pass, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv, H, s);
+    if (g.soft) hipLaunchKernelGGL(k_mincut_pass<true>, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv, H, s);
+    else hipLaunchKernelGGL(k_mincut_pass<false>, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv, H, s);
 }
 
 void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finish, dim3(wave_blocks(g)), dim3(256), 0, st, cost, g, sv, H);
+    if (g.soft) hipLaunchKernelGGL(k_finish<true>, dim3(wave_blocks(g)), dim3(256), 0, st, cost, g, sv, H);
+    else hipLaunchKernelGGL(k_finish<false>, dim3(wave_blocks(g)), dim3(256), 0, st, cost, g, sv, H);
 }
 
 }  // namespace smf
