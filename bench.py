@@ -11,8 +11,10 @@ The cost volume is resident in HBM before the timed region starts.
 The batched leg then solves the 64-volume batch workload (nx, ny, K uniform
 in [64, 256], delta in {1, 2, 3}, layered costs with per-volume seeds) once
 as one batch and once as 64 plain solves one after another on the same
-stream, and reports both rates under "batched".  Prints one JSON line.
-Only one GPU is supported.
+stream, and reports both rates under "batched".  The soft leg solves the
+seismic volume with the soft smoothness term (smooth_weight, default 16)
+and reports under "soft".  Prints one JSON line.  Only one GPU is
+supported.
 """
 from __future__ import annotations
 
@@ -62,6 +64,12 @@ def parse():
                     help="only run the batched leg (prints its JSON object)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the 64 plain solves that the batched leg compares against")
+    ap.add_argument("--smooth-weight", type=int, default=16, metavar="A",
+                    help="soft smoothness weight of the soft leg (0 skips the leg)")
+    ap.add_argument("--soft-cpu-crop", type=int, default=40,
+                    help="columns per side of the oracle's CPU sample for the soft leg")
+    ap.add_argument("--soft-only", action="store_true",
+                    help="only run the soft leg (prints its JSON object)")
     ap.add_argument("--counters-summary", metavar="DIR",
                     help="only summarise a rocprofv3 --pmc output directory: mean counter "
                          "values per dispatch of every kernel, one JSON line per kernel")
@@ -123,15 +131,16 @@ def stored_traffic(kernel: str):
 
 
 
-def cpu_baseline(cost, delta, crop):
+def cpu_baseline(cost, delta, crop, alpha=0):
     import numpy as np
 
     import oracle
 
     sub = np.ascontiguousarray(cost[:crop, :crop])
     t = time.perf_counter()
-    oracle.solve(sub, delta)
+    oracle.solve(sub, delta, alpha)
     dt = time.perf_counter() - t
+    soft = f", smooth weight {alpha}" if alpha else ""
     return {
         "value": round(sub.size / dt / 1e6, 4),
         "unit": "Mvoxels/s",
@@ -139,8 +148,59 @@ def cpu_baseline(cost, delta, crop):
         "kind": "oracle",
         "seconds": round(dt, 2),
         "sample": f"x<{crop}, y<{crop} crop ({crop}x{crop}x{cost.shape[2]}) of the same "
-                  f"volume, delta={delta}; single-threaded Dinic (oracle/oracle.c)",
+                  f"volume, delta={delta}{soft}; single-threaded Dinic (oracle/oracle.c)",
     }
+
+
+def soft_leg(args, torch, smf, cost, delta, stream):
+    """The seismic volume with the soft smoothness term alpha * |h(p) - h(q)|
+    (smooth_weight): the same volume and delta, one more arc per neighbour
+    and height."""
+    nx, ny, K = cost.shape
+    c = torch.from_numpy(cost).cuda()
+    solver = smf.Solver(nx, ny, K, delta)
+    solver.set_param("smooth_weight", args.smooth_weight)
+    per_class = {k: {"ns": 0, "n": 0, "bytes": 0} for k in CLASSES}
+    solver.set_param("kernel_timing", (1 << len(CLASSES)) - 1)
+    solver.set_param("count_work", 1)
+    solver.solve(c, stream)                       # warm-up: every class timed
+    for k in CLASSES:
+        per_class[k]["ns"] += solver.stat(f"time_ns.{k}")
+        per_class[k]["n"] += solver.stat(f"launches.{k}")
+        per_class[k]["bytes"] += solver.stat(f"bytes.{k}")
+    dom = max(CLASSES, key=lambda k: per_class[k]["ns"])
+    solver.set_param("kernel_timing", 1 << CLASSES.index(dom))
+    dom_ns = dom_n = dom_bytes = sweeps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(c, stream)
+        dom_ns += solver.stat(f"time_ns.{dom}")
+        dom_n += solver.stat(f"launches.{dom}")
+        dom_bytes += solver.stat(f"bytes.{dom}")
+        sweeps += solver.stat("sweeps")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    flow, energy = solver.flow_value(), solver.energy()
+    solver.close()
+    avg_ns = dom_ns / max(1, dom_n)
+    achieved = dom_bytes / max(1, dom_n) / avg_ns if avg_ns else 0.0
+    out = {
+        "value": round(cost.size * args.steps / elapsed / 1e6, 3),
+        "unit": "Mvoxels/s",
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "steps": args.steps,
+        "smooth_weight": args.smooth_weight,
+        "sweeps_per_step": sweeps / args.steps,
+        "result": {"flow": flow, "energy": energy},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CLASS[dom], "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_us": round(avg_ns / 1e3, 2)},
+        "workload": WORKLOAD + f", soft smoothness weight {args.smooth_weight}",
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cost, delta, args.soft_cpu_crop, args.smooth_weight)
+    return out
 
 
 def batched_leg(args, torch, smf, synth, stream):
@@ -234,6 +294,11 @@ def main():
               flush=True)
         return
     cost, delta = synth.config_seismic()
+    if args.soft_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"soft": soft_leg(args, torch, smf, cost, delta, torch.cuda.current_stream())}),
+              flush=True)
+        return
     nx, ny, K = cost.shape
     V = cost.size
     dev = torch.device("cuda", 0)
@@ -338,6 +403,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched_leg(args, torch, smf, synth, stream)
+    if args.smooth_weight > 0 and not args.no_batch:
+        out["soft"] = soft_leg(args, torch, smf, cost, delta, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cost, delta, args.cpu_crop)
     print(json.dumps(out), flush=True)
