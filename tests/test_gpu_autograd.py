@@ -74,6 +74,43 @@ def test_gradient_finite_differences_oracle(mods):
     assert checked >= 20
 
 
+def test_soft_forward_and_gradient(mods):
+    """With the soft smoothness term (alpha = 0.5 in cost units, weight 8
+    after the x16 quantisation): the forward against the oracle, and the
+    gradient, still the one-hot of the surface, against +-1 finite
+    differences of the exact soft energy on columns of unique height."""
+    _, ag = mods
+    cost, _, _ = synth.diff_costs(batch=2, n=12, K=24, seed0=5201, device="cuda")
+    cost = cost.clone().requires_grad_(True)
+    a = ag.soft_weight(0.5)
+    assert a == 8
+    E, h = ag.surface_energy(cost, 2, alpha=0.5)
+    E.sum().backward()
+    ci = ag.quantize(cost.detach()).cpu().numpy()
+    rng = np.random.default_rng(4)
+    checked = 0
+    for b in range(2):
+        ref = oracle.solve(ci[b], 2, a)
+        assert E[b].item() == pytest.approx(ref.energy / 16.0, abs=0)
+        np.testing.assert_array_equal(h[b].cpu().numpy(), ref.hmin)
+        grad = cost.grad[b].cpu().numpy()
+        uniq = np.argwhere(ref.hmin == ref.hmax)
+        for (x, y) in uniq[rng.permutation(len(uniq))[:8]]:
+            for z in {int(ref.hmin[x, y]), int(rng.integers(0, 24))}:
+                up = ci[b].copy(); up[x, y, z] += 1
+                dn = ci[b].copy(); dn[x, y, z] -= 1
+                d_up = oracle.solve(up, 2, a).energy - ref.energy
+                d_dn = ref.energy - oracle.solve(dn, 2, a).energy
+                assert d_up == d_dn == int(grad[x, y, z]), (b, x, y, z, d_up, d_dn)
+                checked += 1
+    assert checked >= 16
+    # the cached solver goes back to the hard bound with alpha = 0
+    E0, h0 = ag.surface_energy(cost.detach(), 2)
+    r0 = oracle.solve(ci[0], 2)
+    assert E0[0].item() == pytest.approx(r0.energy / 16.0, abs=0)
+    np.testing.assert_array_equal(h0[0].cpu().numpy(), r0.hmin)
+
+
 def test_gradient_reaches_the_network(mods):
     _, ag = mods
     _, net, x = synth.diff_costs(batch=2, n=16, K=32, device="cuda")
