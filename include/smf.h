@@ -210,9 +210,10 @@ int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
 
 /* Autotuner of the relabel period (the paper tunes its relabel factor
  * empirically, Section 3.4).  Volumes fall into classes keyed by
- * (ceil log2 K, min(delta, 4), floor log2 (nx*ny)).  For every class of the
- * handle's volumes that the process-wide tuning cache does not hold yet,
- * the largest volume of that class is solved on a temporary handle with
+ * (ceil log2 K, min(delta, 4), floor log2 (nx*ny), smooth_weight > 0).  For
+ * every class of the handle's volumes that the process-wide tuning cache
+ * does not hold yet, the largest volume of that class is solved (with its
+ * smooth_weight) on a temporary handle with
  * each candidate period (2, 3, 4, 6, 8, 12), timed on the host clock (the
  * fastest of three runs when a solve takes under 2 s), and the fastest
  * period is cached; then every volume of `h` gets
@@ -234,15 +235,17 @@ int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev, const int64_t *o
 int smf_tune_apply(smf_handle *h);
 
 /* Adds the entries of a tuning-cache text file (lines "kbits delta pbits
- * period best_ns") to the cache, or writes the cache to one.  SMF_ERR_ARG
- * if the file cannot be opened. */
+ * soft period best_ns"; lines "kbits delta pbits period best_ns" are
+ * classes with soft = 0) to the cache, or writes the cache to one.
+ * SMF_ERR_ARG if the file cannot be opened. */
 int smf_tune_cache_load(const char *path);
 int smf_tune_cache_save(const char *path);
 
 /* Empties the tuning cache (and stops it reading SMF_TUNE_CACHE). */
 int smf_tune_cache_clear(void);
 
-/* Cached period for a volume shape (0 if its class is not cached). */
+/* Cached period for a volume shape without the soft smoothness term (0 if
+ * its class is not cached). */
 int smf_tune_lookup(int32_t nx, int32_t ny, int32_t K, int32_t delta, int64_t *period);
 
 /* Backward of the optimal energy with respect to the costs (Section 1.1,

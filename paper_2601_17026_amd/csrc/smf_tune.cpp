@@ -4,11 +4,13 @@
 // the sweeps it saves; the paper settles it empirically (Section 3.4, the
 // relabel factor of the global-relabel sweep).  Here the period is chosen
 // per class of volume -- key (ceil log2 K, min(delta, 4), floor log2 of the
-// column count) -- by timing complete solves of the largest volume of each
-// class with every candidate period (the fastest of three runs for short
-// solves), and remembered in a process-wide cache
-// that can be saved to and loaded from a text file (one line per class:
-// "kbits delta pbits period best_ns").
+// column count, whether the soft smoothness weight is positive) -- by
+// timing complete solves of the largest volume of each class with every
+// candidate period (the fastest of three runs for short solves), and
+// remembered in a process-wide cache that can be saved to and loaded from a
+// text file (one line per class: "kbits delta pbits soft period best_ns";
+// lines of five fields, written before the soft flag existed, are classes
+// without the soft term).
 //
 // The tuner is a client of the C-ABI: it solves the representative volume
 // on a temporary handle of its own and writes the chosen periods into the
@@ -33,7 +35,7 @@ void clear_error();
 
 namespace {
 
-using Key = std::tuple<int, int, int>;
+using Key = std::tuple<int, int, int, int>;
 
 struct Choice {
     int64_t period;
@@ -66,19 +68,23 @@ int floor_log2(int64_t v)
     return b;
 }
 
-Key key_of(int32_t nx, int32_t ny, int32_t K, int32_t delta)
+Key key_of(int32_t nx, int32_t ny, int32_t K, int32_t delta, int64_t alpha)
 {
-    return Key(ceil_log2(K), std::min<int32_t>(delta, 4), floor_log2((int64_t)nx * ny));
+    return Key(ceil_log2(K), std::min<int32_t>(delta, 4), floor_log2((int64_t)nx * ny), alpha > 0 ? 1 : 0);
 }
 
 int load_locked(const char *path)
 {
     FILE *f = fopen(path, "r");
     if (!f) return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_load: cannot open ") + path);
-    int a, b, c;
-    long long p, ns;
-    while (fscanf(f, "%d %d %d %lld %lld", &a, &b, &c, &p, &ns) == 5)
-        if (p >= 1) g_cache[Key(a, b, c)] = Choice{p, ns};
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        int a, b, c, d;
+        long long v[3];
+        const int got = sscanf(line, "%d %d %d %d %lld %lld %lld", &a, &b, &c, &d, &v[0], &v[1], &v[2]);
+        if (got == 6 && v[0] >= 1) g_cache[Key(a, b, c, d)] = Choice{v[0], v[1]};
+        else if (got == 5 && (long long)d >= 1) g_cache[Key(a, b, c, 0)] = Choice{d, v[0]};
+    }
     fclose(f);
     return SMF_OK;
 }
@@ -88,8 +94,9 @@ int save_locked(const char *path)
     FILE *f = fopen(path, "w");
     if (!f) return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_save: cannot open ") + path);
     for (const auto &kv : g_cache)
-        fprintf(f, "%d %d %d %lld %lld\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                std::get<2>(kv.first), (long long)kv.second.period, (long long)kv.second.best_ns);
+        fprintf(f, "%d %d %d %d %lld %lld\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                std::get<2>(kv.first), std::get<3>(kv.first), (long long)kv.second.period,
+                (long long)kv.second.best_ns);
     if (fclose(f) != 0)
         return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_save: cannot write ") + path);
     return SMF_OK;
@@ -103,14 +110,14 @@ void load_env_locked()
     if (path && *path) (void)load_locked(path);
 }
 
-// Shapes of the handle's volumes via the C-ABI.
-int shapes_of(smf_handle *h, std::vector<int64_t> s[4])
+// Shapes and soft smoothness weights of the handle's volumes via the C-ABI.
+int shapes_of(smf_handle *h, std::vector<int64_t> s[5])
 {
     int64_t n = 0;
     int rc = smf_get_stat(h, "volumes", &n);
     if (rc) return rc;
-    const char *keys[4] = {"nx", "ny", "K", "delta"};
-    for (int j = 0; j < 4; ++j) {
+    const char *keys[5] = {"nx", "ny", "K", "delta", "smooth_weight"};
+    for (int j = 0; j < 5; ++j) {
         s[j].assign((size_t)n, 0);
         rc = smf_batch_get_stat(h, keys[j], s[j].data());
         if (rc) return rc;
@@ -119,12 +126,12 @@ int shapes_of(smf_handle *h, std::vector<int64_t> s[4])
 }
 
 // Periods for the handle's volumes from the cache (0 where no entry).
-std::vector<int64_t> periods_locked(const std::vector<int64_t> s[4])
+std::vector<int64_t> periods_locked(const std::vector<int64_t> s[5])
 {
     std::vector<int64_t> out(s[0].size(), 0);
     for (size_t i = 0; i < out.size(); ++i) {
         auto it = g_cache.find(key_of((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i],
-                                      (int32_t)s[3][i]));
+                                      (int32_t)s[3][i], s[4][i]));
         if (it != g_cache.end()) out[i] = it->second.period;
     }
     return out;
@@ -137,7 +144,7 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
 {
     smf::clear_error();
     if (!h || !packed_cost_dev) return smf::set_error(SMF_ERR_ARG, "smf_autotune: NULL handle or cost");
-    std::vector<int64_t> s[4];
+    std::vector<int64_t> s[5];
     int rc = shapes_of(h, s);
     if (rc) return rc;
     const size_t n = s[0].size();
@@ -151,7 +158,7 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
     // the largest volume of every class that the cache does not know yet
     std::map<Key, size_t> todo;
     for (size_t i = 0; i < n; ++i) {
-        const Key k = key_of((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i], (int32_t)s[3][i]);
+        const Key k = key_of((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i], (int32_t)s[3][i], s[4][i]);
         if (g_cache.count(k)) continue;
         auto it = todo.find(k);
         const int64_t size = s[0][i] * s[1][i] * s[2][i];
@@ -163,7 +170,8 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
         smf_handle *t = smf_create((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i], (int32_t)s[3][i]);
         if (!t) return SMF_ERR_NOMEM;   // smf_create described the failure
         const int32_t *cost = packed_cost_dev + off[i];
-        rc = smf_solve(t, cost, stream);   // warm-up
+        rc = smf_set_param(t, "smooth_weight", s[4][i]);
+        if (!rc) rc = smf_solve(t, cost, stream);   // warm-up
         Choice best{0, 0};
         for (int64_t p : kCandidates) {
             if (rc) break;
@@ -223,7 +231,7 @@ extern "C" int smf_tune_apply(smf_handle *h)
 {
     smf::clear_error();
     if (!h) return smf::set_error(SMF_ERR_ARG, "smf_tune_apply: NULL handle");
-    std::vector<int64_t> s[4];
+    std::vector<int64_t> s[5];
     int rc = shapes_of(h, s);
     if (rc) return rc;
     std::lock_guard<std::mutex> lock(g_mu);
@@ -263,7 +271,7 @@ extern "C" int smf_tune_lookup(int32_t nx, int32_t ny, int32_t K, int32_t delta,
         return smf::set_error(SMF_ERR_ARG, "smf_tune_lookup: bad shape or NULL output");
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_locked();
-    auto it = g_cache.find(key_of(nx, ny, K, delta));
+    auto it = g_cache.find(key_of(nx, ny, K, delta, 0));
     *period = it == g_cache.end() ? 0 : it->second.period;
     return SMF_OK;
 }

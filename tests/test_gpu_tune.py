@@ -73,3 +73,30 @@ def test_autotune_plain_handle(smf):
         r = oracle.solve(cost, delta)
         assert s.flow_value() == r.flow and s.energy() == r.energy
         np.testing.assert_array_equal(s.surface().cpu().numpy(), r.hmin)
+
+
+def test_autotune_soft_class(smf, tmp_path):
+    # one shape with and without the soft smoothness term: two classes,
+    # each timed with its own weight; tuned solves stay exact
+    shapes = [(40, 40, 100, 2), (40, 40, 100, 2)]
+    alphas = [0, 6]
+    vols = [synth.layered_cost(40, 40, 100, 2, 0.4, 255, 0.05, 1600 + i) for i in range(2)]
+    smf.tune_cache_clear()
+    with smf.BatchSolver(shapes) as b:
+        b.set_param_per_volume("smooth_weight", alphas)
+        packed = b.pack([torch.from_numpy(v).cuda() for v in vols])
+        print("case: autotune with a soft class", flush=True)
+        smf.autotune(b, packed)
+        assert all(p >= 1 for p in b.stat_per_volume("relabel_period"))
+        b.solve(packed)
+        flows, energies = b.flow_values(), b.energies()
+        surfs = [s.cpu().numpy() for s in b.unpack_surfaces(b.surfaces())]
+    for v, a, f, e, s in zip(vols, alphas, flows, energies, surfs):
+        r = oracle.solve(v, 2, a)
+        assert (f, e) == (r.flow, r.energy)
+        np.testing.assert_array_equal(s, r.hmin)
+    path = tmp_path / "tune.txt"
+    smf.tune_cache_save(str(path))
+    keys = sorted(tuple(line.split()[:4]) for line in path.read_text().splitlines())
+    assert keys == [("7", "2", "10", "0"), ("7", "2", "10", "1")]
+    smf.tune_cache_clear()

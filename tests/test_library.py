@@ -77,7 +77,8 @@ def test_python_binding_lists_header_symbols():
 
 def test_tune_cache_roundtrip_without_gpu(tmp_path):
     # the autotuner's cache: classes keyed by (ceil log2 K, min(delta, 4),
-    # floor log2 columns); file load, lookup, save and clear need no device
+    # floor log2 columns, soft term); files of five fields per line (no soft
+    # flag) still load; load, lookup, save and clear need no device
     lib = ctypes.CDLL(LIB)
     lib.smf_tune_lookup.argtypes = [ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_int64)]
     lib.smf_tune_cache_load.argtypes = [ctypes.c_char_p]
@@ -100,9 +101,15 @@ def test_tune_cache_roundtrip_without_gpu(tmp_path):
     assert look(128, 255, 100, 2) == 8      # 32640 columns -> 14
     assert look(128, 256, 100, 2) == 0      # 32768 columns -> 15
     assert look(512, 512, 384, 7) == 3      # delta above 4 shares the class of 4
+    # a class with the soft smoothness term (sixth field layout) is separate
+    soft = tmp_path / "soft.txt"
+    soft.write_text("7 2 14 1 4 777\n")
+    assert lib.smf_tune_cache_load(str(soft).encode()) == 0
+    assert look(128, 128, 100, 2) == 8
     dst = tmp_path / "out.txt"
     assert lib.smf_tune_cache_save(str(dst).encode()) == 0
-    assert sorted(dst.read_text().split("\n")) == sorted(src.read_text().split("\n"))
+    assert sorted(dst.read_text().split("\n")) == sorted(
+        ["", "7 2 14 0 8 12345", "7 2 14 1 4 777", "9 4 18 0 3 999"])
     assert lib.smf_tune_cache_load(str(tmp_path / "missing.txt").encode()) == -1
     assert b"cannot open" in lib.smf_last_error()
     out = ctypes.c_int64()
