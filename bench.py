@@ -76,6 +76,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def counters_summary(path):
     """Mean per-dispatch values of every counter of a rocprofv3 --pmc run."""
     import collections
@@ -156,6 +161,7 @@ def soft_leg(args, torch, smf, cost, delta, stream):
     """The seismic volume with the soft smoothness term alpha * |h(p) - h(q)|
     (smooth_weight): the same volume and delta, one more arc per neighbour
     and height."""
+    progress(f"soft leg: smooth_weight {args.smooth_weight}")
     nx, ny, K = cost.shape
     c = torch.from_numpy(cost).cuda()
     solver = smf.Solver(nx, ny, K, delta)
@@ -199,6 +205,7 @@ def soft_leg(args, torch, smf, cost, delta, stream):
         "workload": WORKLOAD + f", soft smoothness weight {args.smooth_weight}",
     }
     if not args.no_cpu_baseline:
+        progress("soft leg: CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(cost, delta, args.soft_cpu_crop, args.smooth_weight)
     return out
 
@@ -216,6 +223,7 @@ def batched_leg(args, torch, smf, synth, stream):
 
     # the autotuner picks each volume class's relabel period (set-up, not
     # timed); the batch and the plain solves both use its choices
+    progress("batched leg: tuning the relabel periods")
     t0 = time.perf_counter()
     if args.relabel_period > 0:
         batch.set_param("relabel_period", args.relabel_period)
@@ -228,6 +236,7 @@ def batched_leg(args, torch, smf, synth, stream):
     t_tune = time.perf_counter() - t0
     periods = batch.stat_per_volume("relabel_period")
 
+    progress("batched leg: batch solves")
     batch.solve(packed, stream=stream)          # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -240,6 +249,7 @@ def batched_leg(args, torch, smf, synth, stream):
 
     seq = {}
     if not args.no_sequential:
+        progress("batched leg: 64 plain solves")
         for i in range(4):                           # warm-up
             plain[i].solve(views[i], stream)
         torch.cuda.synchronize()
@@ -307,6 +317,7 @@ def main():
     stream = torch.cuda.current_stream()
     solver = smf.Solver(nx, ny, K, delta)
     tune_s = 0.0
+    progress("plain leg: tuning the relabel period")
     if args.relabel_period > 0:
         solver.set_param("relabel_period", args.relabel_period)
     elif not args.no_tune:
@@ -318,6 +329,7 @@ def main():
 
     # warm-up solves time every kernel class; the class with the most time is
     # the dominant kernel of the roofline
+    progress("plain leg: warm-up and timed solves")
     per_class = {k: {"ns": 0, "n": 0, "bytes": 0} for k in CLASSES}
     solver.set_param("kernel_timing", (1 << len(CLASSES)) - 1)
     solver.set_param("count_work", 1)
@@ -406,6 +418,7 @@ def main():
     if args.smooth_weight > 0 and not args.no_batch:
         out["soft"] = soft_leg(args, torch, smf, cost, delta, stream)
     if not args.no_cpu_baseline:
+        progress("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(cost, delta, args.cpu_crop)
     print(json.dumps(out), flush=True)
 

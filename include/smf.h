@@ -215,7 +215,8 @@ int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
  * does not hold yet, the largest volume of that class is solved (with its
  * smooth_weight) on a temporary handle with
  * each candidate period (2, 3, 4, 6, 8, 12), timed on the host clock (the
- * fastest of three runs when a solve takes under 2 s), and the fastest
+ * fastest of three runs when a solve takes under 0.25 s, of two under 2 s),
+ * and the fastest
  * period is cached; then every volume of `h` gets
  * its class's period (smf_batch_set_param).  For a batch of more than one
  * volume the tuner then times whole solves of `h` with every volume's

@@ -49,10 +49,11 @@ bool g_env_loaded = false;
 const int64_t kCandidates[] = {2, 3, 4, 6, 8, 12};
 // scale factors 1, 1.5, 2 and 3 (doubled) of the whole-batch step
 const int kBatchScale2[] = {2, 3, 4, 6};
-// a solve shorter than this (2 s) is timed three times and the fastest
-// counts: run-to-run spread of a solve is a few percent, as large as the
-// differences between neighbouring periods
-constexpr int64_t kShortSolveNs = 2000000000;
+// Repeats per candidate: the run-to-run spread of a solve is a few
+// percent, as large as the differences between neighbouring periods, so
+// the fastest of three runs counts for solves under 0.25 s and the faster
+// of two under 2 s.
+constexpr int64_t kShortSolveNs = 250000000, kLongSolveNs = 2000000000;
 
 int ceil_log2(int64_t v)
 {
@@ -184,7 +185,7 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
                 const auto t1 = std::chrono::steady_clock::now();
                 const int64_t d = std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count();
                 ns = ns < 0 ? d : std::min(ns, d);
-                if (d >= kShortSolveNs) break;
+                if (d >= kLongSolveNs || (rep == 1 && d >= kShortSolveNs)) break;
             }
             if (!rc && (best.period == 0 || ns < best.best_ns)) best = Choice{p, ns};
         }
