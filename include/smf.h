@@ -134,10 +134,20 @@ int smf_batch_surfaces(const smf_handle *h, int32_t *packed_out_dev, void *strea
  *                   are implied by (p,z) -> (p,0) -> (q,0) and change no cut.
  * Source arcs are saturated and never carry flow back.  For a batch, each
  * buffer holds the volumes' nodes packed in order (total T nodes; flow_lat
- * [4][T]).  The flows on the soft smoothness arcs (smooth_weight > 0) are
- * not exported.  For certificates and debugging; enqueued on `stream`. */
+ * [4][T]).  The flows on the soft smoothness arcs (smooth_weight > 0) come
+ * from smf_export_soft_flows.  For certificates and debugging; enqueued on
+ * `stream`. */
 int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res_dev,
                      int32_t *flow_down_dev, int32_t *flow_lat_dev, void *stream);
+
+/* Copies the flows on the soft smoothness arcs (p,z) -> (q,z) of the last
+ * successful solve into `flow_soft_dev` (device pointer, [4][nx][ny][K]
+ * int32 in neighbour order +x, -x, +y, -y; for a batch [4][T] over the
+ * packed nodes): the arc's flow is stored at its tail, 0 at z = 0 and for
+ * absent neighbours (the soft arcs of Section 1.2's edge costs, see
+ * "smooth_weight").  SMF_ERR_ARG if no positive smooth_weight is set.
+ * Enqueued on `stream`. */
+int smf_export_soft_flows(const smf_handle *h, int32_t *flow_soft_dev, void *stream);
 
 /* Tuning and limits.  Keys:
  *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1,

@@ -83,6 +83,10 @@ def _load():
                                         ctypes.c_int32, P, P, P, P, P,
                                         ctypes.POINTER(_Cert)]
         lib.certify_preflow.restype = ctypes.c_int
+        lib.certify_preflow_soft.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P,
+                                             ctypes.POINTER(_Cert)]
+        lib.certify_preflow_soft.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -138,8 +142,12 @@ class Certificate:
                 and self.flow == self.cut)
 
 
-def certify(cost, delta, excess, sink_res, flow_down, flow_lat, surface) -> Certificate:
+def certify(cost, delta, excess, sink_res, flow_down, flow_lat, surface, alpha=0,
+            flow_soft=None) -> Certificate:
     """Check a final preflow of the implicit column graph and a surface.
+    With alpha > 0, flow_soft (4, nx, ny, K) holds the flows on the soft
+    arcs (p,z) -> (q,z) of capacity alpha, neighbour order +x, -x, +y, -y,
+    and the energy includes alpha * |h(p) - h(q)|.
 
     excess, sink_res, flow_down: (nx, ny, K) int32; flow_lat: (4, nx, ny, K)
     int32 in the neighbour order +x, -x, +y, -y; surface: (nx, ny) int32.
@@ -152,8 +160,16 @@ def certify(cost, delta, excess, sink_res, flow_down, flow_lat, surface) -> Cert
     arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in
             (excess, sink_res, flow_down, flow_lat, surface)]
     r = _Cert()
-    rc = _load().certify_preflow(c.ctypes.data, nx, ny, K, int(delta),
-                                 *[a.ctypes.data for a in arrs], ctypes.byref(r))
+    if alpha:
+        fs = np.ascontiguousarray(flow_soft, dtype=np.int32)
+        if fs.shape != (4, nx, ny, K):
+            raise ValueError("flow_soft must be (4, nx, ny, K)")
+        rc = _load().certify_preflow_soft(c.ctypes.data, nx, ny, K, int(delta), int(alpha),
+                                          *[a.ctypes.data for a in arrs[:4]], fs.ctypes.data,
+                                          arrs[4].ctypes.data, ctypes.byref(r))
+    else:
+        rc = _load().certify_preflow(c.ctypes.data, nx, ny, K, int(delta),
+                                     *[a.ctypes.data for a in arrs], ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"certify_preflow failed with status {rc}")
     return Certificate(r.flow, r.cut, r.energy, r.bad_capacity, r.bad_conservation,

@@ -14,6 +14,13 @@
  *     capacity of the cut (R, complement) (Theorem 1.1), and R is contained
  *     in every minimum cut, i.e. it is the minimal one.
  *
+ * With a soft smoothness weight alpha > 0 the checked graph also has the
+ * arcs (p,z) -> (q,z), z >= 1, of capacity alpha (their flows stored per
+ * direction at the tail like the lateral ones); they enter the bounds, the
+ * conservation, the residual reach, and the cut capacity as alpha *
+ * max(0, h(p) - h(q)) per ordered neighbour pair.  The energy then includes
+ * alpha * |h(p) - h(q)| per unordered pair.
+ *
  * The arc set checked is the one the solver stores: the down arc
  * (p,z)->(p,z-1) for z >= 1, and for each 4-neighbour q of p the lateral arc
  * (p,z)->(q,z-delta) when z > delta, plus (p,0)->(q,0).  The omitted arcs
@@ -40,14 +47,16 @@ typedef struct {
 static int lat_arc_exists(int64_t z, int64_t delta) { return z == 0 || z > delta; }
 static int64_t lat_target(int64_t z, int64_t delta) { return z == 0 ? 0 : z - delta; }
 
-int certify_preflow(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_,
-                    int32_t delta_, const int32_t *excess, const int32_t *sink_res,
-                    const int32_t *flow_down, const int32_t *flow_lat,
-                    const int32_t *surface, cert_result *out)
+int certify_preflow_soft(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_,
+                         int32_t delta_, int32_t alpha_, const int32_t *excess,
+                         const int32_t *sink_res, const int32_t *flow_down,
+                         const int32_t *flow_lat, const int32_t *flow_soft,
+                         const int32_t *surface, cert_result *out)
 {
     memset(out, 0, sizeof(*out));
-    const int64_t nx = nx_, ny = ny_, K = K_, delta = delta_;
-    if (nx < 1 || ny < 1 || K < 1 || delta < 0) return out->status = -1;
+    const int64_t nx = nx_, ny = ny_, K = K_, delta = delta_, alpha = alpha_;
+    if (nx < 1 || ny < 1 || K < 1 || delta < 0 || alpha < 0 || (alpha > 0 && !flow_soft))
+        return out->status = -1;
     const int64_t N = nx * ny * K, P = nx * ny;
     static const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
 
@@ -84,6 +93,19 @@ int certify_preflow(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_,
                     int64_t u = (qx * ny + qy) * K + lat_target(z, delta);
                     net[v] -= f; net[u] += f;
                 }
+                if (!flow_soft) continue;
+                for (int k = 0; k < 4; ++k) {
+                    int64_t f = flow_soft[(int64_t)k * N + v];
+                    int64_t qx = x + dx[k], qy = y + dy[k];
+                    int in = qx >= 0 && qx < nx && qy >= 0 && qy < ny;
+                    if (!in || z == 0 || alpha == 0) {
+                        if (f != 0) out->bad_capacity++;
+                        continue;
+                    }
+                    if (f < 0 || f > alpha) out->bad_capacity++;
+                    int64_t u = (qx * ny + qy) * K + z;
+                    net[v] -= f; net[u] += f;
+                }
             }
 
     /* Terminal arcs: the source arcs are saturated (the solver never returns
@@ -111,6 +133,10 @@ int certify_preflow(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_,
                 if (qx < 0 || qx >= nx || qy < 0 || qy >= ny) continue;
                 int64_t hq = surface[qx * ny + qy];
                 if (hq - h > delta || h - hq > delta) out->bad_smooth++;
+                if (hq >= 0 && hq < K) {
+                    if (h > hq) out->cut += alpha * (h - hq);   /* soft arcs (p,z)->(q,z), hq < z <= h */
+                    if (k == 0 || k == 2) out->energy += alpha * (h > hq ? h - hq : hq - h);
+                }
             }
             for (int64_t z = 0; z < K; ++z) {
                 int64_t v = p * K + z;
@@ -145,6 +171,11 @@ int certify_preflow(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_,
                 int64_t u = q * K + zt;
                 if (flow_lat[(int64_t)kk * N + u] > 0) VISIT(u);
             }
+            /* soft arc (p,z) -> (q,z): residual alpha - f(p->q) + f(q->p) */
+            if (alpha > 0 && z >= 1) {
+                int64_t u = q * K + z;
+                if (alpha - flow_soft[(int64_t)k * N + v] + flow_soft[(int64_t)kk * N + u] > 0) VISIT(u);
+            }
         }
     }
 #undef VISIT
@@ -158,4 +189,13 @@ int certify_preflow(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_,
 
     free(net); free(mark); free(queue);
     return 0;
+}
+
+/* The hard-bound certificate (alpha = 0, no soft arcs). */
+int certify_preflow(const int32_t *cost, int32_t nx, int32_t ny, int32_t K, int32_t delta,
+                    const int32_t *excess, const int32_t *sink_res, const int32_t *flow_down,
+                    const int32_t *flow_lat, const int32_t *surface, cert_result *out)
+{
+    return certify_preflow_soft(cost, nx, ny, K, delta, 0, excess, sink_res, flow_down, flow_lat,
+                                NULL, surface, out);
 }

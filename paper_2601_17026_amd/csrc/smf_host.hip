@@ -874,6 +874,17 @@ static int set_alpha(smf_handle *h, const int64_t *alpha, const char *who)
     return SMF_OK;
 }
 
+extern "C" int smf_export_soft_flows(const smf_handle *h, int32_t *flow_soft_dev, void *stream)
+{
+    if (!h || !flow_soft_dev) return fail(SMF_ERR_ARG, "smf_export_soft_flows: NULL argument");
+    if (!h->soft_flow || !h->g.soft)
+        return fail(SMF_ERR_ARG, "smf_export_soft_flows: no positive smooth_weight is set");
+    if (!h->solved) return fail(SMF_ERR_NOT_SOLVED, "smf_export_soft_flows: no successful solve");
+    HIP_TRY(hipMemcpyAsync(flow_soft_dev, h->soft_flow, 4 * sizeof(int) * (size_t)h->g.Ntot,
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return SMF_OK;
+}
+
 extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
 {
     if (!h || !key) return fail(SMF_ERR_ARG, "smf_set_param: NULL argument");

@@ -41,6 +41,7 @@ _lib.smf_flow_value.argtypes = [_P, _PI64]
 _lib.smf_energy.argtypes = [_P, _PI64]
 _lib.smf_surface.argtypes = [_P, _P, _P]
 _lib.smf_export_state.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.smf_export_soft_flows.argtypes = [_P, _P, _P]
 _lib.smf_set_param.argtypes = [_P, ctypes.c_char_p, _I64]
 _lib.smf_get_stat.argtypes = [_P, ctypes.c_char_p, _PI64]
 _lib.smf_status_string.argtypes = [ctypes.c_int]
@@ -68,13 +69,15 @@ for _name in ("smf_autotune", "smf_tune_apply", "smf_tune_cache_load", "smf_tune
               "smf_tune_cache_clear", "smf_tune_lookup"):
     getattr(_lib, _name).restype = ctypes.c_int
 for _name in ("smf_solve", "smf_flow_value", "smf_energy", "smf_surface",
-              "smf_export_state", "smf_set_param", "smf_get_stat", "smf_batch_solve",
+              "smf_export_state", "smf_export_soft_flows", "smf_set_param", "smf_get_stat",
+              "smf_batch_solve",
               "smf_batch_flow_values", "smf_batch_energies", "smf_batch_surfaces",
               "smf_batch_set_param", "smf_batch_get_stat"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 EXPORTED = ("smf_create", "smf_destroy", "smf_solve", "smf_flow_value", "smf_energy",
-            "smf_surface", "smf_export_state", "smf_set_param", "smf_get_stat",
+            "smf_surface", "smf_export_state", "smf_export_soft_flows", "smf_set_param",
+            "smf_get_stat",
             "smf_status_string", "smf_last_error", "smf_onehot_backward",
             "smf_batch_create", "smf_batch_solve", "smf_batch_flow_values",
             "smf_batch_energies", "smf_batch_surfaces", "smf_batch_set_param",
@@ -191,6 +194,15 @@ class Solver:
                                      fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
         return e, ts, fd, fl
 
+    def export_soft_flows(self, stream=None):
+        """Flows on the soft smoothness arcs (p,z) -> (q,z) as a (4, nx, ny, K)
+        device tensor, neighbour order +x, -x, +y, -y."""
+        nx, ny, K = self.shape
+        fs = torch.empty((4, nx, ny, K), dtype=torch.int32, device="cuda")
+        _check(_lib.smf_export_soft_flows(self._h, fs.data_ptr(), _stream_ptr(stream)),
+               "smf_export_soft_flows")
+        return fs
+
 
 class BatchSolver:
     """One handle for a batch of volumes of uneven shapes (nx, ny, K, delta),
@@ -282,6 +294,13 @@ class BatchSolver:
         _check(_lib.smf_export_state(self._h, e.data_ptr(), ts.data_ptr(), fd.data_ptr(),
                                      fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
         return e, ts, fd, fl
+
+    def export_soft_flows(self, stream=None):
+        """Flows on the soft smoothness arcs as a (4, total nodes) device tensor."""
+        fs = torch.empty((4, sum(self.sizes)), dtype=torch.int32, device="cuda")
+        _check(_lib.smf_export_soft_flows(self._h, fs.data_ptr(), _stream_ptr(stream)),
+               "smf_export_soft_flows")
+        return fs
 
 
 def autotune(solver, packed: torch.Tensor, offsets=None, stream=None) -> None:

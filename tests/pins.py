@@ -176,8 +176,17 @@ def networkx_flow(cost: np.ndarray, delta: int, alpha: int = 0) -> int:
 
 
 def reduced_preflow(cost: np.ndarray, delta: int):
+    """The hard-bound case of reduced_preflow_soft (no soft arcs); returns
+    (excess, sink residual, down flow, lateral flows, flow value)."""
+    e, ts, fd, fl, _, flow = reduced_preflow_soft(cost, delta, 0)
+    return e, ts, fd, fl, flow
+
+
+def reduced_preflow_soft(cost: np.ndarray, delta: int, alpha: int):
     """A maximum preflow of the reduced column graph by textbook FIFO
     push-relabel (Section 2.1), in plain Python loops for tiny volumes.
+    With alpha > 0 the graph also has the soft arcs (p,z) -> (q,z), z >= 1,
+    of capacity alpha; their flows come back as a fifth array.
 
     The reduced graph keeps the down arcs and, per 4-neighbour q, the
     lateral arcs (p,z) -> (q, z - delta) for z > delta plus (p,0) -> (q,0);
@@ -221,6 +230,8 @@ def reduced_preflow(cost: np.ndarray, delta: int):
                     qx, qy = x + ddx, y + ddy
                     if 0 <= qx < nx and 0 <= qy < ny and (z == 0 or z > delta):
                         add(v, idx(qx, qy, 0 if z == 0 else z - delta), -1, ("l", k))
+                    if alpha > 0 and 0 <= qx < nx and 0 <= qy < ny and z >= 1:
+                        add(v, idx(qx, qy, z), alpha, ("s", k))
 
     n = N + 2
     d = [0] * N
@@ -275,6 +286,7 @@ def reduced_preflow(cost: np.ndarray, delta: int):
     ts = np.zeros(N, dtype=np.int64)
     fd = np.zeros(N, dtype=np.int64)
     fl = np.zeros((4, N), dtype=np.int64)
+    fs = np.zeros((4, N), dtype=np.int64)
     flow = 0
     for tail, head, cap, f, kind in arcs:
         if kind[0] == "t":
@@ -282,8 +294,11 @@ def reduced_preflow(cost: np.ndarray, delta: int):
             flow += f
         elif kind[0] == "d":
             fd[tail] = f
-        else:
+        elif kind[0] == "l":
             fl[kind[1], tail] = f
+        else:
+            fs[kind[1], tail] = f
     sh = (nx, ny, K)
     return (e.reshape(sh).astype(np.int32), ts.reshape(sh).astype(np.int32),
-            fd.reshape(sh).astype(np.int32), fl.reshape((4,) + sh).astype(np.int32), flow)
+            fd.reshape(sh).astype(np.int32), fl.reshape((4,) + sh).astype(np.int32),
+            fs.reshape((4,) + sh).astype(np.int32), flow)

@@ -22,14 +22,21 @@ def smf():
     return mod
 
 
-def _solve(smf, cost, delta, alpha, params=None):
+def _solve(smf, cost, delta, alpha, params=None, certify=False):
     c = torch.from_numpy(np.ascontiguousarray(cost, dtype=np.int32)).cuda()
     with smf.Solver(*cost.shape, delta) as s:
         s.set_param("smooth_weight", alpha)
         for k, v in (params or {}).items():
             s.set_param(k, v)
         s.solve(c)
-        return dict(flow=s.flow_value(), energy=s.energy(), surface=s.surface().cpu().numpy())
+        out = dict(flow=s.flow_value(), energy=s.energy(), surface=s.surface().cpu().numpy())
+        if certify:
+            e, ts, fd, fl = (t.cpu().numpy() for t in s.export_state())
+            fs = s.export_soft_flows().cpu().numpy()
+            torch.cuda.synchronize()
+            out["cert"] = oracle.certify(cost, delta, e, ts, fd, fl, out["surface"], alpha=alpha,
+                                         flow_soft=fs)
+        return out
 
 
 def _check(cost, delta, alpha, g):
@@ -58,12 +65,37 @@ def test_soft_tiny(smf, shape, delta, alpha):
 @pytest.mark.parametrize("case", ["small", "layered", "ragged"])
 @pytest.mark.parametrize("alpha", [1, 3, 16])
 def test_soft_workloads(smf, case, alpha):
-    # several tiles of columns and chunks, K not a multiple of 64
+    # several tiles of columns and chunks, K not a multiple of 64; the final
+    # preflow with its soft-arc flows also passes the certificate
     cost, delta = {"small": synth.config_small(),
                    "layered": (synth.layered_cost(37, 29, 70, 2, 0.4, 255, 0.05, 23), 1),
                    "ragged": (synth.layered_cost(50, 21, 130, 2, 0.5, 255, 0.1, 29), 2)}[case]
     print(f"case: soft {case} {cost.shape} delta {delta} alpha {alpha}", flush=True)
-    _check(cost, delta, alpha, _solve(smf, cost, delta, alpha))
+    g = _solve(smf, cost, delta, alpha, certify=True)
+    _check(cost, delta, alpha, g)
+    assert g["cert"].ok, g["cert"]
+    assert g["cert"].flow == g["flow"] and g["cert"].energy == g["energy"]
+
+
+def test_soft_full_size_seismic(smf):
+    # 512 x 512 x 384 with alpha 16, the soft leg of the benchmark: too large
+    # for the oracle, so the max-flow/min-cut certificate of the final
+    # preflow (soft flows included) proves F and the minimal surface, and F
+    # equals the closed form of the energy
+    cost, delta = synth.config_seismic()
+    print("case: soft full-size seismic 512x512x384 delta 2 alpha 16", flush=True)
+    g = _solve(smf, cost, delta, 16, certify=True)
+    assert g["cert"].ok, g["cert"]
+    assert g["cert"].flow == g["flow"] and g["cert"].energy == g["energy"]
+    assert g["flow"] == pins.flow_closed_form(cost, g["energy"])
+
+
+def test_soft_export_errors(smf):
+    cost, delta = synth.config_small()
+    with smf.Solver(*cost.shape, delta) as s:
+        s.solve(torch.from_numpy(cost).cuda())
+        with pytest.raises(smf.SmfError):
+            s.export_soft_flows()       # no soft term set
 
 
 @pytest.mark.parametrize("params", [{"relabel_period": 1}, {"gap_every": 1}, {"bfs_early_stop": 0},

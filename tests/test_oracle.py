@@ -267,3 +267,41 @@ def test_soft_planted_surface():
     r = oracle.solve(c, 1, 2)
     np.testing.assert_array_equal(r.hmin, h)
     _check_soft_invariants(c, 1, 2, r)
+
+
+@pytest.mark.parametrize("shape,delta,alpha", [((2, 3, 5), 1, 2), ((3, 3, 6), 2, 5), ((1, 4, 7), 0, 3), ((4, 2, 6), 3, 1)])
+def test_certificate_accepts_soft_preflow(shape, delta, alpha):
+    # an independent push-relabel with the soft arcs reaches the oracle's
+    # flow value, and the certificate accepts its state with the oracle's
+    # minimal surface and soft energy
+    for seed in range(3):
+        c = synth.random_cost(*shape, -25, 25, seed=700 + seed)
+        r = oracle.solve(c, delta, alpha)
+        e, ts, fd, fl, fs, flow = pins.reduced_preflow_soft(c, delta, alpha)
+        assert flow == r.flow
+        cert = oracle.certify(c, delta, e, ts, fd, fl, r.hmin, alpha=alpha, flow_soft=fs)
+        assert cert.ok, cert
+        assert cert.flow == r.flow and cert.energy == r.energy
+
+
+def test_certificate_rejects_soft_mistakes():
+    c = synth.random_cost(3, 3, 6, -25, 25, seed=701)
+    delta, alpha = 1, 3
+    r = oracle.solve(c, delta, alpha)
+    e, ts, fd, fl, fs, flow = pins.reduced_preflow_soft(c, delta, alpha)
+    assert oracle.certify(c, delta, e, ts, fd, fl, r.hmin, alpha=alpha, flow_soft=fs).ok
+    # the soft flows left out: conservation fails where they moved excess
+    if fs.any():
+        assert not oracle.certify(c, delta, e, ts, fd, fl, r.hmin, alpha=alpha,
+                                  flow_soft=np.zeros_like(fs)).ok
+    # a soft flow above its capacity
+    fs2 = fs.copy(); fs2[0, 0, 0, 2] = alpha + 1
+    assert oracle.certify(c, delta, e, ts, fd, fl, r.hmin, alpha=alpha, flow_soft=fs2).bad_capacity > 0
+    # the hard-bound surface is not the soft optimum here, or the checker
+    # must still accept it only if it is the soft minimal cut
+    hard = oracle.solve(c, delta)
+    cert_h = oracle.certify(c, delta, e, ts, fd, fl, hard.hmin, alpha=alpha, flow_soft=fs)
+    assert cert_h.ok == bool((hard.hmin == r.hmin).all())
+    # a soft preflow checked as if there were no soft arcs fails
+    if fs.any():
+        assert not oracle.certify(c, delta, e, ts, fd, fl, r.hmin).ok
