@@ -201,3 +201,21 @@ def test_batch_workload_64_volumes(smf):
             s.solve(torch.from_numpy(vols[i]).cuda())
             assert s.flow_value() == g["flow"][i]
             np.testing.assert_array_equal(s.surface().cpu().numpy(), g["surface"][i])
+
+
+def test_batch_many_volumes_scattered_searches(smf):
+    # 150 small volumes with periods 1..7 spread over the batch: searches take
+    # part in scattered subsets of volumes, so the level launches cover many
+    # runs of volumes (more than the 16 column ranges a launch takes, so
+    # gaps are merged) and volumes leave a search at different polls
+    rng = np.random.default_rng(90)
+    shapes = [(int(rng.integers(1, 9)), int(rng.integers(1, 9)), int(rng.integers(2, 40)),
+               int(rng.integers(0, 4))) for _ in range(150)]
+    vols = [synth.random_cost(nx, ny, K, -30, 30, seed=9500 + i) if i % 3 == 0 else
+            synth.layered_cost(nx, ny, K, 1, 0.4, 255, 0.1, 9500 + i)
+            for i, (nx, ny, K, _) in enumerate(shapes)]
+    periods = [int(p) for p in rng.integers(1, 8, size=150)]
+    print("case: 150 small volumes, scattered searches", flush=True)
+    g = _solve_batch(smf, shapes, vols, params={"bfs_poll_every": 2}, per_volume={"relabel_period": periods})
+    _check_oracle(shapes, vols, g)
+    assert max(g["relabels"]) > 1
