@@ -166,6 +166,11 @@ int smf_export_soft_flows(const smf_handle *h, int32_t *flow_soft_dev, void *str
  *                        at most one per column)
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
+ *   "block_search"    -- 1 (default): a plain handle of at most 1536 columns
+ *                        and 4096 64-height column chunks runs each global
+ *                        relabel as one block with its
+ *                        records in LDS (no launch or host poll per level);
+ *                        0: always one launch per level
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
  *   "count_work"      -- 1: kernels count their algorithmic bytes ("bytes.<class>"
  *                        statistics of bfs, push, relabel; one atomic per wave

@@ -21,6 +21,7 @@ constexpr int kInf = 0x40000000;       // label of a node that cannot reach t
 constexpr int kUnl = kInf - 1;         // not (yet) reached by the running BFS
 constexpr int kErrCostRange = 1;       // a cost outside (-2^30, 2^30)
 constexpr int kErrOverflow = 2;        // an int32 excess or flow would overflow
+constexpr int kErrSearch = 4;          // a one-block search ran past its level bound
 constexpr int kWave = 64;              // CDNA wavefront width = heights per chunk
 constexpr int kLvlSlots = 64;          // BFS level flags kept per volume
 constexpr int kMaxRanges = 16;         // column ranges a BFS level launch covers
@@ -132,6 +133,7 @@ struct Scratch {
     int changed;         // a min-cut pass changed something
     int count[2];        // sizes of the two column work lists
     int short_count;     // size of the running global relabel's short-column list
+    int block_levels;    // levels run by one-block searches since the solve began
 };
 constexpr int kScratchHead = 64;
 static_assert(sizeof(Scratch) <= kScratchHead, "Scratch must fit its header");

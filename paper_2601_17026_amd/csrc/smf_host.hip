@@ -35,6 +35,9 @@ void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, in
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
                       int *Tout, int *LFout, const LevelRanges &R, hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
+bool bfs_block_fits(const Geom &g);
+void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
+                      int max_level, Scratch *s, hipStream_t st);
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
@@ -202,6 +205,7 @@ struct smf_handle {
     int64_t poll_every = 1;
     int64_t bfs_poll_every = 16;
     int64_t bfs_early_stop = 1;
+    int64_t block_search = 1;      // small single volumes: whole searches in one block
     int64_t verbose = 0;           // 1: progress lines on stderr
     int64_t gap_every = 0;         // sweeps between gap searches (0: off)
 
@@ -410,6 +414,8 @@ static int wait_snapshot(smf_handle *h, int slot)
         return fail(SMF_ERR_RANGE, "smf_solve: a cost lies outside (-2^30, 2^30)");
     if (h->host->err & kErrOverflow)
         return fail(SMF_ERR_RANGE, "smf_solve: an int32 excess or flow counter overflowed");
+    if (h->host->err & kErrSearch)
+        return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: breadth-first search did not settle");
     return SMF_OK;
 }
 
@@ -518,6 +524,18 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     {
         TimedScope ts(h->timer, KC_BFS_RESET, s);
         launch_bfs_init(h->g, h->st, T[1], LF[1], c0, c1, s);   // level 1 lives in buffer 1
+    }
+    if (h->block_search && bfs_block_fits(h->g)) {
+        // a small single volume: the whole search in one block, no polls
+        {
+            TimedScope ts(h->timer, KC_BFS, s);
+            launch_bfs_block(h->g, h->st, T[1], LF[1], (int)h->bfs_early_stop,
+                             (int)std::min<int64_t>(h->max_inst_nodes + 2, INT32_MAX), h->scr, s);
+        }
+        HIP_TRY(hipGetLastError());
+        h->inst_relabels[0]++;
+        h->global_relabels++;
+        return SMF_OK;
     }
     // The host reads the counters one batch of levels behind the device:
     // batch k+1 is enqueued before batch k's snapshot is examined, so the
@@ -727,6 +745,7 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     HIP_TRY(hipGetLastError());
     rc = sync_scratch(h, s);
     if (rc) return rc;
+    h->bfs_passes += h->host->block_levels;
     for (int i = 0; i < n; ++i) {
         h->flow[i] = h->is_host[i].flow;
         h->energy[i] = h->is_host[i].energy;
@@ -932,6 +951,11 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
         if (value < 4 || value > (1 << 20))
             return fail(SMF_ERR_ARG, "smf_set_param: sweep_waves must lie in [4, 2^20]");
         h->g.sweep_waves = (int)value;
+        return SMF_OK;
+    }
+    else if (!strcmp(key, "block_search")) {
+        if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: block_search is 0 or 1");
+        h->block_search = value;
         return SMF_OK;
     }
     else if (!strcmp(key, "bfs_early_stop")) {

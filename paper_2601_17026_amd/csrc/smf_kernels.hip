@@ -423,6 +423,7 @@ __global__ void k_init_scratch(Geom g, Scratch *s)
     if (i == 0) {
         s->err = 0;
         s->changed = 0;
+        s->block_levels = 0;
         s->count[0] = 0;
         s->count[1] = 0;
     }
@@ -1348,6 +1349,41 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
     }
 }
 
+// One column's step of level L -> L+1: reads the records of column p and
+// of its neighbours from Tin / LFin (P columns per array), sets T (the old
+// threshold), cand (the new one when the column moved), lf and `self` (the
+// column changed at level L-1), and returns whether the threshold moved.
+// The change flags in the records give the frontier: with no change at
+// level L-1 around p none of p's inputs moved, and both record buffers
+// already hold p's record.
+template <bool kSoft>
+__device__ __forceinline__ bool column_step(const Geom &g, const Col &col, int p, const int *Tin,
+                                            const int *LFin, int P, int &T, int &cand, int lf[4],
+                                            bool &self, long long &bytes)
+{
+    const int K = col.I.K, dl = col.I.delta;
+    int q[4], tq[4], lq[4];
+    const int tw = Tin[p];
+    self = tw < 0;
+    T = tw & ~kChanged;
+    bool near = self;
+    int nq = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        q[k] = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
+        const int w = q[k] >= 0 ? Tin[q[k]] : -1;
+        lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
+        lf[k] = LFin[(size_t)k * P + p];
+        near = near || (q[k] >= 0 && w < 0);
+        tq[k] = q[k] >= 0 ? (w & ~kChanged) : -1;
+        nq += q[k] >= 0;
+    }
+    bytes = 4 * (1 + nq) + 4 * (4 + nq) + 4;
+    cand = T;
+    if (near) bytes += 8 * level_update<kSoft>(g, p, K, dl, col.I.alpha, T, tq, lq, lf, cand);
+    return near && cand < T;
+}
+
 // Level L -> L+1, one lane per column of the ranges R.  The threshold
 // arithmetic reads the records of the column and its neighbours; the lowest
 // flow-carrying lateral arcs among the newly reached heights [cand, T) come
@@ -1367,7 +1403,7 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
     for (int j = 1; j < R.n; ++j) r += t >= R.pre[j];
     const bool valid = t < R.pre[R.n];
     const int p = valid ? R.lo[r] + (t - R.pre[r]) : 0;
-    bool self = false, near = false;
+    bool self = false, need = false;
     int T = 0, cand = 0, ii = 0;
     long long base = 0;
     int lf[4] = {0, 0, 0, 0};
@@ -1375,32 +1411,9 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
     if (valid) {
         const Col col = column(g, p);
         ii = col.ii;
-        const int K = col.I.K, dl = col.I.delta;
         base = (long long)col.base;
-        // the column's and its neighbours' records in one round of loads;
-        // the change flags in them give the frontier: with no change at level
-        // L-1 around p none of p's inputs moved, and both record buffers
-        // already hold p's record
-        int q[4], tq[4], lq[4];
-        const int tw = Tin[p];
-        self = tw < 0;
-        T = tw & ~kChanged;
-        near = self;
-        int nq = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            q[k] = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
-            const int w = q[k] >= 0 ? Tin[q[k]] : -1;
-            lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
-            lf[k] = LFin[(size_t)k * P + p];
-            near = near || (q[k] >= 0 && w < 0);
-            tq[k] = q[k] >= 0 ? (w & ~kChanged) : -1;
-            nq += q[k] >= 0;
-        }
-        bytes = 4 * (1 + nq) + 4 * (4 + nq) + 4;
-        if (near) bytes += 8 * level_update<kSoft>(g, p, K, dl, col.I.alpha, T, tq, lq, lf, cand);
+        need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, bytes);
     }
-    const bool need = valid && near && cand < T;
     if (valid) {
         Tout[p] = need ? (cand | kChanged) : T;
         if (need || self) {
@@ -1412,6 +1425,90 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
     // level L labelled something in the volumes of the lanes with `need`
     set_level_flag(g, ii, need, L % kLvlSlots);
     bytes += label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, base);
+    if (g.count_work) count_bytes(g, 0, bytes);
+}
+
+// A whole search of one small volume in one block (a plain handle of at
+// most kBlockSearchCols columns): the records live in LDS, double-buffered
+// as in global memory, and block barriers separate the levels instead of
+// launches and host polls.  Level 1 comes from k_bfs_init (records T1,
+// LF1).  The search ends when a level labels nothing (unreached nodes get
+// kInf) or, with early_stop, once no column's threshold lies above its
+// lowest active node (unreached nodes get the first level not run).  The
+// block then writes those fill labels itself and adds its level count to
+// s->block_levels.  Every column step is the one of k_bfs_level, so the
+// labels are the same.
+constexpr int kBlockSearchCols = 1536;
+
+template <bool kSoft>
+__global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d, const int *__restrict__ T1,
+                                                   const int *__restrict__ LF1, int early_stop,
+                                                   int max_level, Scratch *s)
+{
+    extern __shared__ int sm[];
+    const int P = g.Ptot;
+    int *const sT[2] = {sm, sm + P};
+    int *const sLF[2] = {sm + 2 * P, sm + 6 * P};
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        sT[1][i] = T1[i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sLF[1][(size_t)k * P + i] = LF1[(size_t)k * P + i];
+    }
+    __syncthreads();
+    const int slots = (P + (int)blockDim.x - 1) / (int)blockDim.x;
+    const Inst I = g.inst[0];
+    long long bytes = 0;
+    int L = 1, cur = 1, run = 0;
+    bool complete = false;
+    for (;; ++L, cur ^= 1) {
+        if (L > max_level) {
+            if (threadIdx.x == 0) atomicOr(&s->err, kErrSearch);
+            break;
+        }
+        const int *Tin = sT[cur], *LFin = sLF[cur];
+        int *Tout = sT[cur ^ 1], *LFout = sLF[cur ^ 1];
+        bool moved = false;
+        for (int slot = 0; slot < slots; ++slot) {
+            const int p = slot * (int)blockDim.x + (int)threadIdx.x;
+            const bool valid = p < P;
+            bool self = false, need = false;
+            int T = 0, cand = 0;
+            long long base = 0, b = 0;
+            int lf[4] = {0, 0, 0, 0};
+            if (valid) {
+                const Col col = column_in(I, 0, p);
+                base = (long long)col.base;
+                need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, b);
+                Tout[p] = need ? (cand | kChanged) : T;
+                if (need || self)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) LFout[(size_t)k * P + p] = lf[k];
+            }
+            bytes += b + label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, base);
+            moved = moved || need;
+        }
+        ++run;
+        // every record of level L+1 is written before any is read or counted
+        __syncthreads();
+        if (!__syncthreads_or(moved)) {
+            complete = true;   // level L labelled nothing
+            break;
+        }
+        if (early_stop) {
+            bool short_col = false;
+            for (int p = threadIdx.x; p < P; p += blockDim.x)
+                short_col = short_col || (sT[cur ^ 1][p] & ~kChanged) > g.low_act[p];
+            if (!__syncthreads_or(short_col)) {
+                ++L;   // levels <= L are done: unreached nodes lie beyond L + 1
+                break;
+            }
+        }
+    }
+    // fix-up: L is the first level whose labels were not all written
+    const int fill = complete ? kInf : L + 1;
+    for (long long v = threadIdx.x; v < (long long)I.N; v += blockDim.x)
+        if (d[I.node_base + v] == kUnl) d[I.node_base + v] = fill;
+    if (threadIdx.x == 0) atomicAdd(&s->block_levels, run);
     if (g.count_work) count_bytes(g, 0, bytes);
 }
 
@@ -1667,6 +1764,28 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
     else
         hipLaunchKernelGGL(k_bfs_level<false>, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d,
                            L, Tin, LFin, Tout, LFout, R);
+}
+
+// Deep columns make a level of one block longer than a level launched
+// over the grid (measured: 32x48x500 5% slower, 24x64x256 even), so the
+// block search also needs few 64-height chunks.
+constexpr long long kBlockSearchChunks = 4096;
+
+bool bfs_block_fits(const Geom &g)
+{
+    return g.n == 1 && g.Ptot <= kBlockSearchCols && (long long)g.Ptot * g.max_nch <= kBlockSearchChunks;
+}
+
+void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
+                      int max_level, Scratch *s, hipStream_t st)
+{
+    const size_t lds = sizeof(int) * 10 * (size_t)g.Ptot;
+    if (g.soft)
+        hipLaunchKernelGGL(k_bfs_block<true>, dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1, early_stop,
+                           max_level, s);
+    else
+        hipLaunchKernelGGL(k_bfs_block<false>, dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1, early_stop,
+                           max_level, s);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)

@@ -175,9 +175,13 @@ def test_error_paths(smf):
     {"relabel_period": 1},
     {"relabel_period": 40},
     {"poll_every": 4, "bfs_poll_every": 3},
+    {"block_search": 0},
+    {"block_search": 0, "bfs_early_stop": 0},
 ])
 def test_parameter_variants(smf, params):
-    # every schedule knob leaves the exact result unchanged
+    # every schedule knob leaves the exact result unchanged; both volumes
+    # have at most 1536 columns, so their searches run in one block unless
+    # block_search is 0
     for cost, delta in (synth.config_small(),
                         (synth.layered_cost(37, 29, 70, 2, 0.4, 255, 0.05, 23), 1)):
         print(f"case: params {params} shape {cost.shape}", flush=True)

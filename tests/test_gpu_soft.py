@@ -99,7 +99,7 @@ def test_soft_export_errors(smf):
 
 
 @pytest.mark.parametrize("params", [{"relabel_period": 1}, {"gap_every": 1}, {"bfs_early_stop": 0},
-                                    {"relabel_period": 1000, "gap_every": 1}])
+                                    {"relabel_period": 1000, "gap_every": 1}, {"block_search": 0}])
 def test_soft_parameter_variants(smf, params):
     cost = synth.layered_cost(24, 31, 45, 2, 0.4, 255, 0.05, 31)
     print(f"case: soft variants {params}", flush=True)
