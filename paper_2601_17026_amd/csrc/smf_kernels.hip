@@ -544,14 +544,29 @@ __device__ __forceinline__ void mark_mask(const Work &w, int q, unsigned long lo
 
 // Column list of every column with a non-empty work mask.  Also clears the
 // counters that the relabel phase after it fills: the size of its output
-// list and the per-volume active counts.
-__global__ __launch_bounds__(256) void k_compact(Geom g, Work w, int *next_count)
+// list and the per-volume active counts.  A block of 1024 columns takes its
+// share of the list with one atomic (one per wave serialised on the single
+// counter when the columns number millions).
+__global__ __launch_bounds__(1024) void k_compact(Geom g, Work w, int *next_count)
 {
+    __shared__ int wave_n[16], block_base;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
     if (p == 0) *next_count = 0;
     if (p < g.n) g.is[p].active = 0;
     const bool want = p < g.Ptot && w.mask[p] != 0;
-    wave_append(w.list, w.count, want, p);
+    const unsigned long long b = __ballot(want);
+    if (lane == 0) wave_n[wid] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int i = 0; i < (int)blockDim.x / kWave; ++i) total += wave_n[i];
+        block_base = total ? atomicAdd(w.count, total) : 0;
+    }
+    __syncthreads();
+    int off = block_base;
+    for (int i = 0; i < wid; ++i) off += wave_n[i];
+    if (want) w.list[off + __popcll(b & ((1ULL << lane) - 1ULL))] = p;
 }
 
 // Loads of one 64-height chunk of a column: the node words of every lane,
@@ -1749,7 +1764,7 @@ void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, in
 
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_count, dim3(64), dim3(256), 0, st, g, T, slot);
+    hipLaunchKernelGGL(k_bfs_count, dim3(256), dim3(256), 0, st, g, T, slot);
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
@@ -1820,7 +1835,7 @@ void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wo
 void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st)
 {
     const long long n = g.Ptot > g.n ? g.Ptot : g.n;
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n)), dim3(256), 0, st, g, w, next_count);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + 1023) / 1024)), dim3(1024), 0, st, g, w, next_count);
 }
 
 void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st)
