@@ -202,3 +202,18 @@ def test_gap_heuristic_freezes_nodes(smf, case):
     assert g["stats"]["gap_relabels"] > 0
     _assert_matches_oracle(cost, delta, g)
     assert g["cert"].ok, g["cert"]
+
+
+@pytest.mark.parametrize("shape,delta", [((32, 48, 64), 2), ((48, 32, 128), 1)])
+def test_block_search_at_its_limit(smf, shape, delta):
+    # 1536 columns (the most a one-block search takes, 60 KiB of LDS
+    # records) with one and two 64-height chunks: the one-block search and
+    # the launch-per-level search give the oracle's exact result
+    cost = synth.layered_cost(*shape, 2, 0.4, 255, 0.05, 47)
+    print(f"case: block search limit {shape} delta {delta}", flush=True)
+    r = oracle.solve(cost, delta)
+    for bs in (1, 0):
+        g = _gpu_solve(smf, cost, delta, certify=True, params={"block_search": bs})
+        assert (g["flow"], g["energy"]) == (r.flow, r.energy), bs
+        np.testing.assert_array_equal(g["surface"], r.hmin)
+        assert g["cert"].ok, (bs, g["cert"])
