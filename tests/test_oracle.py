@@ -169,6 +169,18 @@ def test_certificate_rejects_mistakes():
     ts0 = np.maximum(0, w).astype(np.int32)
     z = oracle.certify(c, delta, e0, ts0, N0, np.zeros_like(fl), r.hmin)
     assert z.bad_conservation == 0 and not z.ok
+    # one unit taken back from a sink arc inside the minimal cut: the state
+    # is still a preflow whose reach set has the same column tops, but it is
+    # one unit short of maximum and the sink is reachable from the excess
+    inside = (np.arange(c.shape[2])[None, None, :] <= r.hmin[:, :, None]) & (w > 0) & (ts < w)
+    assert inside.any()
+    v = tuple(np.argwhere(inside)[0])
+    e1, ts1 = e.copy(), ts.copy()
+    e1[v] += 1
+    ts1[v] += 1
+    short = oracle.certify(c, delta, e1, ts1, fd, fl, r.hmin)
+    assert short.bad_capacity == 0 and short.bad_conservation == 0
+    assert short.bad_reach > 0 and short.flow == r.flow - 1 and not short.ok
 
 
 # ---- soft smoothness: alpha * sum |h(p) - h(q)| over neighbour pairs ----------
