@@ -217,3 +217,50 @@ def test_block_search_at_its_limit(smf, shape, delta):
         assert (g["flow"], g["energy"]) == (r.flow, r.energy), bs
         np.testing.assert_array_equal(g["surface"], r.hmin)
         assert g["cert"].ok, (bs, g["cert"])
+
+
+def test_int32_excess_overflow_is_reported(smf):
+    # Costs at the edge of the accepted range (|c| = 2^30 - 1).  The top
+    # nodes of the two outer columns of a 3x1x2 volume (delta 0) hold
+    # 2^31 - 2 units of excess each, and their only admissible arc leads to
+    # the middle column's top node, whose sink arc takes 1 unit and which has
+    # no admissible arc of its own in the first push phase.  Whatever order
+    # the three atomic updates of its excess take, the int32 word would pass
+    # 2^31 - 1: the solve must fail with ERR_RANGE instead of returning a
+    # wrong result, and the handle must then solve an ordinary volume exactly.
+    M = (1 << 30) - 1
+    cost = np.array([[[M, -M]], [[0, 1]], [[M, -M]]], dtype=np.int32)
+    r = oracle.solve(cost, 0)
+    assert r.flow == 1
+    print("case: int32 excess overflow 3x1x2", flush=True)
+    with smf.Solver(3, 1, 2, 0) as s:
+        with pytest.raises(smf.SmfError) as ei:
+            s.solve(torch.from_numpy(cost).cuda())
+        assert ei.value.status == smf.ERR_RANGE
+        ok = synth.random_cost(3, 1, 2, -50, 50, seed=61)
+        s.solve(torch.from_numpy(ok).cuda())
+        r = oracle.solve(ok, 0)
+        assert (s.flow_value(), s.energy()) == (r.flow, r.energy)
+        np.testing.assert_array_equal(s.surface().cpu().numpy(), r.hmin)
+
+
+@pytest.mark.parametrize("shape,delta", [((4, 4, 6), 1), ((3, 5, 9), 0), ((6, 2, 5), 2)])
+def test_extreme_costs_exact_or_range_error(smf, shape, delta):
+    # costs drawn from the whole accepted range: every solve either gives the
+    # oracle's exact result (with a valid certificate) or reports ERR_RANGE,
+    # never a silently wrong answer
+    M = (1 << 30) - 1
+    outcomes = set()
+    for seed in range(4):
+        cost = synth.random_cost(*shape, -M, M, seed=6100 + seed)
+        print(f"case: extreme costs {shape} delta {delta} seed {seed}", flush=True)
+        try:
+            g = _gpu_solve(smf, cost, delta, certify=True)
+        except smf.SmfError as e:
+            assert e.status == smf.ERR_RANGE, e
+            outcomes.add("range")
+            continue
+        _assert_matches_oracle(cost, delta, g)
+        assert g["cert"].ok, g["cert"]
+        outcomes.add("exact")
+    print(f"outcomes {sorted(outcomes)}", flush=True)
