@@ -150,3 +150,33 @@ def test_soft_mid_volume(smf):
     cost = synth.layered_cost(80, 72, 66, 3, 0.4, 255, 0.05, 71)
     print("case: soft 80x72x66 delta 2 alpha 2", flush=True)
     _check(cost, 2, 2, _solve(smf, cost, 2, 2))
+
+
+def test_soft_weight_at_its_limit(smf):
+    # alpha = 2^29 is the largest weight accepted (the soft residuals
+    # alpha - f + f' then stay below 2^31); 2^29 + 1 is refused
+    amax = 1 << 29
+    with smf.Solver(4, 4, 4, 1) as s:
+        with pytest.raises(smf.SmfError):
+            s.set_param("smooth_weight", amax + 1)
+    for shape, delta in [((5, 4, 9), 2), ((3, 6, 70), 1)]:
+        cost = synth.random_cost(*shape, 0, 1000, seed=9300)
+        print(f"case: soft weight 2^29 {shape} delta {delta}", flush=True)
+        g = _solve(smf, cost, delta, amax, certify=True)
+        _check(cost, delta, amax, g)
+        assert g["cert"].ok, g["cert"]
+        # any step costs more than the whole feature term could gain
+        assert (g["surface"] == g["surface"][0, 0]).all()
+    # the largest weight with costs over the whole accepted range: the exact
+    # result or ERR_RANGE, never a wrong answer
+    M = (1 << 30) - 1
+    for seed in range(3):
+        cost = synth.random_cost(4, 4, 6, -M, M, seed=9310 + seed)
+        print(f"case: soft weight 2^29 extreme costs seed {seed}", flush=True)
+        try:
+            g = _solve(smf, cost, 1, amax, certify=True)
+        except smf.SmfError as e:
+            assert e.status == smf.ERR_RANGE, e
+            continue
+        _check(cost, 1, amax, g)
+        assert g["cert"].ok, g["cert"]
