@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/smf.h"
+#include "level_cover.h"
 #include "smf_device.h"
 
 namespace smf {
@@ -434,58 +435,19 @@ static int sync_scratch(smf_handle *h, hipStream_t s)
 // unfinished level, a valid lower bound).  The host checks every
 // bfs_poll_every levels; levels launched after a volume's last productive
 // one are no-ops for it.
-// Chooses the volumes that the next levels of a search cover: every volume
-// in `live`, and of the others in `cover` only those in the smallest gaps
-// between runs of live volumes, as many as keep the covered volumes within
-// kMaxRanges runs of consecutive volumes (volumes are packed in order, so a
-// run is one column range).  `cover` only ever shrinks during a search: a
-// level may cover a column only if every earlier level covered it, since
-// the record buffers of a column that a level skipped fall behind.  Every
-// live volume lies in `cover`, and `cover` forms at most kMaxRanges runs,
-// so the gaps inside a run of `cover` always suffice.
-static void shrink_cover(const smf_handle *h, const std::vector<char> &live, std::vector<char> &cover,
+// Chooses the volumes, and so the column ranges, that the next levels of a
+// search cover (every live volume, `cover` only shrinking; level_cover.h).
+// False if more than kMaxRanges ranges would be needed, which the rules of
+// the choice exclude.
+static bool shrink_cover(const smf_handle *h, const std::vector<char> &live, std::vector<char> &cover,
                          LevelRanges &R)
 {
-    const int n = h->n;
-    std::vector<std::pair<int, int>> runs;   // first and last volume of each run of live volumes
-    for (int i = 0; i < n; ++i) {
-        if (!live[i]) continue;
-        if (!runs.empty() && runs.back().second == i - 1) runs.back().second = i;
-        else runs.push_back({i, i});
-    }
-    // gaps between consecutive runs whose volumes are all still covered
-    std::vector<std::pair<long long, size_t>> gaps;   // (columns, run before the gap)
-    for (size_t k = 0; k + 1 < runs.size(); ++k) {
-        bool ok = true;
-        long long cols = 0;
-        for (int i = runs[k].second + 1; i < runs[k + 1].first; ++i) {
-            ok = ok && cover[i];
-            cols += h->inst[i].P;
-        }
-        if (ok) gaps.push_back({cols, k});
-    }
-    std::sort(gaps.begin(), gaps.end());
-    std::vector<char> join(runs.size(), 0);   // run k continues into run k + 1
-    size_t nruns = runs.size();
-    for (const auto &gp : gaps) {
-        if (nruns <= (size_t)kMaxRanges) break;
-        join[gp.second] = 1;
-        --nruns;
-    }
-    std::vector<char> next((size_t)n, 0);
-    R.n = 0;
-    R.pre[0] = 0;
-    for (size_t k = 0; k < runs.size();) {
-        size_t e = k;
-        while (join[e]) ++e;
-        const int a = runs[k].first, b = runs[e].second;
-        for (int i = a; i <= b; ++i) next[i] = 1;
-        R.lo[R.n] = h->inst[a].col_base;
-        R.pre[R.n + 1] = R.pre[R.n] + (h->inst[b].col_base + h->inst[b].P - h->inst[a].col_base);
-        ++R.n;
-        k = e + 1;
-    }
-    cover.swap(next);
+    const int nr = cover_ranges(
+        h->n, [h](int i) { return h->inst[i].col_base; }, [h](int i) { return h->inst[i].P; }, live,
+        cover, kMaxRanges, R.lo, R.pre);
+    if (nr < 0) return false;
+    R.n = nr;
+    return true;
 }
 
 static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> &part)
@@ -516,8 +478,8 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
     for (int i = 0; i < n; ++i)
         cover[i] = h->inst[i].col_base >= c0 && h->inst[i].col_base < c1;
     LevelRanges R;
-    shrink_cover(h, live, cover, R);
-    if (R.n > kMaxRanges) return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
+    if (!shrink_cover(h, live, cover, R))
+        return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
     HIP_TRY(hipMemcpyAsync(h->part_dev, h->part_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
     launch_bfs_begin(h->g, s);
     launch_set_int(&h->scr->short_count, 0, s);
@@ -589,7 +551,8 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
                 }
                 break;
             }
-            if (ended) shrink_cover(h, live, cover, R);
+            if (ended && !shrink_cover(h, live, cover, R))
+                return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
         }
         inflight = true;
         slot ^= 1;
