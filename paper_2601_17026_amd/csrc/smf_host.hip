@@ -323,7 +323,14 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     h->max_inst_nodes = max_nodes;
     h->inst_period.assign((size_t)n, 0);
     const size_t P = (size_t)Ptot, N = (size_t)Ntot;
-    if (hipGetDevice(&h->device) != hipSuccess || !dev_alloc(h->inst_dev, n) ||
+    const hipError_t dev_err = hipGetDevice(&h->device);
+    if (dev_err != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        fail(SMF_ERR_HIP, std::string("smf_batch_create: no usable HIP device: ") + hipGetErrorString(dev_err));
+        return nullptr;
+    }
+    if (!dev_alloc(h->inst_dev, n) ||
         !dev_alloc(h->col_inst, P) || !dev_alloc(h->cnt_dev, counter_bytes(n)) || !dev_alloc(h->part_dev, n) ||
         !dev_alloc(h->fill_dev, n) || !dev_alloc(h->state, 8 * N) || !dev_alloc(h->H, P) ||
         !dev_alloc(h->bfs, 12 * P) || !dev_alloc(h->bits, (size_t)kMasks * max_nch * P) ||

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "smf.h")
 LIB = os.path.join(ROOT, "paper_2601_17026_amd", "_libsmf.so")
@@ -131,3 +133,16 @@ def test_tune_cache_env_file_without_gpu(tmp_path):
     env = dict(os.environ, SMF_TUNE_CACHE=str(src))
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
     assert r.stdout.strip() == "12"
+
+
+def test_no_gpu_fails_loudly():
+    # with no GPU, creating a solver raises and names the missing device:
+    # nothing on the product path falls back to the CPU
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2601_17026_amd import smf
+    for make in (lambda: smf.Solver(4, 4, 4, 1), lambda: smf.BatchSolver([(4, 4, 4, 1), (3, 5, 6, 0)])):
+        with pytest.raises(smf.SmfError) as ei:
+            make()
+        assert "no usable HIP device" in str(ei.value)
