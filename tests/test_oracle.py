@@ -1,5 +1,8 @@
 """Pins of the CPU oracle (no GPU): the oracle against brute force, an exact
 row DP, closed forms, library max-flow routines and its own invariants."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -317,3 +320,29 @@ def test_certificate_rejects_soft_mistakes():
     # a soft preflow checked as if there were no soft arcs fails
     if fs.any():
         assert not oracle.certify(c, delta, e, ts, fd, fl, r.hmin).ok
+
+
+# ---- stored expected values (tests/golden, written by make_golden.py) -------
+
+def _stored(name):
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,maker", [("small", synth.config_small), ("mid", synth.config_mid)])
+def test_generators_reproduce_stored_inputs(name, maker):
+    # the seeded inputs are the bytes the stored values were computed on
+    cost, delta = maker()
+    ref = _stored(name)
+    assert list(cost.shape) == ref["shape"] and delta == ref["delta"]
+    assert synth.sha256(cost) == ref["cost_sha256"], "input generator drifted"
+
+
+def test_oracle_reproduces_stored_small_workload():
+    # regression check of the oracle itself on the 32x32x64 workload
+    cost, delta = synth.config_small()
+    ref = _stored("small")
+    r = oracle.solve(cost, delta)
+    assert (r.flow, r.energy) == (ref["flow"], ref["energy"])
+    assert synth.sha256(r.hmin.astype(np.int32)) == ref["surface_sha256"]
+    assert synth.sha256(r.hmax.astype(np.int32)) == ref["surface_max_sha256"]
