@@ -25,11 +25,13 @@ from . import smf
 _SOLVERS: dict = {}
 
 
-def _solver(B: int, nx: int, ny: int, K: int, delta: int) -> smf.BatchSolver:
-    key = (torch.cuda.current_device(), B, nx, ny, K, delta)
+def _solver(device: int, B: int, nx: int, ny: int, K: int, delta: int) -> smf.BatchSolver:
+    """A cached batch handle on GPU `device` for B volumes of one shape."""
+    key = (device, B, nx, ny, K, delta)
     s = _SOLVERS.get(key)
     if s is None:
-        s = smf.BatchSolver([(nx, ny, K, delta)] * B)
+        with torch.cuda.device(device):
+            s = smf.BatchSolver([(nx, ny, K, delta)] * B)
         _SOLVERS[key] = s
     return s
 
@@ -46,7 +48,7 @@ class SurfaceEnergy(torch.autograd.Function):
             raise ValueError("cost must be a (B, nx, ny, K) CUDA tensor")
         B, nx, ny, K = cost.shape
         ci = quantize(cost.detach().float(), scale)
-        solver = _solver(B, nx, ny, K, int(delta))
+        solver = _solver(cost.device.index, B, nx, ny, K, int(delta))
         solver.set_param_per_volume("smooth_weight", [soft_weight(alpha, scale)] * B)
         h = torch.empty((B, nx, ny), dtype=torch.int32, device=cost.device)
         solver.solve(ci.view(-1))

@@ -97,18 +97,33 @@ def _check(status: int, where: str) -> None:
         raise SmfError(status, where)
 
 
-def _stream_ptr(stream) -> int:
+def _stream_ptr(stream, device: int) -> int:
+    """The HIP stream of `stream` (default: the current stream of `device`),
+    which must belong to `device`."""
     if stream is None:
-        stream = torch.cuda.current_stream()
+        stream = torch.cuda.current_stream(device)
+    elif stream.device.index != device:
+        raise ValueError(f"stream is on {stream.device}, the handle on cuda:{device}")
     return int(stream.cuda_stream)
 
 
-def _dev_i32(t: torch.Tensor, shape, name: str) -> torch.Tensor:
+def _on_device(t: torch.Tensor, name: str, device: int) -> None:
+    if t.device.index != device:
+        raise ValueError(f"{name} is on {t.device}, the handle on cuda:{device}")
+
+
+def _dev_i32(t: torch.Tensor, shape, name: str, device: int) -> torch.Tensor:
     if t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous int32 CUDA tensor")
+    _on_device(t, name, device)
     if tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
     return t
+
+
+def _empty(shape, dtype, device: int) -> torch.Tensor:
+    """An output buffer on GPU `device`."""
+    return torch.empty(shape, dtype=dtype, device=torch.device("cuda", device))
 
 
 class Solver:
@@ -122,6 +137,7 @@ class Solver:
         if not h:
             raise SmfError(ERR_NOMEM, "smf_create")
         self._h = h
+        self.device = torch.cuda.current_device()   # the GPU the library allocated on
 
     def close(self) -> None:
         h = getattr(self, "_h", None)
@@ -162,8 +178,8 @@ class Solver:
         return list(arr)
 
     def solve(self, cost: torch.Tensor, stream=None) -> None:
-        _dev_i32(cost, self.shape, "cost")
-        _check(_lib.smf_solve(self._h, cost.data_ptr(), _stream_ptr(stream)), "smf_solve")
+        _dev_i32(cost, self.shape, "cost", self.device)
+        _check(_lib.smf_solve(self._h, cost.data_ptr(), _stream_ptr(stream, self.device)), "smf_solve")
 
     def flow_value(self) -> int:
         out = ctypes.c_int64()
@@ -178,28 +194,26 @@ class Solver:
     def surface(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         nx, ny, _ = self.shape
         if out is None:
-            out = torch.empty((nx, ny), dtype=torch.int32, device="cuda")
-        _dev_i32(out, (nx, ny), "out")
-        _check(_lib.smf_surface(self._h, out.data_ptr(), _stream_ptr(stream)), "smf_surface")
+            out = _empty((nx, ny), torch.int32, self.device)
+        _dev_i32(out, (nx, ny), "out", self.device)
+        _check(_lib.smf_surface(self._h, out.data_ptr(), _stream_ptr(stream, self.device)), "smf_surface")
         return out
 
     def export_state(self, stream=None):
         """Final preflow as (excess, sink_res, flow_down, flow_lat) device tensors."""
         nx, ny, K = self.shape
-        e = torch.empty((nx, ny, K), dtype=torch.int32, device="cuda")
-        ts = torch.empty_like(e)
-        fd = torch.empty_like(e)
-        fl = torch.empty((4, nx, ny, K), dtype=torch.int32, device="cuda")
+        e, ts, fd = (_empty((nx, ny, K), torch.int32, self.device) for _ in range(3))
+        fl = _empty((4, nx, ny, K), torch.int32, self.device)
         _check(_lib.smf_export_state(self._h, e.data_ptr(), ts.data_ptr(), fd.data_ptr(),
-                                     fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
+                                     fl.data_ptr(), _stream_ptr(stream, self.device)), "smf_export_state")
         return e, ts, fd, fl
 
     def export_soft_flows(self, stream=None):
         """Flows on the soft smoothness arcs (p,z) -> (q,z) as a (4, nx, ny, K)
         device tensor, neighbour order +x, -x, +y, -y."""
         nx, ny, K = self.shape
-        fs = torch.empty((4, nx, ny, K), dtype=torch.int32, device="cuda")
-        _check(_lib.smf_export_soft_flows(self._h, fs.data_ptr(), _stream_ptr(stream)),
+        fs = _empty((4, nx, ny, K), torch.int32, self.device)
+        _check(_lib.smf_export_soft_flows(self._h, fs.data_ptr(), _stream_ptr(stream, self.device)),
                "smf_export_soft_flows")
         return fs
 
@@ -219,6 +233,7 @@ class BatchSolver:
         if not h:
             raise SmfError(ERR_NOMEM, "smf_batch_create")
         self._h = h
+        self.device = torch.cuda.current_device()   # the GPU the library allocated on
         self.sizes = [nx * ny * K for nx, ny, K, _ in shapes]
         self.columns = [nx * ny for nx, ny, _, _ in shapes]
         self.offsets = [0]
@@ -244,7 +259,7 @@ class BatchSolver:
         if len(costs) != self.n:
             raise ValueError(f"expected {self.n} volumes, got {len(costs)}")
         for c, (nx, ny, K, _) in zip(costs, self.shapes):
-            _dev_i32(c, (nx, ny, K), "cost")
+            _dev_i32(c, (nx, ny, K), "cost", self.device)
         return torch.cat([c.reshape(-1) for c in costs])
 
     def solve(self, packed: torch.Tensor, offsets=None, stream=None) -> None:
@@ -252,11 +267,12 @@ class BatchSolver:
         (default: densely packed in order)."""
         if packed.device.type != "cuda" or packed.dtype != torch.int32 or not packed.is_contiguous():
             raise ValueError("packed costs must be a contiguous int32 CUDA tensor")
+        _on_device(packed, "packed costs", self.device)
         offs = self.offsets if offsets is None else [int(o) for o in offsets]
         if len(offs) != self.n or any(o < 0 or o + n > packed.numel() for o, n in zip(offs, self.sizes)):
             raise ValueError("cost offsets do not fit the packed buffer")
         arr = (ctypes.c_int64 * self.n)(*offs)
-        _check(_lib.smf_batch_solve(self._h, packed.data_ptr(), arr, _stream_ptr(stream)),
+        _check(_lib.smf_batch_solve(self._h, packed.data_ptr(), arr, _stream_ptr(stream, self.device)),
                "smf_batch_solve")
 
     def flow_values(self) -> list:
@@ -273,9 +289,9 @@ class BatchSolver:
         """Packed surfaces: volume i's (nx, ny) heights at col_offsets[i]."""
         total = sum(self.columns)
         if out is None:
-            out = torch.empty((total,), dtype=torch.int32, device="cuda")
-        _dev_i32(out, (total,), "out")
-        _check(_lib.smf_batch_surfaces(self._h, out.data_ptr(), _stream_ptr(stream)),
+            out = _empty((total,), torch.int32, self.device)
+        _dev_i32(out, (total,), "out", self.device)
+        _check(_lib.smf_batch_surfaces(self._h, out.data_ptr(), _stream_ptr(stream, self.device)),
                "smf_batch_surfaces")
         return out
 
@@ -287,18 +303,16 @@ class BatchSolver:
         """Final packed preflow as flat (excess, sink_res, flow_down, flow_lat)
         device tensors; flow_lat is (4, total nodes)."""
         total = sum(self.sizes)
-        e = torch.empty((total,), dtype=torch.int32, device="cuda")
-        ts = torch.empty_like(e)
-        fd = torch.empty_like(e)
-        fl = torch.empty((4, total), dtype=torch.int32, device="cuda")
+        e, ts, fd = (_empty((total,), torch.int32, self.device) for _ in range(3))
+        fl = _empty((4, total), torch.int32, self.device)
         _check(_lib.smf_export_state(self._h, e.data_ptr(), ts.data_ptr(), fd.data_ptr(),
-                                     fl.data_ptr(), _stream_ptr(stream)), "smf_export_state")
+                                     fl.data_ptr(), _stream_ptr(stream, self.device)), "smf_export_state")
         return e, ts, fd, fl
 
     def export_soft_flows(self, stream=None):
         """Flows on the soft smoothness arcs as a (4, total nodes) device tensor."""
-        fs = torch.empty((4, sum(self.sizes)), dtype=torch.int32, device="cuda")
-        _check(_lib.smf_export_soft_flows(self._h, fs.data_ptr(), _stream_ptr(stream)),
+        fs = _empty((4, sum(self.sizes)), torch.int32, self.device)
+        _check(_lib.smf_export_soft_flows(self._h, fs.data_ptr(), _stream_ptr(stream, self.device)),
                "smf_export_soft_flows")
         return fs
 
@@ -309,12 +323,14 @@ def autotune(solver, packed: torch.Tensor, offsets=None, stream=None) -> None:
     period.  `packed` is the volume (Solver) or the packed batch costs."""
     if packed.device.type != "cuda" or packed.dtype != torch.int32 or not packed.is_contiguous():
         raise ValueError("costs must be a contiguous int32 CUDA tensor")
+    _on_device(packed, "costs", solver.device)
     arr = None
     if offsets is not None:
         arr = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
     elif isinstance(solver, BatchSolver):
         arr = (ctypes.c_int64 * solver.n)(*solver.offsets)
-    _check(_lib.smf_autotune(solver._h, packed.data_ptr(), arr, _stream_ptr(stream)), "smf_autotune")
+    _check(_lib.smf_autotune(solver._h, packed.data_ptr(), arr, _stream_ptr(stream, solver.device)),
+           "smf_autotune")
 
 
 def tune_apply(solver) -> None:
@@ -346,20 +362,33 @@ def onehot_backward(surface: torch.Tensor, grad_energy: torch.Tensor, K: int,
     if surface.dim() != 3:
         raise ValueError("surface must be (n, nx, ny)")
     n, nx, ny = surface.shape
-    _dev_i32(surface, (n, nx, ny), "surface")
+    if surface.device.type != "cuda":
+        raise ValueError("surface must be a CUDA tensor")
+    device = surface.device.index
+    _dev_i32(surface, (n, nx, ny), "surface", device)
     if grad_energy.device.type != "cuda" or grad_energy.dtype != torch.float32 \
             or not grad_energy.is_contiguous() or tuple(grad_energy.shape) != (n,):
         raise ValueError("grad_energy must be a contiguous float32 CUDA tensor of shape (n,)")
+    _on_device(grad_energy, "grad_energy", device)
     if out is None:
-        out = torch.empty((n, nx, ny, K), dtype=torch.float32, device=surface.device)
-    _check(_lib.smf_onehot_backward(surface.data_ptr(), grad_energy.data_ptr(), out.data_ptr(),
-                                    n, nx, ny, int(K), _stream_ptr(stream)), "smf_onehot_backward")
+        out = _empty((n, nx, ny, int(K)), torch.float32, device)
+    elif out.device.type != "cuda" or out.dtype != torch.float32 or not out.is_contiguous() \
+            or tuple(out.shape) != (n, nx, ny, int(K)):
+        raise ValueError(f"out must be a contiguous float32 CUDA tensor of shape {(n, nx, ny, int(K))}")
+    _on_device(out, "out", device)
+    with torch.cuda.device(device):   # the kernel runs on the surface's GPU
+        _check(_lib.smf_onehot_backward(surface.data_ptr(), grad_energy.data_ptr(), out.data_ptr(),
+                                        n, nx, ny, int(K), _stream_ptr(stream, device)),
+               "smf_onehot_backward")
     return out
 
 
 def solve(cost: torch.Tensor, delta: int, stream=None):
     """Solves one (nx, ny, K) int32 CUDA volume; returns (flow, energy, surface)."""
-    with Solver(*cost.shape, delta) as s:
-        s.solve(cost, stream)
-        surf = s.surface(stream=stream)
-        return s.flow_value(), s.energy(), surf
+    if cost.device.type != "cuda":
+        raise ValueError("cost must be a CUDA tensor")
+    with torch.cuda.device(cost.device.index):   # the handle lives on the volume's GPU
+        with Solver(*cost.shape, delta) as s:
+            s.solve(cost, stream)
+            surf = s.surface(stream=stream)
+            return s.flow_value(), s.energy(), surf
