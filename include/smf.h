@@ -25,6 +25,10 @@
  *   - "device pointer" means memory the caller allocated on the current HIP
  *     device; the caller keeps ownership.  Volumes are contiguous
  *     [nx][ny][K] int32 (z fastest), surfaces contiguous [nx][ny] int32.
+ *   - A handle belongs to the HIP device that was current when it was
+ *     created: every device pointer and stream passed with it must belong
+ *     to that device (the library cannot check this; memory of another
+ *     device is a fault, not an error code).
  *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
  *   - Every int-returning call returns SMF_OK (0) or a negative SMF_ERR_*
  *     code; smf_last_error() then describes the failure (thread-local).
