@@ -5,7 +5,9 @@ None of these shares code with the oracle or with the GPU library:
     definition of the optimal net surface, Section 1.2 and Eq. 1);
   - an exact dynamic program along a single row of columns;
   - the closed form of the max-flow value from the optimal energy;
-  - library max-flow routines (scipy, networkx) on the explicit graph.
+  - library max-flow routines (scipy, networkx) on the explicit graph, and
+    a second oracle built on scipy's: both extreme minimum cuts read off
+    its residual graph.
 """
 from __future__ import annotations
 
@@ -153,6 +155,35 @@ def scipy_flow(cost: np.ndarray, delta: int, alpha: int = 0) -> int:
     # delta = 0) add up, as the sparse constructor sums duplicates
     m = sp.csr_array((a[:, 2].astype(np.int32), (a[:, 0], a[:, 1])), shape=(n, n))
     return int(maximum_flow(m, s, t).flow_value)
+
+
+def scipy_cuts(cost: np.ndarray, delta: int, alpha: int = 0):
+    """A second oracle: scipy's max-flow on the explicit graph, and the
+    extreme minimum cuts read off its residual graph (Theorem 1.1): S_min is
+    what s reaches, S_max what cannot reach t.  Returns (F, h_min, h_max)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order, maximum_flow
+
+    nx, ny, K = cost.shape
+    arcs, s, t, n = explicit_arcs(cost, delta, inf=1 << 28, alpha=alpha)
+    a = np.array(arcs, dtype=np.int64)
+    cap = sp.csr_array((a[:, 2].astype(np.int32), (a[:, 0], a[:, 1])), shape=(n, n))
+    res = maximum_flow(cap, s, t)
+    # net flow is antisymmetric, so capacity minus flow is the residual
+    # capacity of every ordered pair, reverse arcs included
+    r = sp.csr_array(cap.astype(np.int64) - res.flow.astype(np.int64))
+    r.data[r.data < 0] = 0
+    r.eliminate_zeros()
+    from_s = np.zeros(n, bool)
+    from_s[breadth_first_order(r, s, directed=True, return_predecessors=False)] = True
+    to_t = np.zeros(n, bool)
+    to_t[breadth_first_order(sp.csr_array(r.T), t, directed=True, return_predecessors=False)] = True
+    smin = from_s[:-2].reshape(nx, ny, K)
+    smax = ~to_t[:-2].reshape(nx, ny, K)
+    zs = np.arange(K)
+    hmin = np.where(smin, zs, -1).max(axis=2).astype(np.int32)
+    hmax = np.where(smax, zs, -1).max(axis=2).astype(np.int32)
+    return int(res.flow_value), hmin, hmax
 
 
 def networkx_flow(cost: np.ndarray, delta: int, alpha: int = 0) -> int:

@@ -346,3 +346,37 @@ def test_oracle_reproduces_stored_small_workload():
     assert (r.flow, r.energy) == (ref["flow"], ref["energy"])
     assert synth.sha256(r.hmin.astype(np.int32)) == ref["surface_sha256"]
     assert synth.sha256(r.hmax.astype(np.int32)) == ref["surface_max_sha256"]
+
+
+# ---- a second oracle: scipy's max-flow with cuts read off its residual ------
+
+def test_second_oracle_small_workload():
+    # the 32x32x64 workload: flow value and both extreme minimum cuts agree
+    # bit for bit (the two cuts differ in some columns, so h_max is checked
+    # on its own)
+    cost, delta = synth.config_small()
+    r = oracle.solve(cost, delta)
+    F, hmin, hmax = pins.scipy_cuts(cost, delta)
+    assert F == r.flow
+    np.testing.assert_array_equal(hmin, r.hmin)
+    np.testing.assert_array_equal(hmax, r.hmax)
+    assert (r.hmin != r.hmax).any()
+
+
+@pytest.mark.parametrize("shape,delta,alpha", [
+    ((1, 9, 7), 1, 0), ((6, 1, 5), 0, 0), ((5, 6, 1), 2, 0), ((4, 5, 6), 9, 0),
+    ((12, 10, 20), 2, 0), ((9, 8, 33), 1, 0), ((7, 9, 12), 1, 2), ((10, 6, 15), 3, 5),
+])
+def test_second_oracle_random_shapes(shape, delta, alpha):
+    # degenerate shapes (one row, one column line, K = 1, delta >= K),
+    # random and layered costs, with and without the soft term
+    for seed in range(2):
+        if seed == 0:
+            c = synth.random_cost(*shape, 0, 3, seed=800 + sum(shape))    # many ties
+        else:
+            c = synth.layered_cost(*shape, 1, 0.4, 255, 0.05, 810 + sum(shape))
+        r = oracle.solve(c, delta, alpha)
+        F, hmin, hmax = pins.scipy_cuts(c, delta, alpha)
+        assert F == r.flow
+        np.testing.assert_array_equal(hmin, r.hmin)
+        np.testing.assert_array_equal(hmax, r.hmax)
