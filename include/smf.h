@@ -83,7 +83,10 @@ smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int32_t *ny,
 void smf_destroy(smf_handle *h);
 
 /* Solves the volume `cost_dev` (device pointer, [nx][ny][K] int32, every
- * value in (-2^30, 2^30)).  Work is enqueued on `stream`; the call drives
+ * value in (-2^30, 2^30)): builds the graph of Section 1.2 from the costs,
+ * runs push-relabel with global relabelling (Section 2.1) to a maximum
+ * preflow, and reads the minimum cut off it (Section 1.3, Eqs. 5-7,
+ * Theorem 1.1).  Work is enqueued on `stream`; the call drives
  * the iteration from the host and returns when the result is complete, so
  * on SMF_OK the flow value, energy and surface are ready.  The cost buffer
  * is only read.  SMF_ERR_ARG for a batch handle of more than one volume. */
@@ -97,11 +100,14 @@ int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream);
 int smf_batch_solve(smf_handle *h, const int32_t *packed_cost_dev, const int64_t *offsets_host,
                     void *stream);
 
-/* Max-flow value F of the last successful solve (host int64 out).
+/* Max-flow value F of the last successful solve (host int64 out): the
+ * flow into t of Eq. 5, equal to the capacity of the minimum cut
+ * (Theorem 1.1).
  * SMF_ERR_ARG for a batch of more than one volume. */
 int smf_flow_value(const smf_handle *h, int64_t *out);
 
-/* Optimal energy E* = sum_p c(p, h(p)) of the last successful solve, plus
+/* Optimal energy E* = sum_p c(p, h(p)) of the last successful solve (the
+ * surface cost of Eq. 1 at the minimal-cut surface), plus
  * alpha * sum |h(p) - h(q)| over 4-neighbour column pairs when the soft
  * smoothness weight alpha ("smooth_weight") is positive.
  * SMF_ERR_ARG for a batch of more than one volume. */
@@ -116,7 +122,10 @@ int smf_batch_flow_values(const smf_handle *h, int64_t *out);
 int smf_batch_energies(const smf_handle *h, int64_t *out);
 
 /* Copies the minimal-cut surface h (values in [0, K-1]) of the last
- * successful solve into `out_dev` (device pointer, [nx][ny] int32),
+ * successful solve into `out_dev`: h(p) is the highest node of column p on
+ * the source side of the inclusion-minimal minimum cut (Eqs. 6-7,
+ * Theorem 1.1), the pointwise-lowest minimiser of Eq. 1 under the smoothness
+ * bound (device pointer, [nx][ny] int32),
  * enqueued on `stream`. */
 int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream);
 

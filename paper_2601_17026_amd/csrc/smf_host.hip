@@ -42,7 +42,8 @@ void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
-void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st);
+void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, bool use_gap,
+                    hipStream_t st);
 void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st);
 void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
@@ -633,6 +634,7 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     // enqueued after the volumes have finished finds empty work lists.
     int slot = 0;
     bool inflight = false;
+    bool gap_fresh = false;   // a gap search ran after the last relabel phase
     for (;;) {
         if (h->sweeps >= h->max_sweeps)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: sweep cap reached");
@@ -659,14 +661,18 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
             launch_compact(h->g, h->work[1], h->work[0].count, s);
             {
                 TimedScope ts(h->timer, KC_RELABEL, s);
-                launch_relabel(h->g, h->st, h->work[1], h->work[0], s);
+                // a gap holds only for the labels it was found on: the
+                // relabel phase right after its search uses it, no later one
+                launch_relabel(h->g, h->st, h->work[1], h->work[0], gap_fresh, s);
             }
+            gap_fresh = false;
             h->sweeps++;
             for (int i = 0; i < n; ++i)
                 if (!done[i]) { since[i]++; h->inst_sweeps[i]++; }
             if (h->gap_every > 0 && h->sweeps % h->gap_every == 0) {
                 launch_gap_find(h->g, h->st, h->max_inst_nodes, s);
                 h->gap_searches++;
+                gap_fresh = true;
             }
         }
         HIP_TRY(hipGetLastError());

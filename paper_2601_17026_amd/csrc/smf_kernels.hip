@@ -895,11 +895,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // d(w) + len(u, w) (kInf when that exceeds every possible distance).  The
 // column's mask is rebuilt from the nodes that stay active, which are
 // counted per volume, and the column goes on the next push phase's list.
+// With use_gap (only in the relabel phase right after a gap search: the
+// pushes in between change no label) a node labelled above its volume's gap
+// was cut off from t when the gap was found and is frozen; a later phase
+// must not use that gap, since a node relabelled across it since then may
+// still reach t.
 // Eight waves per SIMD (64 VGPRs, a few spilled): with the sweep grid of
 // 8192 waves every wave is resident at once, and the phase is bound by
 // memory latency, which more waves in flight hide.
 template <bool kSoft>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_relabel(Geom g, State st, Work win, Work wout)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_relabel(Geom g, State st, Work win, Work wout, int use_gap)
 {
     const int lane = lane_id();
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -927,7 +932,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         const int ii = uniform(__shfl(myii, src, kWave));
         if (ii != cur_ii) {
             cur = g.inst[ii];
-            gap = g.is[ii].gap;
+            gap = use_gap ? g.is[ii].gap : kInf;
             cur_ii = ii;
         }
         const Col col = column_in(cur, ii, p);
@@ -1364,39 +1369,47 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
     }
 }
 
-// One column's step of level L -> L+1: reads the records of column p and
-// of its neighbours from Tin / LFin (P columns per array), sets T (the old
-// threshold), cand (the new one when the column moved), lf and `self` (the
+// One column's step of level L -> L+1: reads the threshold words of column
+// p and of its neighbours from Tin (P columns per array), sets T (the old
+// threshold), cand (the new one when the column moved) and `self` (the
 // column changed at level L-1), and returns whether the threshold moved.
-// The change flags in the records give the frontier: with no change at
-// level L-1 around p none of p's inputs moved, and both record buffers
-// already hold p's record.
+// The change flags in the threshold words give the frontier: with no change
+// at level L-1 around p none of p's inputs moved, and both record buffers
+// already hold p's record, so only a column next to a change loads its
+// lowest-flow record lf[] and its neighbours' words of it (LFin) and scans
+// its masks.  `bytes` gets the column's algorithmic bytes: its own threshold
+// word read and rewritten, and when near a change its 16-byte record and the
+// mask words scanned.  Neighbours' words are their own records, counted with
+// their own column.
 template <bool kSoft>
 __device__ __forceinline__ bool column_step(const Geom &g, const Col &col, int p, const int *Tin,
                                             const int *LFin, int P, int &T, int &cand, int lf[4],
                                             bool &self, long long &bytes)
 {
     const int K = col.I.K, dl = col.I.delta;
-    int q[4], tq[4], lq[4];
+    int q[4], tq[4];
     const int tw = Tin[p];
     self = tw < 0;
     T = tw & ~kChanged;
     bool near = self;
-    int nq = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         q[k] = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
         const int w = q[k] >= 0 ? Tin[q[k]] : -1;
-        lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
-        lf[k] = LFin[(size_t)k * P + p];
         near = near || (q[k] >= 0 && w < 0);
         tq[k] = q[k] >= 0 ? (w & ~kChanged) : -1;
-        nq += q[k] >= 0;
     }
-    bytes = 4 * (1 + nq) + 4 * (4 + nq) + 4;
+    bytes = 8;
     cand = T;
-    if (near) bytes += 8 * level_update<kSoft>(g, p, K, dl, col.I.alpha, T, tq, lq, lf, cand);
-    return near && cand < T;
+    if (!near) return false;
+    int lq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
+        lf[k] = LFin[(size_t)k * P + p];
+    }
+    bytes += 16 + 8 * level_update<kSoft>(g, p, K, dl, col.I.alpha, T, tq, lq, lf, cand);
+    return cand < T;
 }
 
 // Level L -> L+1, one lane per column of the ranges R.  The threshold
@@ -1838,10 +1851,12 @@ void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t s
     hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + 1023) / 1024)), dim3(1024), 0, st, g, w, next_count);
 }
 
-void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, hipStream_t st)
+void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work &wout, bool use_gap,
+                    hipStream_t st)
 {
-    if (g.soft) hipLaunchKernelGGL(k_relabel<true>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
-    else hipLaunchKernelGGL(k_relabel<false>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout);
+    const int ug = use_gap ? 1 : 0;
+    if (g.soft) hipLaunchKernelGGL(k_relabel<true>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout, ug);
+    else hipLaunchKernelGGL(k_relabel<false>, dim3(sweep_blocks(g)), dim3(256), 0, st, g, sv, win, wout, ug);
 }
 
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
