@@ -289,6 +289,27 @@ int smf_onehot_backward(const int32_t *surface_dev, const float *grad_energy_dev
                         float *grad_cost_dev, int32_t n, int32_t nx, int32_t ny, int32_t K,
                         void *stream);
 
+/* Allocation-free solve of one volume, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Computes what smf_create + smf_solve +
+ * smf_flow_value + smf_energy + smf_surface + smf_destroy give for the same
+ * volume (no soft smoothness term, default schedule) and calls no hipMalloc,
+ * hipFree, pinned-memory or other allocating routine.  Inputs and outputs are
+ * the caller's: cost_dev [nx][ny][K] int32 device pointer (values in
+ * (-2^30, 2^30)), surface_dev [nx][ny] int32 device pointer (written),
+ * flow_out and energy_out host int64 (written on SMF_OK).  All solver state
+ * lives in one static device array of SMF_NOALLOC_MAX_BYTES bytes that every
+ * GPU the library runs on holds until the process ends; a volume needs
+ * about 33 bytes per node plus 120 bytes per column, and a larger one is
+ * refused with SMF_ERR_NOMEM before any device work.  Calls on one GPU share
+ * that array: calls that overlap on one GPU (other host threads, or streams
+ * not ordered with the previous call's) race and give wrong results.
+ * Blocks the host until the result is complete (counters are read with
+ * blocking copies); work runs on `stream`. */
+#define SMF_NOALLOC_MAX_BYTES (64ULL << 20)
+int smf_solve_noalloc(const int32_t *cost_dev, int32_t nx, int32_t ny, int32_t K, int32_t delta,
+                      int32_t *surface_dev, int64_t *flow_out, int64_t *energy_out, void *stream);
+
 /* Static text for a status code. */
 const char *smf_status_string(int status);
 

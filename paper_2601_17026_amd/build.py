@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "_libsmf.so")
-SOURCES = ["smf_kernels.hip", "smf_host.hip", "smf_grad.hip", "smf_tune.cpp"]
+SOURCES = ["smf_kernels.hip", "smf_host.hip", "smf_noalloc.hip", "smf_grad.hip", "smf_tune.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

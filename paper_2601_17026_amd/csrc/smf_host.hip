@@ -53,18 +53,26 @@ void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H
 
 using namespace smf;
 
-static thread_local std::string g_last_error;
+// Text of the last failure on this host thread, kept in a fixed buffer so
+// that recording a failure allocates nothing (longer texts are cut).
+constexpr size_t kErrLen = 512;
+static thread_local char g_last_error[kErrLen];
 
-static int fail(int code, const std::string &msg)
+static int fail_text(int code, const char *msg)
 {
-    g_last_error = msg;
+    size_t i = 0;
+    for (; msg && msg[i] && i + 1 < kErrLen; ++i) g_last_error[i] = msg[i];
+    g_last_error[i] = 0;
     return code;
 }
+
+static int fail(int code, const std::string &msg) { return fail_text(code, msg.c_str()); }
 
 namespace smf {
 // Records the failure of an entry point defined in another source file.
 int set_error(int code, const std::string &msg) { return fail(code, msg); }
-void clear_error() { g_last_error.clear(); }
+int set_error_text(int code, const char *msg) { return fail_text(code, msg); }
+void clear_error() { g_last_error[0] = 0; }
 }  // namespace smf
 
 #define HIP_TRY(call)                                                                     \
@@ -273,7 +281,7 @@ static bool alloc_snapshots(smf_handle *h)
 extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int32_t *ny,
                                         const int32_t *K, const int32_t *delta)
 {
-    g_last_error.clear();
+    g_last_error[0] = 0;
     if (n < 1 || !nx || !ny || !K || !delta) {
         fail(SMF_ERR_ARG, "smf_batch_create: need n >= 1 and non-NULL shape arrays");
         return nullptr;
@@ -754,7 +762,7 @@ static int solve_checked(smf_handle *h, const int32_t *cost_dev, const int64_t *
 
 extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
 {
-    g_last_error.clear();
+    g_last_error[0] = 0;
     if (!h || !cost_dev) return fail(SMF_ERR_ARG, "smf_solve: NULL handle or cost");
     if (h->n != 1) return fail(SMF_ERR_ARG, "smf_solve: the handle holds a batch; use smf_batch_solve");
     return solve_checked(h, cost_dev, nullptr, (hipStream_t)stream);
@@ -763,7 +771,7 @@ extern "C" int smf_solve(smf_handle *h, const int32_t *cost_dev, void *stream)
 extern "C" int smf_batch_solve(smf_handle *h, const int32_t *packed_cost_dev,
                                const int64_t *offsets_host, void *stream)
 {
-    g_last_error.clear();
+    g_last_error[0] = 0;
     if (!h || !packed_cost_dev) return fail(SMF_ERR_ARG, "smf_batch_solve: NULL handle or cost");
     if (offsets_host)
         for (int i = 0; i < h->n; ++i)
@@ -1045,4 +1053,4 @@ extern "C" const char *smf_status_string(int status)
     }
 }
 
-extern "C" const char *smf_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *smf_last_error(void) { return g_last_error; }

@@ -65,6 +65,9 @@ _lib.smf_tune_cache_load.argtypes = [ctypes.c_char_p]
 _lib.smf_tune_cache_save.argtypes = [ctypes.c_char_p]
 _lib.smf_tune_cache_clear.argtypes = []
 _lib.smf_tune_lookup.argtypes = [_I32, _I32, _I32, _I32, _PI64]
+_lib.smf_solve_noalloc.argtypes = [_P, _I32, _I32, _I32, _I32, _P, _PI64, _PI64, _P]
+_lib.smf_solve_noalloc.restype = ctypes.c_int
+NOALLOC_MAX_BYTES = 64 << 20   # SMF_NOALLOC_MAX_BYTES
 for _name in ("smf_autotune", "smf_tune_apply", "smf_tune_cache_load", "smf_tune_cache_save",
               "smf_tune_cache_clear", "smf_tune_lookup"):
     getattr(_lib, _name).restype = ctypes.c_int
@@ -82,7 +85,8 @@ EXPORTED = ("smf_create", "smf_destroy", "smf_solve", "smf_flow_value", "smf_ene
             "smf_batch_create", "smf_batch_solve", "smf_batch_flow_values",
             "smf_batch_energies", "smf_batch_surfaces", "smf_batch_set_param",
             "smf_batch_get_stat", "smf_autotune", "smf_tune_apply", "smf_tune_cache_load",
-            "smf_tune_cache_save", "smf_tune_cache_clear", "smf_tune_lookup")
+            "smf_tune_cache_save", "smf_tune_cache_clear", "smf_tune_lookup",
+            "smf_solve_noalloc")
 
 
 class SmfError(RuntimeError):
@@ -392,3 +396,24 @@ def solve(cost: torch.Tensor, delta: int, stream=None):
             s.solve(cost, stream)
             surf = s.surface(stream=stream)
             return s.flow_value(), s.energy(), surf
+
+
+def solve_noalloc(cost: torch.Tensor, delta: int, surface: torch.Tensor | None = None, stream=None):
+    """Solves one (nx, ny, K) int32 CUDA volume through the allocation-free
+    entry point (all solver state in the library's static device workspace);
+    returns (flow, energy, surface).  `surface` is an optional (nx, ny) int32
+    output on the volume's GPU; without it one is allocated here (by torch,
+    outside the library call)."""
+    if cost.device.type != "cuda":
+        raise ValueError("cost must be a CUDA tensor")
+    dev = cost.device.index
+    nx, ny, K = (int(v) for v in cost.shape)
+    _dev_i32(cost, (nx, ny, K), "cost", dev)
+    out = _empty((nx, ny), torch.int32, dev) if surface is None else \
+        _dev_i32(surface, (nx, ny), "surface", dev)
+    flow, energy = ctypes.c_int64(), ctypes.c_int64()
+    with torch.cuda.device(dev):
+        _check(_lib.smf_solve_noalloc(cost.data_ptr(), nx, ny, K, int(delta), out.data_ptr(),
+                                      ctypes.byref(flow), ctypes.byref(energy), _stream_ptr(stream, dev)),
+               "smf_solve_noalloc")
+    return flow.value, energy.value, out
