@@ -87,6 +87,17 @@ def _load():
                                              ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P,
                                              ctypes.POINTER(_Cert)]
         lib.certify_preflow_soft.restype = ctypes.c_int
+        lib.band_effective.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, P, P, P, P]
+        lib.band_effective.restype = ctypes.c_int
+        lib.oracle_solve_band.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, P, P, P, P, P, P,
+                                          ctypes.POINTER(_Result)]
+        lib.oracle_solve_band.restype = ctypes.c_int
+        lib.certify_preflow_band.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, P, P, P, P, P, P, P,
+                                             ctypes.POINTER(_Cert)]
+        lib.certify_preflow_band.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -172,5 +183,94 @@ def certify(cost, delta, excess, sink_res, flow_down, flow_lat, surface, alpha=0
                                      *[a.ctypes.data for a in arrs], ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"certify_preflow failed with status {rc}")
+    return Certificate(r.flow, r.cut, r.energy, r.bad_capacity, r.bad_conservation,
+                       r.bad_smooth, r.bad_reach)
+
+
+# ---- narrow-band volumes (Section 3.4) ---------------------------------------
+#
+# Column p holds the heights off[p] .. off[p] + ext[p] - 1 of the volume; the
+# band costs are cost[x, y, j] = cost at height off[x, y] + j for j < ext[x, y]
+# (the array is padded to K >= max ext; padding is not read).  A surface takes
+# one height per column inside its band, |h(p) - h(q)| <= delta for
+# 4-neighbours.  Heights are reported as heights of the volume.
+
+
+def _band_arrays(off, ext, nx, ny):
+    o = np.ascontiguousarray(off, dtype=np.int32)
+    e = np.ascontiguousarray(ext, dtype=np.int32)
+    if o.shape != (nx, ny) or e.shape != (nx, ny):
+        raise ValueError("off and ext must be (nx, ny)")
+    return o, e
+
+
+def band_effective(off, ext, delta: int, K: int | None = None):
+    """(lo, hi): the heights that some delta-smooth surface inside the bands
+    takes in each column, or None when no such surface exists."""
+    o = np.ascontiguousarray(off, dtype=np.int32)
+    nx, ny = o.shape
+    o, e = _band_arrays(off, ext, nx, ny)
+    lo = np.empty((nx, ny), dtype=np.int32)
+    hi = np.empty((nx, ny), dtype=np.int32)
+    rc = _load().band_effective(nx, ny, int(K if K is not None else e.max()), int(delta),
+                                o.ctypes.data, e.ctypes.data, lo.ctypes.data, hi.ctypes.data)
+    if rc < 0:
+        raise ValueError("bad band arguments")
+    return None if rc else (lo, hi)
+
+
+@dataclass
+class BandResult:
+    flow: int          # max-flow value of the band graph (Eq. 5)
+    cut: int           # capacity of its minimal min cut (Eq. 6)
+    energy: int        # E* = sum_p c(p, h_min(p))
+    energy_hmax: int   # sum_p c(p, h_max(p))
+    hmin: np.ndarray   # (nx, ny) heights of the volume, pointwise-lowest optimum
+    hmax: np.ndarray   # (nx, ny) pointwise-highest optimum
+    lo: np.ndarray     # (nx, ny) lowest feasible height per column
+    hi: np.ndarray     # (nx, ny) highest feasible height per column
+    conservation_ok: bool
+    capacity_ok: bool
+    smin_in_smax: bool
+
+
+class NoFeasibleSurface(ValueError):
+    """No delta-smooth surface fits the bands."""
+
+
+def solve_band(cost: np.ndarray, delta: int, off, ext) -> BandResult:
+    c = np.ascontiguousarray(cost, dtype=np.int32)
+    nx, ny, K = c.shape
+    o, e = _band_arrays(off, ext, nx, ny)
+    outs = [np.empty((nx, ny), dtype=np.int32) for _ in range(4)]
+    r = _Result()
+    rc = _load().oracle_solve_band(c.ctypes.data, nx, ny, K, int(delta), o.ctypes.data,
+                                   e.ctypes.data, *[a.ctypes.data for a in outs], ctypes.byref(r))
+    if rc == -3:
+        raise NoFeasibleSurface("no delta-smooth surface fits the bands")
+    if rc != 0:
+        raise RuntimeError(f"oracle_solve_band failed with status {rc}")
+    lo, hi, hmin, hmax = outs
+    return BandResult(r.flow, r.cut, r.energy, r.energy_hmax, hmin, hmax, lo, hi,
+                      bool(r.conservation_ok), bool(r.capacity_ok), bool(r.smin_in_smax))
+
+
+def certify_band(cost, delta, off, ext, excess, sink_res, flow_down, flow_lat,
+                 surface) -> Certificate:
+    """Check a final preflow of a band solve.  The state arrays hold node
+    (p, lo(p) + j) at [x, y, j] (lo from band_effective; slots above hi(p) -
+    lo(p) unused), flow_lat is (4, nx, ny, K) in the order +x, -x, +y, -y;
+    the surface holds heights of the volume."""
+    c = np.ascontiguousarray(cost, dtype=np.int32)
+    nx, ny, K = c.shape
+    o, e = _band_arrays(off, ext, nx, ny)
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in
+            (excess, sink_res, flow_down, flow_lat, surface)]
+    r = _Cert()
+    rc = _load().certify_preflow_band(c.ctypes.data, nx, ny, K, int(delta), o.ctypes.data,
+                                      e.ctypes.data, *[a.ctypes.data for a in arrs],
+                                      ctypes.byref(r))
+    if rc != 0:
+        raise RuntimeError(f"certify_preflow_band failed with status {rc}")
     return Certificate(r.flow, r.cut, r.energy, r.bad_capacity, r.bad_conservation,
                        r.bad_smooth, r.bad_reach)

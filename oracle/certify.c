@@ -199,3 +199,142 @@ int certify_preflow(const int32_t *cost, int32_t nx, int32_t ny, int32_t K, int3
     return certify_preflow_soft(cost, nx, ny, K, delta, 0, excess, sink_res, flow_down, flow_lat,
                                 NULL, surface, out);
 }
+
+/*
+ * Certificate of a narrow-band solve (the band graph of oracle.c,
+ * oracle_solve_band).  The solver keeps the heights lo(p)..hi(p) that some
+ * delta-smooth surface takes in column p (band_effective) and stores node
+ * (p, lo(p) + j) at p*K + j; slots j > hi(p) - lo(p) are unused and must hold
+ * no excess, sink residual or flow.  Its arcs: the down arc (p,j)->(p,j-1)
+ * for j >= 1, and per 4-neighbour q, with sh = delta + lo(q) - lo(p), the
+ * lateral arc (p,j)->(q,j-sh) for j > sh plus (p,0)->(q,0); the omitted
+ * arcs (p,j)->(q,0), 1 <= j <= sh, are implied by (p,j)->(p,0)->(q,0).
+ * The surface is given as heights of the volume.  The checks are those of
+ * certify_preflow_soft, on this arc set.  Returns 0, -1 on bad arguments
+ * (or bands that admit no smooth surface), -2 when memory runs out.
+ */
+int band_effective(int32_t nx, int32_t ny, int32_t K, int32_t delta, const int32_t *off,
+                   const int32_t *ext, int32_t *lo, int32_t *hi);
+
+int certify_preflow_band(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t K_, int32_t delta_,
+                         const int32_t *off, const int32_t *ext, const int32_t *excess,
+                         const int32_t *sink_res, const int32_t *flow_down, const int32_t *flow_lat,
+                         const int32_t *surface, cert_result *out)
+{
+    memset(out, 0, sizeof(*out));
+    const int64_t nx = nx_, ny = ny_, K = K_, delta = delta_, P = nx * ny, N = P * K;
+    if (nx < 1 || ny < 1 || K < 1 || delta < 0) return out->status = -1;
+    int32_t *lo = malloc((size_t)P * sizeof(int32_t)), *hi = malloc((size_t)P * sizeof(int32_t));
+    int64_t *net = calloc((size_t)N, sizeof(int64_t));
+    uint8_t *mark = calloc((size_t)N, 1);
+    int64_t *queue = malloc((size_t)N * sizeof(int64_t));
+    if (!lo || !hi || !net || !mark || !queue) {
+        free(lo); free(hi); free(net); free(mark); free(queue);
+        return out->status = -2;
+    }
+    if (band_effective(nx_, ny_, K_, delta_, off, ext, lo, hi) != 0) {
+        free(lo); free(hi); free(net); free(mark); free(queue);
+        return out->status = -1;
+    }
+    static const int stp[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+    /* neighbour of column p in direction k, or -1 */
+#define NBR(p, k) (((p) / ny + stp[k][0] < 0 || (p) / ny + stp[k][0] >= nx || \
+                    (p) % ny + stp[k][1] < 0 || (p) % ny + stp[k][1] >= ny) ? (int64_t)-1 : \
+                   ((p) / ny + stp[k][0]) * ny + (p) % ny + stp[k][1])
+    /* cost at local slot j of column p */
+#define CST(p, j) ((int64_t)cost[(p) * K + lo[p] - off[p] + (j)])
+    int64_t Bb = INT64_MIN;
+    for (int64_t p = 0; p < P; ++p)
+        if (CST(p, 0) > Bb) Bb = CST(p, 0);
+    Bb = Bb + 1;
+
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t n = hi[p] - lo[p] + 1;
+        for (int64_t j = 0; j < K; ++j) {
+            const int64_t v = p * K + j;
+            const int64_t fdv = flow_down[v];
+            if (j >= n) {   /* unused slot */
+                if (excess[v] != 0 || sink_res[v] != 0 || fdv != 0) out->bad_capacity++;
+                for (int k = 0; k < 4; ++k)
+                    if (flow_lat[(int64_t)k * N + v] != 0) out->bad_capacity++;
+                continue;
+            }
+            if (fdv < 0 || (j == 0 && fdv != 0)) out->bad_capacity++;
+            if (j > 0) { net[v - 1] += fdv; net[v] -= fdv; }
+            for (int k = 0; k < 4; ++k) {
+                const int64_t f = flow_lat[(int64_t)k * N + v];
+                const int64_t q = NBR(p, k);
+                const int64_t sh = q < 0 ? 0 : delta + lo[q] - lo[p];
+                const int64_t jt = j == 0 ? 0 : j - sh;
+                if (q < 0 || (j != 0 && j <= sh) || jt > hi[q] - lo[q]) {
+                    if (f != 0) out->bad_capacity++;
+                    continue;
+                }
+                if (f < 0) out->bad_capacity++;
+                net[v] -= f;
+                net[q * K + jt] += f;
+            }
+        }
+    }
+    for (int64_t p = 0; p < P; ++p)
+        for (int64_t j = 0; j <= hi[p] - lo[p]; ++j) {
+            const int64_t v = p * K + j;
+            const int64_t w = j == 0 ? CST(p, 0) - Bb : CST(p, j) - CST(p, j - 1);
+            const int64_t cap_s = w < 0 ? -w : 0, cap_t = w > 0 ? w : 0, rt = sink_res[v];
+            if (rt < 0 || rt > cap_t) out->bad_capacity++;
+            out->flow += cap_t - rt;
+            if (excess[v] < 0) out->bad_capacity++;
+            if (excess[v] != cap_s - (cap_t - rt) + net[v]) out->bad_conservation++;
+        }
+
+    /* surface: inside the effective band, smooth; its energy and cut */
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t h = surface[p];
+        if (h < lo[p] || h > hi[p]) { out->bad_smooth++; continue; }
+        out->energy += CST(p, h - lo[p]);
+        for (int k = 0; k < 4; ++k) {
+            const int64_t q = NBR(p, k);
+            if (q >= 0 && (surface[q] - h > delta || h - surface[q] > delta)) out->bad_smooth++;
+        }
+        for (int64_t j = 0; j <= hi[p] - lo[p]; ++j) {
+            const int64_t w = j == 0 ? CST(p, 0) - Bb : CST(p, j) - CST(p, j - 1);
+            if (lo[p] + j <= h) { if (w > 0) out->cut += w; }
+            else if (w < 0) out->cut -= w;
+        }
+    }
+
+    /* residual reach from the nodes with excess */
+    int64_t head = 0, tail = 0, sink_hit = 0;
+    for (int64_t p = 0; p < P; ++p)
+        for (int64_t j = 0; j <= hi[p] - lo[p]; ++j)
+            if (excess[p * K + j] > 0) { mark[p * K + j] = 1; queue[tail++] = p * K + j; }
+#define REACH(u) do { if (!mark[u]) { mark[u] = 1; queue[tail++] = (u); } } while (0)
+    while (head < tail) {
+        const int64_t v = queue[head++], p = v / K, j = v % K, n = hi[p] - lo[p] + 1;
+        if (sink_res[v] > 0) sink_hit = 1;
+        if (j > 0) REACH(v - 1);
+        if (j + 1 < n && flow_down[v + 1] > 0) REACH(v + 1);
+        for (int k = 0; k < 4; ++k) {
+            const int64_t q = NBR(p, k);
+            if (q < 0) continue;
+            const int64_t sh = delta + lo[q] - lo[p];          /* arcs p -> q */
+            if (j == 0 || j > sh) REACH(q * K + (j == 0 ? 0 : j - sh));
+            /* q's arc towards p (direction k ^ 1) that lands on (p, j) */
+            const int64_t shq = delta + lo[p] - lo[q];
+            const int64_t jq = j == 0 ? 0 : j + shq;
+            if (jq <= hi[q] - lo[q] && flow_lat[(int64_t)(k ^ 1) * N + q * K + jq] > 0) REACH(q * K + jq);
+        }
+    }
+#undef REACH
+    if (sink_hit) out->bad_reach++;
+    for (int64_t p = 0; p < P; ++p) {
+        int64_t top = -1;
+        for (int64_t j = 0; j <= hi[p] - lo[p]; ++j)
+            if (mark[p * K + j]) top = lo[p] + j;
+        if (top != surface[p]) out->bad_reach++;
+    }
+#undef NBR
+#undef CST
+    free(lo); free(hi); free(net); free(mark); free(queue);
+    return 0;
+}

@@ -27,7 +27,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE_DIR = os.path.join(ROOT, "oracle")
 SOURCES = ("oracle.c", "certify.c")
-PIN_TESTS = os.path.join(ROOT, "tests", "test_oracle.py")
+PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle.py"),
+             os.path.join(ROOT, "tests", "test_oracle_band.py")]
 
 # (name, file, text in the source, its replacement); the text must occur
 # exactly once in that file.
@@ -57,8 +58,8 @@ MUTANTS = [
     ("blocking_flow_keeps_reverse", "oracle.c",
      "g->res[g->rev[a]] += push;", "g->res[g->rev[a]] += 0 * push;"),
     ("flow_total_keeps_last_phase", "oracle.c",
-     "out->flow += blocking_flow(&g, s, t, level, cur, buf);",
-     "out->flow = blocking_flow(&g, s, t, level, cur, buf);"),
+     "out->flow += blocking_flow(g, s, t, level, cur, buf);",
+     "out->flow = blocking_flow(g, s, t, level, cur, buf);"),
     # --- cuts, surfaces and energies (Eq. 6, Theorem 1.1, Eq. 1) -----------
     ("sink_side_search_forward", "oracle.c",
      "if (g->res[g->rev[a]] > 0 && !mark[u])", "if (g->res[a] > 0 && !mark[u])"),
@@ -67,7 +68,7 @@ MUTANTS = [
     ("hmax_from_sink_side", "oracle.c",
      "if (!treach[v]) hi = z;", "if (treach[v]) hi = z;"),
     ("cut_counts_inner_arcs", "oracle.c",
-     "if (g.fwd[a] && !sreach[g.head[a]]) {", "if (g.fwd[a] && sreach[g.head[a]]) {"),
+     "if (g->fwd[a] && !sreach[g->head[a]]) {", "if (g->fwd[a] && sreach[g->head[a]]) {"),
     ("smooth_term_y_pairs_dropped", "oracle.c",
      "if (y + 1 < ny) sum += llabs(a - h[x * ny + y + 1]);",
      "if (y + 1 < ny) sum += 0 * llabs(a - h[x * ny + y + 1]);"),
@@ -105,6 +106,36 @@ MUTANTS = [
      "alpha + flow_soft[(int64_t)k * N + v] - flow_soft[(int64_t)kk * N + u] > 0"),
     ("cert_sink_reach_ignored", "certify.c",
      "if (sink_res[v] > 0) reached_sink = 1;", "if (sink_res[v] < 0) reached_sink = 1;"),
+    # --- narrow-band graphs (Section 3.4) --------------------------------------
+    ("band_lower_rule_wrong_sign", "oracle.c",
+     "if (lo[p] - delta > lo[q]) { lo[q] = lo[p] - delta; changed = 1; }",
+     "if (lo[p] + delta > lo[q]) { lo[q] = lo[p] + delta; changed = 1; }"),
+    ("band_upper_rule_dropped", "oracle.c",
+     "if (hi[q] + delta < hi[p]) { hi[p] = hi[q] + delta; changed = 1; }",
+     "if (0 && hi[q] + delta < hi[p]) { hi[p] = hi[q] + delta; changed = 1; }"),
+    ("band_lateral_head_off_by_one", "oracle.c",
+     "int64_t zq = z - b->delta < b->lo[q] ? b->lo[q] : z - b->delta;",
+     "int64_t zq = z - b->delta + 1 < b->lo[q] ? b->lo[q] : z - b->delta + 1;"),
+    ("band_cost_from_effective_bottom", "oracle.c",
+     "const int32_t *cp = b->cost + p * b->K - b->off[p];",
+     "const int32_t *cp = b->cost + p * b->K - b->lo[p];"),
+    ("band_base_from_band_bottom", "oracle.c",
+     "int64_t c0 = b->cost[p * b->K + b->lo[p] - b->off[p]];",
+     "int64_t c0 = b->cost[p * b->K];"),
+    ("band_hmin_lowest_instead_of_highest", "oracle.c",
+     "if (sreach[v]) hl = z;", "if (sreach[v] && hl < 0) hl = z;"),
+    ("band_energy_wrong_height", "oracle.c",
+     "if (hl >= 0) out->energy += cost[p * K + hl - off[p]];",
+     "if (hl >= 0) out->energy += cost[p * K + hl - lo[p]];"),
+    ("cert_band_shift_reversed", "certify.c",
+     "const int64_t sh = delta + lo[q] - lo[p];          /* arcs p -> q */",
+     "const int64_t sh = delta + lo[p] - lo[q];          /* arcs p -> q */"),
+    ("cert_band_reverse_tail_height", "certify.c",
+     "const int64_t jq = j == 0 ? 0 : j + shq;", "const int64_t jq = j == 0 ? 0 : j + shq + 1;"),
+    ("cert_band_base_offset_dropped", "certify.c", "Bb = Bb + 1;", "Bb = Bb + 0;"),
+    ("cert_band_unused_slots_unchecked", "certify.c",
+     "if (excess[v] != 0 || sink_res[v] != 0 || fdv != 0) out->bad_capacity++;",
+     "if (0) out->bad_capacity++;"),
 ]
 
 # The child process points the oracle package at the given library and runs
@@ -114,7 +145,7 @@ _RUNNER = (
     "import oracle\n"
     "oracle._LIB_PATH = sys.argv[1]\n"
     "import pytest\n"
-    "sys.exit(pytest.main(['-x', '-q', '-p', 'no:cacheprovider', sys.argv[2]]))\n"
+    "sys.exit(pytest.main(['-x', '-q', '-p', 'no:cacheprovider', *sys.argv[2:]]))\n"
 )
 
 
@@ -142,7 +173,7 @@ def _pins_pass(lib):
     """True when every pin test passes against `lib`."""
     env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1")
     try:
-        r = subprocess.run([sys.executable, "-c", _RUNNER, lib, PIN_TESTS], cwd=ROOT, env=env,
+        r = subprocess.run([sys.executable, "-c", _RUNNER, lib, *PIN_TESTS], cwd=ROOT, env=env,
                            capture_output=True, text=True, timeout=300)
     except subprocess.TimeoutExpired:
         return False, "pin tests did not finish within 300 s"
