@@ -13,7 +13,9 @@ in [64, 256], delta in {1, 2, 3}, layered costs with per-volume seeds) once
 as one batch and once as 64 plain solves one after another on the same
 stream, and reports both rates under "batched".  The soft leg solves the
 seismic volume with the soft smoothness term (smooth_weight, default 16)
-and reports under "soft".  Prints one JSON line.  Only one GPU is
+and reports under "soft".  The band leg solves the seismic volume restricted
+to a narrow band of 97 heights per column around a landmark surface and
+reports under "band".  Prints one JSON line.  Only one GPU is
 supported.
 """
 from __future__ import annotations
@@ -75,6 +77,8 @@ def parse():
     ap.add_argument("--workload", choices=("seismic", "mid", "small"), default="seismic",
                     help="plain-leg volume: seismic 512x512x384 (default, the headline), mid "
                          "256x256x256 or small 32x32x64")
+    ap.add_argument("--band-only", action="store_true",
+                    help="only run the narrow-band leg on the seismic volume (prints its JSON object)")
     ap.add_argument("--soft-only", action="store_true",
                     help="only run the soft leg (prints its JSON object)")
     ap.add_argument("--counters-summary", metavar="DIR",
@@ -217,6 +221,42 @@ def soft_leg(args, torch, smf, cost, delta, stream):
     return out
 
 
+def band_leg(args, torch, smf, synth, seismic, stream):
+    """The seismic volume restricted to a narrow band around a landmark
+    surface (Section 3.4): 97 heights per column around the interpolated
+    middle horizon.  Rate in Mvoxels/s of the band's voxels."""
+    progress("band leg")
+    band, off, ext, delta = synth.config_seismic_band(seismic=seismic)
+    c = torch.from_numpy(band).cuda()
+    solver = smf.Solver(*band.shape, delta)
+    solver.set_band(off, ext)
+    if args.relabel_period > 0:
+        solver.set_param("relabel_period", args.relabel_period)
+    solver.solve(c, stream)                       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = 0
+    for _ in range(args.steps):
+        solver.solve(c, stream)
+        sweeps += solver.stat("sweeps")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    flow, energy = solver.flow_value(), solver.energy()
+    solver.close()
+    vox = int(ext.astype("int64").sum())
+    return {
+        "value": round(vox * args.steps / elapsed / 1e6, 3),
+        "unit": "Mvoxels/s",
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "steps": args.steps,
+        "voxels": vox,
+        "sweeps_per_step": sweeps / args.steps,
+        "result": {"flow": flow, "energy": energy},
+        "workload": "seismic 512x512x384 delta=2 restricted to 97 heights per column around the "
+                    "bilinear landmark surface (landmarks every 32 columns) of the middle planted horizon",
+    }
+
+
 def batched_leg(args, torch, smf, synth, stream):
     """Batch of 64 uneven volumes: one batch solve against 64 plain solves."""
     shapes = synth.batch_shapes()
@@ -310,8 +350,17 @@ def main():
         print(json.dumps({"batched": batched_leg(args, torch, smf, synth, torch.cuda.current_stream())}),
               flush=True)
         return
-    cost, delta = {"seismic": synth.config_seismic, "mid": synth.config_mid,
-                   "small": synth.config_small}[args.workload]()
+    seismic = None
+    if args.workload == "seismic":
+        seismic = synth.config_seismic(heights=True)
+        cost, delta = seismic[0], seismic[1]
+    else:
+        cost, delta = {"mid": synth.config_mid, "small": synth.config_small}[args.workload]()
+    if args.band_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"band": band_leg(args, torch, smf, synth, seismic, torch.cuda.current_stream())}),
+              flush=True)
+        return
     if args.soft_only:
         torch.cuda.set_device(0)
         print(json.dumps({"soft": soft_leg(args, torch, smf, cost, delta, torch.cuda.current_stream())}),
@@ -430,6 +479,8 @@ def main():
         out["batched"] = batched_leg(args, torch, smf, synth, stream)
     if args.smooth_weight > 0 and not args.no_batch:
         out["soft"] = soft_leg(args, torch, smf, cost, delta, stream)
+    if seismic is not None and not args.no_batch:
+        out["band"] = band_leg(args, torch, smf, synth, seismic, stream)
     if not args.no_cpu_baseline:
         progress("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(cost, delta, args.cpu_crop)

@@ -162,6 +162,29 @@ int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res
  * Enqueued on `stream`. */
 int smf_export_soft_flows(const smf_handle *h, int32_t *flow_soft_dev, void *stream);
 
+/* Narrow band (Section 3.4: the graph is built only in a band of heights
+ * around the surface that the user's landmarks outline, a stick of heights
+ * above and below it).  For a handle of one volume: column p = x*ny + y
+ * holds only the heights offset_host[p] .. offset_host[p] + extent_host[p]
+ * - 1 of the volume (host arrays of nx*ny int32, read during the call;
+ * offset >= 0, 1 <= extent <= K, offset + extent <= 2^30), and the cost
+ * volume passed to smf_solve then holds, at [x][y][j], the cost at height
+ * offset[p] + j (j < extent[p]; entries beyond are not read).  A surface takes
+ * one height in every column's band with |h(p) - h(q)| <= delta.  The call
+ * finds the heights such surfaces actually take per column, [lo(p), hi(p)]
+ * (the pairwise bounds lo(q) >= lo(p) - delta, hi(p) <= hi(q) + delta at
+ * their fixed point; each bound is attained), and the graph is Section 1.2's
+ * on those heights: B = max_p c(p, lo(p)) + 1, w(p, lo(p)) = c(p, lo(p)) - B,
+ * lateral arcs (p, z) -> (q, max(lo(q), z - delta)).  smf_surface then
+ * returns heights of the volume, smf_energy sum_p c(p, h(p)) and
+ * smf_flow_value the max-flow of that graph; smf_export_state stores node
+ * (p, lo(p) + j) at [x][y][j] (slots above hi(p) - lo(p) unused, all zero).
+ * SMF_ERR_ARG when no delta-smooth surface fits the bands, for a batch of more
+ * than one volume, with a positive smooth_weight, or for bad values;
+ * SMF_ERR_NOMEM if the 12-byte-per-column table cannot be allocated (once
+ * per handle).  NULL for both arrays removes the band. */
+int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *extent_host);
+
 /* Tuning and limits.  Keys:
  *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1,
  *                        default 4;
@@ -222,7 +245,8 @@ int smf_batch_set_param(smf_handle *h, const char *key, const int64_t *values);
  * gap heuristic), "gap_searches", and with kernel_timing on,
  * "time_ns.<class>" (summed event time) and "launches.<class>" for the
  * kernel classes build, bfs_reset, bfs, push, relabel, mincut, finish, and
- * "bytes.<class>": algorithmic bytes of the class over the solve (state words
+ * "band" (1 with a narrow band set), "bytes.<class>": algorithmic bytes of the
+ * class over the solve (state words
  * read or written, each access counted once; counted on the device for the
  * data-dependent classes bfs, push and relabel), and the sizes "volumes",
  * "columns" and "nodes".  For a batch the counters cover the whole batch

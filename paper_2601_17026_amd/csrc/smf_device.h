@@ -94,6 +94,16 @@ struct Geom {
     // relabel phase
     int level_block;
     int sweep_waves;
+    // Narrow band (a single volume): column p holds the heights blo[p] ..
+    // blo[p] + bext[p] - 1 of the volume (the range that smooth surfaces
+    // inside the caller's bands take there) in its node slots 0 .. bext[p]-1;
+    // the slots above are unused (no excess, no arcs, label kInf).  Slot j's
+    // cost is the caller's cost bcs[p] + j of the column.  band = 0: every
+    // column holds the heights 0 .. K-1.
+    int band;
+    const int *blo;
+    const int *bext;
+    const int *bcs;
 };
 constexpr int kMaskFl = 0, kMaskFd = 4, kMasks = 5;
 constexpr int kWorkSlots = 64, kWorkStride = 16;
@@ -150,6 +160,35 @@ __device__ __forceinline__ int lat_tail(int z, int delta, int K)
 {
     int zt = z == 0 ? 0 : z + delta;
     return zt < K ? zt : -1;
+}
+
+// Band geometry of column p: its extent, and per neighbour direction k the
+// height shift sh[k] of its lateral arcs (p, z) -> (q_k, z - sh[k]) (z > sh[k],
+// plus (p,0) -> (q_k,0)), the shift shr[k] of the arcs (q_k, z) -> (p, z -
+// shr[k]) and q_k's extent.  Without a band every shift is delta and every
+// extent K.  q[k] < 0: no neighbour (the values are then unused).
+struct BandCol {
+    int ext;
+    int sh[4], shr[4], qext[4];
+};
+
+__device__ __forceinline__ void band_col(const Geom &g, int p, const int q[4], int K, int delta, BandCol &b)
+{
+    if (!g.band) {
+        b.ext = K;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { b.sh[k] = delta; b.shr[k] = delta; b.qext[k] = K; }
+        return;
+    }
+    const int lo = g.blo[p];
+    b.ext = g.bext[p];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int lq = q[k] >= 0 ? g.blo[q[k]] : lo;
+        b.sh[k] = delta + lq - lo;
+        b.shr[k] = delta + lo - lq;
+        b.qext[k] = q[k] >= 0 ? g.bext[q[k]] : K;
+    }
 }
 
 // Global neighbour column in direction k (0:+x, 1:-x, 2:+y, 3:-y) of global

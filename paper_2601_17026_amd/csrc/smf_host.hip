@@ -48,7 +48,7 @@ void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t s
 void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
-void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, hipStream_t st);
+void launch_finish(const int *cost, const Geom &g, const State &sv, int *H, hipStream_t st);
 }  // namespace smf
 
 using namespace smf;
@@ -186,6 +186,7 @@ struct smf_handle {
     unsigned long long *bits = nullptr;   // kMasks * max_nch * Ptot BFS bit-mask words
     int *soft_flow = nullptr;             // 4 * Ntot soft-arc flows, once some alpha > 0
     unsigned long long *sbits = nullptr;  // 4 * max_nch * Ptot soft-arc masks, likewise
+    int *band_dev = nullptr;              // 3 * Ptot: lowest height, extent, cost shift per column
     unsigned long long *wcount = nullptr; // algorithmic byte counters (Geom::work)
     int *hist = nullptr;                  // n x kHistLen label histograms (Geom::hist)
     unsigned long long *wmask = nullptr;  // 2 * Ptot work masks
@@ -233,7 +234,8 @@ static void release(smf_handle *h)
 {
     if (!h) return;
     void *dev[] = {h->inst_dev, h->col_inst, h->cnt_dev, h->part_dev, h->fill_dev, h->state, h->H,
-                   h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist, h->soft_flow, h->sbits};
+                   h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist, h->soft_flow, h->sbits,
+                   h->band_dev};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     for (int i = 0; i < kSnapSlots; ++i)
@@ -385,6 +387,8 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     g.sweep_waves = 8192;
     g.soft = 0;
     g.sbits = nullptr;
+    g.band = 0;
+    g.blo = g.bext = g.bcs = nullptr;
     h->st.sf = nullptr;
     g.low_act = h->bfs + 10 * P;
     g.short_list = h->bfs + 11 * P;
@@ -859,6 +863,8 @@ static int set_alpha(smf_handle *h, const int64_t *alpha, const char *who)
             return fail(SMF_ERR_ARG, std::string(who) + ": smooth_weight must lie in [0, 2^29]");
     bool any = false;
     for (int i = 0; i < h->n; ++i) any = any || alpha[i] > 0;
+    if (any && h->g.band)
+        return fail(SMF_ERR_ARG, std::string(who) + ": the soft smoothness term is not available with a narrow band");
     if (any && !h->soft_flow) {
         int *sf = nullptr;
         unsigned long long *sb = nullptr;
@@ -874,6 +880,88 @@ static int set_alpha(smf_handle *h, const int64_t *alpha, const char *who)
     h->g.soft = any ? 1 : 0;
     h->g.sbits = h->sbits;
     h->st.sf = h->soft_flow;
+    return SMF_OK;
+}
+
+// Narrow band (Section 3.4): the heights each column can take on a smooth
+// surface inside the caller's bands, from the pairwise bounds lo(q) >=
+// lo(p) - delta and hi(p) <= hi(q) + delta, propagated from a queue of
+// columns until they hold everywhere.  False when some column's range empties.
+static bool band_ranges(const Inst &I, const int32_t *off, const int32_t *ext, std::vector<int> &lo,
+                        std::vector<int> &hi)
+{
+    const int nx = I.nx, ny = I.ny, P = I.P, dl = I.delta;
+    lo.resize((size_t)P);
+    hi.resize((size_t)P);
+    std::vector<int> queue((size_t)P);
+    std::vector<char> queued((size_t)P, 1);
+    for (int p = 0; p < P; ++p) {
+        lo[p] = off[p];
+        hi[p] = off[p] + ext[p] - 1;
+        queue[p] = p;
+    }
+    size_t head = 0, count = (size_t)P;   // ring buffer of queued columns
+    while (count) {
+        const int p = queue[head];
+        head = (head + 1) % (size_t)P;
+        --count;
+        queued[p] = 0;
+        const int x = p / ny, y = p % ny;
+        const int nb[4] = {x + 1 < nx ? p + ny : -1, x > 0 ? p - ny : -1, y + 1 < ny ? p + 1 : -1,
+                           y > 0 ? p - 1 : -1};
+        for (int q : nb) {
+            if (q < 0) continue;
+            bool moved = false;
+            if (lo[p] - dl > lo[q]) { lo[q] = lo[p] - dl; moved = true; }
+            if (hi[p] + dl < hi[q]) { hi[q] = hi[p] + dl; moved = true; }
+            if (!moved) continue;
+            if (lo[q] > hi[q]) return false;
+            if (!queued[q]) {
+                queue[(head + count) % (size_t)P] = q;
+                ++count;
+                queued[q] = 1;
+            }
+        }
+    }
+    return true;
+}
+
+extern "C" int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *extent_host)
+{
+    if (!h) return fail(SMF_ERR_ARG, "smf_set_band: NULL handle");
+    if (!offset_host && !extent_host) {
+        h->g.band = 0;
+        return SMF_OK;
+    }
+    if (!offset_host || !extent_host) return fail(SMF_ERR_ARG, "smf_set_band: NULL offsets or extents");
+    if (h->n != 1) return fail(SMF_ERR_ARG, "smf_set_band: a band needs a handle of one volume");
+    if (h->inst[0].alpha > 0)
+        return fail(SMF_ERR_ARG, "smf_set_band: the soft smoothness term is not available with a narrow band");
+    const Inst &I = h->inst[0];
+    for (int p = 0; p < I.P; ++p)
+        if (offset_host[p] < 0 || extent_host[p] < 1 || extent_host[p] > I.K ||
+            (long long)offset_host[p] + extent_host[p] > (1LL << 30))
+            return fail(SMF_ERR_ARG, "smf_set_band: need offset >= 0, 1 <= extent <= K and offset + extent "
+                                     "<= 2^30 in every column");
+    std::vector<int> lo, hi;
+    if (!band_ranges(I, offset_host, extent_host, lo, hi))
+        return fail(SMF_ERR_ARG, "smf_set_band: no delta-smooth surface fits the bands");
+    const size_t P = (size_t)I.P;
+    std::vector<int> up(3 * P);
+    for (size_t p = 0; p < P; ++p) {
+        up[p] = lo[p];
+        up[P + p] = hi[p] - lo[p] + 1;
+        up[2 * P + p] = lo[p] - offset_host[p];
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    if (!h->band_dev && !dev_alloc(h->band_dev, 3 * P))
+        return fail(SMF_ERR_NOMEM, "smf_set_band: allocation of the band table failed");
+    HIP_TRY(hipMemcpy(h->band_dev, up.data(), sizeof(int) * 3 * P, hipMemcpyHostToDevice));
+    h->g.band = 1;
+    h->g.blo = h->band_dev;
+    h->g.bext = h->band_dev + P;
+    h->g.bcs = h->band_dev + 2 * P;
+    h->solved = false;
     return SMF_OK;
 }
 
@@ -984,6 +1072,7 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
     else if (!strcmp(key, "volumes")) *out = h->n;
     else if (!strcmp(key, "columns")) *out = h->g.Ptot;
     else if (!strcmp(key, "nodes")) *out = h->g.Ntot;
+    else if (!strcmp(key, "band")) *out = h->g.band;
     else if (!strncmp(key, "bytes.", 6)) {
         // algorithmic bytes of the last solve per kernel class: counted on the
         // device for the data-dependent kernels, by formula for the others

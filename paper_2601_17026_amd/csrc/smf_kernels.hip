@@ -461,7 +461,7 @@ __global__ void k_bottom_max(const int *__restrict__ cost, Geom g)
     if (p < g.Ptot) {
         const Col c = column(g, p);
         ii = c.ii;
-        v = cost[(size_t)c.I.cost_base + (size_t)c.pl * c.I.K];
+        v = cost[(size_t)c.I.cost_base + (size_t)c.pl * c.I.K + (g.band ? g.bcs[p] : 0)];
     }
     bool pending = ii >= 0;
     for (;;) {
@@ -493,17 +493,29 @@ __global__ __launch_bounds__(256) void k_build(const int *__restrict__ cost, Geo
         ts_sum.to(c.ii);
         const int K = c.I.K;
         const int B = g.is[c.ii].bmax + 1;
-        const size_t cb0 = (size_t)c.I.cost_base + (size_t)c.pl * K;
+        const int ext = g.band ? g.bext[p] : K;   // node slots the column uses
+        const size_t cb0 = (size_t)c.I.cost_base + (size_t)c.pl * K + (g.band ? g.bcs[p] : 0);
         for (int ch = 0; ch < c.I.nch; ++ch) {
             const int z = ch * kWave + lane;
             const bool in = z < K;
-            const int cv = in ? cost[cb0 + z] : 0;
+            const bool live = z < ext;
+            const int cv = live ? cost[cb0 + z] : 0;
             const int up = __shfl_up(cv, 1, kWave);
-            const int cbelow = z == 0 ? B : (lane == 0 ? (in ? cost[cb0 + z - 1] : 0) : up);
+            const int cbelow = z == 0 ? B : (lane == 0 ? (live ? cost[cb0 + z - 1] : 0) : up);
             if (!in) continue;
+            const size_t v = c.base + z;
+            if (!live) {
+                // an unused slot above the column's band: no excess, no arcs
+                st.e[v] = 0;
+                st.ts[v] = 0;
+                st.d[v] = kInf;
+                st.fd[v] = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) st.fl[(size_t)k * g.Ntot + v] = 0;
+                continue;
+            }
             if (cv <= -(1 << 30) || cv >= (1 << 30)) bad = 1;
             const int w = cv - cbelow;
-            const size_t v = c.base + z;
             st.e[v] = w < 0 ? -w : 0;
             st.ts[v] = w > 0 ? w : 0;
             ts_sum.acc += w > 0 ? w : 0;
@@ -608,7 +620,8 @@ __device__ __forceinline__ ChunkIn load_chunk(const State &st, size_t v, int z, 
 // (its reverse residual arcs).  Loaded only for lanes that need them; the
 // words of a chunk are 64 consecutive heights of the neighbour column.
 // Node (q, 0) of neighbour k lies dq[k] words from the column's node (p, 0)
-// at `base` (has[k] false: no neighbour).
+// at `base` (has[k] false: no neighbour); the arcs' heights follow the
+// column's band geometry bc.
 struct Lateral {
     int d_fwd[4];   // label of (q, zh) (kInf: no arc)
     int f_rev[4];   // flow on (q, zt) -> (p, z) (0: no arc)
@@ -616,15 +629,15 @@ struct Lateral {
 };
 
 __device__ __forceinline__ void load_lateral(Lateral &l, const State &st, size_t base,
-                                             const int dq[4], const bool has[4], int z, int K,
-                                             size_t Ntot, int dl, bool need)
+                                             const int dq[4], const bool has[4], const BandCol &bc,
+                                             int z, size_t Ntot, bool need)
 {
-    const bool fwd = need && lat_arc(z, dl);
-    const int zh = lat_head(z, dl);
-    const int zt = lat_tail(z, dl, K);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        l.d_fwd[k] = (fwd && has[k]) ? st.d[base + (ptrdiff_t)(dq[k] + zh)] : kInf;
+        const bool fwd = need && has[k] && lat_arc(z, bc.sh[k]);
+        const int zh = lat_head(z, bc.sh[k]);
+        const int zt = lat_tail(z, bc.shr[k], bc.qext[k]);
+        l.d_fwd[k] = fwd ? st.d[base + (ptrdiff_t)(dq[k] + zh)] : kInf;
         const bool rev = need && has[k] && zt >= 0;
         const size_t w = base + (ptrdiff_t)(rev ? dq[k] + zt : 0);
         l.f_rev[k] = rev ? st.fl[(size_t)(k ^ 1) * Ntot + w] : 0;
@@ -719,10 +732,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             cur_ii = ii;
         }
         const Col col = column_in(cur, ii, p);
-        const int K = col.I.K, dl = col.I.delta, nch = col.I.nch, cpb = col.I.cpb;
+        const int nch = col.I.nch, cpb = col.I.cpb;
         int q[4], dq[4];
         bool has[4];
         neighbours(col, p, q, dq, has);
+        BandCol bc;
+        band_col(g, p, q, col.I.K, col.I.delta, bc);
+        const int K = bc.ext;   // node slots of the column
         const size_t base = col.base;
         const int gtop = 63 - __clzll(m), glow = __ffsll((long long)m) - 1;
         const int ctop = min(nch - 1, gtop * cpb + cpb - 1), clow = glow * cpb;
@@ -800,7 +816,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const bool need = rem > 0;
             if (__ballot(need)) {
                 Lateral lt;
-                load_lateral(lt, st, base, dq, has, z, K, Ntot, dl, need);
+                load_lateral(lt, st, base, dq, has, bc, z, Ntot, need);
                 bytes += need ? 64 : 0;
                 SoftLat sl;
                 if constexpr (kSoft) {
@@ -810,11 +826,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 int fown[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    fown[k] = (need && has[k] && lat_arc(z, dl)) ? st.fl[(size_t)k * Ntot + v] : 0;
-                const int zt = lat_tail(z, dl, K), zh = lat_head(z, dl);
+                    fown[k] = (need && has[k] && lat_arc(z, bc.sh[k])) ? st.fl[(size_t)k * Ntot + v] : 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const bool go = rem > 0 && lt.f_rev[k] > 0 && lt.d_rev[k] + 1 == dv;
+                    const int zt = lat_tail(z, bc.shr[k], bc.qext[k]);
                     if (go) {
                         const long long a = min(rem, (long long)lt.f_rev[k]);
                         const size_t w = base + (ptrdiff_t)(dq[k] + zt);
@@ -849,6 +865,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (fwd_k < 0 && rem > 0 && lt.d_fwd[k] + 1 == dv) fwd_k = k;
+                const int zh = fwd_k >= 0 ? lat_head(z, bc.sh[fwd_k]) : 0;
                 if (fwd_k >= 0) {
                     const size_t w = base + (ptrdiff_t)(dq[fwd_k] + zh);
                     st.fl[(size_t)fwd_k * Ntot + v] = add_flow(fown[fwd_k], rem, err);
@@ -936,12 +953,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             cur_ii = ii;
         }
         const Col col = column_in(cur, ii, p);
-        const int K = col.I.K, dl = col.I.delta, nch = col.I.nch, cpb = col.I.cpb;
+        const int nch = col.I.nch, cpb = col.I.cpb;
         cnt.to(col.ii);
         frozen.to(col.ii);
         int q[4], dq[4];
         bool has[4];
         neighbours(col, p, q, dq, has);
+        BandCol bc;
+        band_col(g, p, q, col.I.K, col.I.delta, bc);
+        const int K = bc.ext;   // node slots of the column
         const size_t base = col.base;
         unsigned long long nm = 0;
         for (int c = 0; c < nch; ++c) {
@@ -962,7 +982,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             }
             if (!__ballot(act)) continue;
             Lateral lt;
-            load_lateral(lt, st, base, dq, has, z, K, Ntot, dl, act);
+            load_lateral(lt, st, base, dq, has, bc, z, Ntot, act);
             bytes += act ? 48 : 0;
             SoftLat sl;
             if constexpr (kSoft) {
@@ -1132,23 +1152,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             continue;
         }
         act.to(vc.ii);
-        const int K = vc.I.K, nch = vc.I.nch;
+        // slots used (Kc) and the volume's K, which also marks "no arc" in lf
+        const int K = vc.I.K, nch = vc.I.nch, Kc = g.band ? g.bext[p] : K;
         const size_t base = vc.base(p);
-        int t1 = K, la = K;
+        int t1 = Kc, la = Kc;
         int lf[4] = {K, K, K, K};
         for (int cg = 0; cg < nch; cg += kInitGroup) {
             InitWords w[kInitGroup];
 #pragma unroll
             for (int j = 0; j < kInitGroup; ++j) {
                 const int z = (cg + j) * kWave + lane;
-                load_init_words(st, Ntot, base + z, z < K, w[j]);
+                load_init_words(st, Ntot, base + z, z < Kc, w[j]);
             }
 #pragma unroll
             for (int j = 0; j < kInitGroup; ++j) {
                 const int c = cg + j;
                 if (c >= nch) break;
                 const int z = c * kWave + lane;
-                const bool in = z < K;
+                const bool in = z < Kc;
                 // the chunk's words of the bit masks, one mask per lane 0..5
                 unsigned long long wm[kMasks];
 #pragma unroll
@@ -1159,7 +1180,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 for (int m = 0; m < kMasks; ++m)
                     if (lane == m) mine = wm[m];
                 if (lane < kMasks) g.bits[((size_t)lane * g.max_nch + c) * Ptot + p] = mine;
-                if (t1 == K) {
+                if (t1 == Kc) {
                     const unsigned long long sm = __ballot(in && w[j].ts > 0);
                     if (sm) t1 = c * kWave + __ffsll((long long)sm) - 1;
                 }
@@ -1168,7 +1189,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 if (in) st.d[base + z] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
                 const bool isact = in && w[j].e > 0 && dv < kInf;
                 if (isact) ++act.acc;
-                if (la == K) {
+                if (la == Kc) {
                     const unsigned long long am = __ballot(isact);
                     if (am) la = c * kWave + __ffsll((long long)am) - 1;
                 }
@@ -1252,13 +1273,14 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
 
 // One level for one column: the new threshold cand from the column's
 // threshold T and its neighbours' thresholds tq[k] (-1: no neighbour in
-// direction k) and lowest flow-carrying arcs into the column lq[k]; lf[]
+// direction k) and lowest flow-carrying arcs into the column lq[k] (K: none;
+// arc heights and the column's extent from bc); lf[]
 // (the column's lowest flow-carrying lateral arc per direction at or above
 // its threshold) is lowered over the newly reached heights [cand, T) from
 // the bit masks.  Returns the mask words read.
 template <bool kSoft>
-__device__ __forceinline__ int level_update(const Geom &g, int p, int K, int dl, int alpha, int T,
-                                           const int tq[4], const int lq[4], int lf[4], int &cand)
+__device__ __forceinline__ int level_update(const Geom &g, int p, int K, const BandCol &bc, int alpha,
+                                           int T, const int tq[4], const int lq[4], int lf[4], int &cand)
 {
     cand = T;
     int words = 0;
@@ -1266,8 +1288,8 @@ __device__ __forceinline__ int level_update(const Geom &g, int p, int K, int dl,
     for (int k = 0; k < 4; ++k) {
         if (tq[k] < 0) continue;
         if (tq[k] == 0) cand = 0;
-        else if (tq[k] + dl < K) cand = min(cand, tq[k] + dl);
-        if (lq[k] < K) cand = min(cand, lat_head_of(lq[k], dl));
+        else if (tq[k] + bc.sh[k] < bc.ext) cand = min(cand, tq[k] + bc.sh[k]);
+        if (lq[k] < K) cand = min(cand, lat_head_of(lq[k], bc.shr[k]));
     }
     if constexpr (kSoft) {
         // soft arcs (p,z) -> (q,z): the lowest z >= T(q) (z >= 1) whose arc
@@ -1289,7 +1311,7 @@ __device__ __forceinline__ int level_update(const Geom &g, int p, int K, int dl,
             }
         }
     }
-    if (T >= 1 && T < K) {
+    if (T >= 1 && T < bc.ext) {
         ++words;
         if ((mask_word(g, kMaskFd, T >> 6, p) >> (T & 63)) & 1ULL) cand = min(cand, T - 1);
     }
@@ -1386,7 +1408,7 @@ __device__ __forceinline__ bool column_step(const Geom &g, const Col &col, int p
                                             const int *LFin, int P, int &T, int &cand, int lf[4],
                                             bool &self, long long &bytes)
 {
-    const int K = col.I.K, dl = col.I.delta;
+    const int K = col.I.K;
     int q[4], tq[4];
     const int tw = Tin[p];
     self = tw < 0;
@@ -1408,7 +1430,9 @@ __device__ __forceinline__ bool column_step(const Geom &g, const Col &col, int p
         lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
         lf[k] = LFin[(size_t)k * P + p];
     }
-    bytes += 16 + 8 * level_update<kSoft>(g, p, K, dl, col.I.alpha, T, tq, lq, lf, cand);
+    BandCol bc;
+    band_col(g, p, q, K, col.I.delta, bc);
+    bytes += 16 + 8 * level_update<kSoft>(g, p, K, bc, col.I.alpha, T, tq, lq, lf, cand);
     return cand < T;
 }
 
@@ -1604,22 +1628,27 @@ __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, S
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= g.Ptot) return;
     const Col col = column(g, p);
-    const int K = col.I.K, dl = col.I.delta;
+    const int K = col.I.K;
     const size_t Ntot = (size_t)g.Ntot;
     const size_t base = col.base;
     const int h0 = H[p];
     int h = h0;
+    int qn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qn[k] = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
+    BandCol bc;
+    band_col(g, p, qn, K, col.I.delta, bc);
     for (int k = 0; k < 4; ++k) {
-        const int qq = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
+        const int qq = qn[k];
         if (qq < 0) continue;
         const int hq = H[qq];
         if (hq < 0) continue;
-        // forward lateral arcs of q's reached prefix land at heights <= hq - delta (or 0)
-        h = max(h, hq > dl ? hq - dl : 0);
+        // forward lateral arcs of q's reached prefix land at heights <= hq - shr (or 0)
+        h = max(h, hq > bc.shr[k] ? hq - bc.shr[k] : 0);
         // reverse residual of p's own lateral arcs into q's reached prefix
-        const int top = min(K - 1, hq + dl);
+        const int top = min(bc.ext - 1, hq + bc.sh[k]);
         for (int z = top; z > h; --z) {
-            if (lat_arc(z, dl) && st.fl[(size_t)k * Ntot + base + z] > 0) {
+            if (lat_arc(z, bc.sh[k]) && st.fl[(size_t)k * Ntot + base + z] > 0) {
                 h = z;
                 break;
             }
@@ -1640,7 +1669,7 @@ __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, S
         }
     }
     // reverse residual of down arcs with flow: (p,h) -> (p,h+1)
-    while (h >= 0 && h + 1 < K && st.fd[base + h + 1] > 0) ++h;
+    while (h >= 0 && h + 1 < bc.ext && st.fd[base + h + 1] > 0) ++h;
     if (h != h0) {
         H[p] = h;
         s->changed = 1;
@@ -1654,7 +1683,7 @@ __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, S
 // column.
 template <bool kSoft>
 __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Geom g, State st,
-                                                const int *H)
+                                                int *H)
 {
     const int lane = lane_id();
     int lo, hi;
@@ -1670,7 +1699,11 @@ __global__ __launch_bounds__(256) void k_finish(const int *__restrict__ cost, Ge
         }
         if (lane == 0) {
             const int h = H[p];
-            if (h >= 0) energy.acc += cost[(size_t)col.I.cost_base + (size_t)col.pl * col.I.K + h];
+            const int cs = g.band ? g.bcs[p] : 0;   // cost index of the column's slot 0
+            if (h >= 0) energy.acc += cost[(size_t)col.I.cost_base + (size_t)col.pl * col.I.K + cs + h];
+            // a band column's surface is reported as a height of the volume
+            // (no later pass reads H; soft smoothness never runs with a band)
+            if (g.band && h >= 0) H[p] = h + g.blo[p];
             if constexpr (kSoft) {
                 if (col.I.alpha > 0)
                     for (int k = 0; k < 4; k += 2) {   // +x, +y
@@ -1870,7 +1903,7 @@ void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipS
     else hipLaunchKernelGGL(k_mincut_pass<false>, dim3(blocks_for(g.Ptot)), dim3(256), 0, st, g, sv, H, s);
 }
 
-void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, hipStream_t st)
+void launch_finish(const int *cost, const Geom &g, const State &sv, int *H, hipStream_t st)
 {
     if (g.soft) hipLaunchKernelGGL(k_finish<true>, dim3(wave_blocks(g)), dim3(256), 0, st, cost, g, sv, H);
     else hipLaunchKernelGGL(k_finish<false>, dim3(wave_blocks(g)), dim3(256), 0, st, cost, g, sv, H);

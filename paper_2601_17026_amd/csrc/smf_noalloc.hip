@@ -48,7 +48,7 @@ void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work 
 void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
-void launch_finish(const int *cost, const Geom &g, const State &sv, const int *H, hipStream_t st);
+void launch_finish(const int *cost, const Geom &g, const State &sv, int *H, hipStream_t st);
 int set_error_text(int code, const char *msg);
 }  // namespace smf
 

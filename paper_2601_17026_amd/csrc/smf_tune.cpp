@@ -145,6 +145,10 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
 {
     smf::clear_error();
     if (!h || !packed_cost_dev) return smf::set_error(SMF_ERR_ARG, "smf_autotune: NULL handle or cost");
+    int64_t band = 0;
+    if (smf_get_stat(h, "band", &band) == SMF_OK && band)
+        return smf::set_error(SMF_ERR_ARG, "smf_autotune: the tuner times full-height volumes; a handle "
+                                           "with a narrow band keeps its relabel period");
     std::vector<int64_t> s[5];
     int rc = shapes_of(h, s);
     if (rc) return rc;

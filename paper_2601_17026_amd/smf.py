@@ -65,6 +65,8 @@ _lib.smf_tune_cache_load.argtypes = [ctypes.c_char_p]
 _lib.smf_tune_cache_save.argtypes = [ctypes.c_char_p]
 _lib.smf_tune_cache_clear.argtypes = []
 _lib.smf_tune_lookup.argtypes = [_I32, _I32, _I32, _I32, _PI64]
+_lib.smf_set_band.argtypes = [_P, _P, _P]
+_lib.smf_set_band.restype = ctypes.c_int
 _lib.smf_solve_noalloc.argtypes = [_P, _I32, _I32, _I32, _I32, _P, _PI64, _PI64, _P]
 _lib.smf_solve_noalloc.restype = ctypes.c_int
 NOALLOC_MAX_BYTES = 64 << 20   # SMF_NOALLOC_MAX_BYTES
@@ -86,7 +88,7 @@ EXPORTED = ("smf_create", "smf_destroy", "smf_solve", "smf_flow_value", "smf_ene
             "smf_batch_energies", "smf_batch_surfaces", "smf_batch_set_param",
             "smf_batch_get_stat", "smf_autotune", "smf_tune_apply", "smf_tune_cache_load",
             "smf_tune_cache_save", "smf_tune_cache_clear", "smf_tune_lookup",
-            "smf_solve_noalloc")
+            "smf_solve_noalloc", "smf_set_band")
 
 
 class SmfError(RuntimeError):
@@ -202,6 +204,22 @@ class Solver:
         _dev_i32(out, (nx, ny), "out", self.device)
         _check(_lib.smf_surface(self._h, out.data_ptr(), _stream_ptr(stream, self.device)), "smf_surface")
         return out
+
+    def set_band(self, offset, extent) -> None:
+        """Narrow band: column (x, y) holds the heights offset[x, y] ..
+        offset[x, y] + extent[x, y] - 1 of the volume (host arrays of shape
+        (nx, ny)); the costs passed to solve() then hold, at [x, y, j], the
+        cost at height offset[x, y] + j.  None, None removes the band."""
+        if offset is None and extent is None:
+            _check(_lib.smf_set_band(self._h, None, None), "smf_set_band")
+            return
+        import numpy as np
+        nx, ny, _ = self.shape
+        o = np.ascontiguousarray(np.asarray(offset), dtype=np.int32)
+        e = np.ascontiguousarray(np.asarray(extent), dtype=np.int32)
+        if o.shape != (nx, ny) or e.shape != (nx, ny):
+            raise ValueError(f"offset and extent must have shape {(nx, ny)}")
+        _check(_lib.smf_set_band(self._h, o.ctypes.data, e.ctypes.data), "smf_set_band")
 
     def export_state(self, stream=None):
         """Final preflow as (excess, sink_res, flow_down, flow_lat) device tensors."""

@@ -92,13 +92,14 @@ def layered_intensity(nx, ny, K, nsurf, sigma, seed):
     return I, hs
 
 
-def layered_cost(nx, ny, K, nsurf, sigma, cmax, fault, seed):
+def layered_cost(nx, ny, K, nsurf, sigma, cmax, fault, seed, heights=False):
     """int32 cost c[x, y, z] in [0, cmax], low where the intensity jumps.
 
     D(z) = |I(z) - I(z-1)| (D(0) = 0); c = rint(cmax (1 - D / max D)).
     A fraction `fault` of the columns is replaced by iid U{0..cmax} costs.
+    heights=True also returns the planted heights (lowest first).
     """
-    I, _ = layered_intensity(nx, ny, K, nsurf, sigma, seed)
+    I, hs = layered_intensity(nx, ny, K, nsurf, sigma, seed)
     D = np.zeros_like(I)
     np.abs(I[:, :, 1:] - I[:, :, :-1], out=D[:, :, 1:])
     del I
@@ -115,7 +116,8 @@ def layered_cost(nx, ny, K, nsurf, sigma, cmax, fault, seed):
         cols = int(mask.sum())
         if cols:
             c[mask] = frng.integers(0, cmax + 1, size=(cols, K), dtype=np.int32)
-    return np.ascontiguousarray(c)
+    c = np.ascontiguousarray(c)
+    return (c, hs) if heights else c
 
 
 def random_cost(nx, ny, K, lo, hi, seed):
@@ -136,9 +138,13 @@ def config_mid(seed=2):
     return layered_cost(256, 256, 256, 2, 0.5, 255, 0.0, seed), 1
 
 
-def config_seismic(seed=3):
+def config_seismic(seed=3, heights=False):
     """512x512 columns x K=384, delta=2, five nested surfaces, sigma 0.4,
-    costs in [0, 1023], 10% of columns uniformly random (faults)."""
+    costs in [0, 1023], 10% of columns uniformly random (faults).
+    heights=True: (cost, delta, planted heights)."""
+    if heights:
+        c, hs = layered_cost(512, 512, 384, 5, 0.4, 1023, 0.10, seed, heights=True)
+        return c, 2, hs
     return layered_cost(512, 512, 384, 5, 0.4, 1023, 0.10, seed), 2
 
 
@@ -179,3 +185,54 @@ def diff_costs(batch=8, n=128, K=128, seed0=5001, net_seed=5000, device="cuda"):
 
 def sha256(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+# ---- narrow bands around landmarks (Section 3.4) ------------------------------
+#
+# The user marks landmark points on the horizon; the graph covers a stick of
+# heights above and below the surface they outline.  Here the landmarks are
+# the planted horizon's heights on a coarse grid of columns, the outlined
+# surface is their bilinear interpolation, and every column holds
+# 2 * stick + 1 heights centred on it (fewer where the volume ends).
+
+
+def landmark_reference(h: np.ndarray, step: int) -> np.ndarray:
+    """Bilinear interpolation of h sampled every `step` columns in x and y
+    (the last row and column always sampled), rounded to heights."""
+    nx, ny = h.shape
+    xs = sorted(set(list(range(0, nx, step)) + [nx - 1]))
+    ys = sorted(set(list(range(0, ny, step)) + [ny - 1]))
+    marks = h[np.ix_(xs, ys)].astype(np.float64)
+    out = np.empty((nx, ny), dtype=np.float64)
+    for x in range(nx):
+        i = max(0, min(len(xs) - 2, int(np.searchsorted(xs, x, side="right")) - 1)) if len(xs) > 1 else 0
+        tx = 0.0 if len(xs) == 1 else (x - xs[i]) / (xs[i + 1] - xs[i])
+        row = marks[i] if len(xs) == 1 else (1 - tx) * marks[i] + tx * marks[i + 1]
+        out[x] = np.interp(np.arange(ny), ys, row)
+    return np.rint(out).astype(np.int64)
+
+
+def band_from_reference(cost: np.ndarray, ref: np.ndarray, stick: int):
+    """(band costs [nx][ny][2 stick + 1], offsets, extents): column (x, y)
+    holds the heights off .. off + ext - 1 around ref(x, y), clipped to the
+    volume; band[x, y, j] = cost[x, y, off + j] (padding beyond ext: 0)."""
+    nx, ny, K = cost.shape
+    width = 2 * stick + 1
+    off = np.clip(ref - stick, 0, K - 1).astype(np.int32)
+    ext = np.minimum(ref + stick + 1, K).astype(np.int64) - off
+    ext = np.clip(ext, 1, width).astype(np.int32)
+    band = np.zeros((nx, ny, width), dtype=np.int32)
+    for x in range(nx):
+        for y in range(ny):
+            band[x, y, :ext[x, y]] = cost[x, y, off[x, y]:off[x, y] + ext[x, y]]
+    return band, off, ext
+
+
+def config_seismic_band(seed=3, stick=48, step=32, horizon=2, seismic=None):
+    """The seismic volume (512 x 512 x 384, delta = 2) restricted to a band of
+    2 * stick + 1 heights around the landmark surface of planted horizon
+    `horizon` (landmarks every `step` columns).  `seismic`: the (cost,
+    delta, heights) of config_seismic(heights=True) if already made."""
+    cost, delta, hs = seismic if seismic is not None else config_seismic(seed, heights=True)
+    band, off, ext = band_from_reference(cost, landmark_reference(hs[horizon], step), stick)
+    return band, off, ext, delta

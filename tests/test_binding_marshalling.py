@@ -261,3 +261,28 @@ def test_module_solve_and_autograd_handles_use_the_volume_gpu(fake):
     assert s1.device == 1 and autograd._solver(1, 2, 3, 4, 5, 1) is s1
     s0 = autograd._solver(0, 2, 3, 4, 5, 1)
     assert s0.device == 0 and s0 is not s1
+
+
+def test_band_and_noalloc_marshalling(fake):
+    s = smf.Solver(3, 2, 10, 1)
+    off = np.arange(6).reshape(3, 2)
+    s.set_band(off, np.full((3, 2), 4))
+    name, args = fake.calls[-1]
+    assert name == "smf_set_band" and args[0] == s._h and args[1] and args[2]
+    s.set_band(None, None)
+    assert fake.last("smf_set_band") == (s._h, None, None)
+    n = len(fake.calls)
+    with pytest.raises(ValueError):
+        s.set_band(np.zeros((2, 3)), np.ones((2, 3)))
+    assert len(fake.calls) == n
+    s.close()
+
+    cost = FakeTensor((3, 2, 10))
+    flow, energy, surf = smf.solve_noalloc(cost, 1)
+    args = fake.last("smf_solve_noalloc")
+    assert args[:6] == (cost.data_ptr(), 3, 2, 10, 1, surf.data_ptr()) and args[8] == 0xA00
+    assert (surf.shape, surf.dtype) == ((3, 2), torch.int32)
+    mine = FakeTensor((3, 2))
+    assert smf.solve_noalloc(cost, 1, surface=mine)[2] is mine
+    with pytest.raises(ValueError):
+        smf.solve_noalloc(FakeTensor((3, 2, 10), dtype=torch.float32), 1)
