@@ -15,7 +15,9 @@ stream, and reports both rates under "batched".  The soft leg solves the
 seismic volume with the soft smoothness term (smooth_weight, default 16)
 and reports under "soft".  The band leg solves the seismic volume restricted
 to a narrow band of 97 heights per column around a landmark surface and
-reports under "band".  Prints one JSON line.  Only one GPU is
+reports under "band"; the differentiable leg times forward and backward of
+the 8 x 128^3 conv-net workload under "differentiable".  Prints one JSON
+line.  Only one GPU is
 supported.
 """
 from __future__ import annotations
@@ -77,6 +79,8 @@ def parse():
     ap.add_argument("--workload", choices=("seismic", "mid", "small"), default="seismic",
                     help="plain-leg volume: seismic 512x512x384 (default, the headline), mid "
                          "256x256x256 or small 32x32x64")
+    ap.add_argument("--diff-only", action="store_true",
+                    help="only run the differentiable leg, 8 x 128^3 forward and backward")
     ap.add_argument("--band-only", action="store_true",
                     help="only run the narrow-band leg on the seismic volume (prints its JSON object)")
     ap.add_argument("--soft-only", action="store_true",
@@ -257,6 +261,58 @@ def band_leg(args, torch, smf, synth, seismic, stream):
     }
 
 
+def diff_leg(args, torch, smf, synth):
+    """The differentiable workload: 8 volumes of 128^3, delta 2, costs from
+    the conv net on the noisy layered intensity (x16 quantised); one step is
+    the forward (batched exact solve) and the backward (one-hot scatter).
+    The backward kernel is also timed alone with events on torch's current
+    stream (the stream it runs on): 4 bytes written per voxel."""
+    from paper_2601_17026_amd import autograd as ag
+
+    progress("differentiable leg")
+    cost, _, _ = synth.diff_costs(batch=8, n=128, K=128, device="cuda")
+    c = cost.clone().requires_grad_(True)
+    gE = torch.linspace(0.5, 2.0, 8, device="cuda")
+    E, h = ag.surface_energy(c, 2)               # warm-up
+    (E * gE).sum().backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c.grad = None
+        E, h = ag.surface_energy(c, 2)
+        (E * gE).sum().backward()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    vox = c.numel()
+    out = torch.empty_like(cost)
+    hh = h.detach().contiguous()
+    for _ in range(3):
+        smf.onehot_backward(hh, gE, 128, out=out)
+    reps = 50
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        smf.onehot_backward(hh, gE, 128, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * ev0.elapsed_time(ev1) / reps
+    alg = 4 * vox + 4 * hh.numel()               # the gradient written, the surfaces read
+    achieved = alg / (us * 1e3)                  # bytes/ns = GB/s
+    return {
+        "value": round(vox * args.steps / elapsed / 1e6, 3),
+        "unit": "Mvoxels/s",
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "steps": args.steps,
+        "voxels": vox,
+        "backward": {"kernel": "k_onehot_backward", "avg_launch_us": round(us, 2),
+                     "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg}},
+        "workload": "8 volumes 128x128x128 delta=2: conv-net costs (3 layers of 3x3x3, 16 channels) on "
+                    "noisy two-horizon intensity, x16 quantised; forward exact solve + one-hot backward",
+    }
+
+
 def batched_leg(args, torch, smf, synth, stream):
     """Batch of 64 uneven volumes: one batch solve against 64 plain solves."""
     shapes = synth.batch_shapes()
@@ -349,6 +405,10 @@ def main():
         torch.cuda.set_device(0)
         print(json.dumps({"batched": batched_leg(args, torch, smf, synth, torch.cuda.current_stream())}),
               flush=True)
+        return
+    if args.diff_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"differentiable": diff_leg(args, torch, smf, synth)}), flush=True)
         return
     seismic = None
     if args.workload == "seismic":
@@ -481,6 +541,7 @@ def main():
         out["soft"] = soft_leg(args, torch, smf, cost, delta, stream)
     if seismic is not None and not args.no_batch:
         out["band"] = band_leg(args, torch, smf, synth, seismic, stream)
+        out["differentiable"] = diff_leg(args, torch, smf, synth)
     if not args.no_cpu_baseline:
         progress("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(cost, delta, args.cpu_crop)

@@ -129,6 +129,17 @@ int smf_batch_energies(const smf_handle *h, int64_t *out);
  * enqueued on `stream`. */
 int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream);
 
+/* Copies the pointwise-highest optimal surface h_max of the last successful
+ * solve into `out_dev` (device pointer, [nx][ny] int32; for a batch the
+ * packed surfaces as smf_batch_surfaces): h_max(p) is the highest node of
+ * column p on the source side of the maximal minimum cut, the set of nodes
+ * that cannot reach t in the residual graph (Eq. 6, Theorem 1.1).  Where
+ * h_max(p) = h(p) the column's optimal height is unique, which is where the
+ * energy is differentiable in that column's costs (Eq. 1).  Needs param
+ * "hmax" = 1 during the solve (one more complete global relabel after
+ * termination); SMF_ERR_NOT_SOLVED otherwise.  Enqueued on `stream`. */
+int smf_surface_max(const smf_handle *h, int32_t *out_dev, void *stream);
+
 /* Copies the surfaces of every volume of the last successful batch solve
  * into `packed_out_dev` (device pointer, sum_i nx[i]*ny[i] int32): volume
  * i's [nx][ny] heights follow those of volumes 0..i-1.  Enqueued on
@@ -207,6 +218,10 @@ int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *exten
  *                        relabel as one block with its
  *                        records in LDS (no launch or host poll per level);
  *                        0: always one launch per level
+ *   "hmax"            -- 1: every solve also reads out the highest optimal
+ *                        surface (smf_surface_max) with one complete global
+ *                        relabel after termination; the first 1 allocates
+ *                        4 bytes per column (SMF_ERR_NOMEM if that fails)
  *   "verbose"         -- 1: one progress line per poll and global relabel on stderr
  *   "count_work"      -- 1: kernels count their algorithmic bytes ("bytes.<class>"
  *                        statistics of bfs, push, relabel; one atomic per wave
@@ -308,7 +323,8 @@ int smf_tune_lookup(int32_t nx, int32_t ny, int32_t K, int32_t delta, int64_t *p
  * grad_cost [n][nx][ny][K] float (fully overwritten; 16-byte aligned when
  * K % 4 == 0).  The indicator is the derivative wherever a column's optimal
  * height is unique and a supergradient otherwise.  Enqueued on `stream`;
- * returns SMF_ERR_ARG for bad sizes or NULL pointers. */
+ * returns SMF_ERR_ARG for bad sizes (n > 65535 or nx*ny > 2^31 - 1
+ * included) or NULL pointers. */
 int smf_onehot_backward(const int32_t *surface_dev, const float *grad_energy_dev,
                         float *grad_cost_dev, int32_t n, int32_t nx, int32_t ny, int32_t K,
                         void *stream);

@@ -87,6 +87,9 @@ def _load():
                                              ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P,
                                              ctypes.POINTER(_Cert)]
         lib.certify_preflow_soft.restype = ctypes.c_int
+        lib.certify_hmax.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, P, P, P, P]
+        lib.certify_hmax.restype = ctypes.c_int
         lib.band_effective.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, P, P, P, P]
         lib.band_effective.restype = ctypes.c_int
@@ -185,6 +188,22 @@ def certify(cost, delta, excess, sink_res, flow_down, flow_lat, surface, alpha=0
         raise RuntimeError(f"certify_preflow failed with status {rc}")
     return Certificate(r.flow, r.cut, r.energy, r.bad_capacity, r.bad_conservation,
                        r.bad_smooth, r.bad_reach)
+
+
+def hmax_from_preflow(delta, sink_res, flow_down, flow_lat) -> np.ndarray:
+    """The pointwise-highest optimal surface read off a maximum preflow of the
+    plain graph (certify.c, certify_hmax): per column the highest node that
+    cannot reach t in the residual graph.  Arrays as for certify()."""
+    ts = np.ascontiguousarray(sink_res, dtype=np.int32)
+    nx, ny, K = ts.shape
+    fd = np.ascontiguousarray(flow_down, dtype=np.int32)
+    fl = np.ascontiguousarray(flow_lat, dtype=np.int32)
+    out = np.empty((nx, ny), dtype=np.int32)
+    rc = _load().certify_hmax(nx, ny, K, int(delta), ts.ctypes.data, fd.ctypes.data,
+                              fl.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"certify_hmax failed with status {rc}")
+    return out
 
 
 # ---- narrow-band volumes (Section 3.4) ---------------------------------------

@@ -338,3 +338,54 @@ int certify_preflow_band(const int32_t *cost, int32_t nx_, int32_t ny_, int32_t 
     free(lo); free(hi); free(net); free(mark); free(queue);
     return 0;
 }
+
+/*
+ * The pointwise-highest optimal surface from a maximum preflow of the plain
+ * graph (state as for certify_preflow): S_max, the source side of the
+ * maximal minimum cut, is the set of nodes that cannot reach t in the
+ * residual graph (Theorem 1.1 applied to the maximal cut; returning excess to
+ * s changes no residual arc on a path to t, so any maximum preflow gives the
+ * same set).  The nodes that reach t are found by a backward search from the
+ * sink arcs with residual capacity; hmax[p] = the highest node of column p
+ * outside that set (-1 if none).  Returns 0, -1 on bad arguments, -2 when
+ * memory runs out.
+ */
+int certify_hmax(int32_t nx_, int32_t ny_, int32_t K_, int32_t delta_, const int32_t *sink_res,
+                 const int32_t *flow_down, const int32_t *flow_lat, int32_t *hmax)
+{
+    const int64_t nx = nx_, ny = ny_, K = K_, delta = delta_, P = nx * ny, N = P * K;
+    if (nx < 1 || ny < 1 || K < 1 || delta < 0 || !hmax) return -1;
+    uint8_t *to_t = calloc((size_t)N, 1);
+    int64_t *queue = malloc((size_t)N * sizeof(int64_t));
+    if (!to_t || !queue) { free(to_t); free(queue); return -2; }
+    static const int mx[4] = {1, -1, 0, 0}, my[4] = {0, 0, 1, -1};
+    int64_t first = 0, last = 0;
+    for (int64_t v = 0; v < N; ++v)
+        if (sink_res[v] > 0) { to_t[v] = 1; queue[last++] = v; }
+#define BACK(u) do { if (!to_t[u]) { to_t[u] = 1; queue[last++] = (u); } } while (0)
+    while (first < last) {
+        const int64_t v = queue[first++], z = v % K, p = v / K, x = p / ny, y = p % ny;
+        if (z + 1 < K) BACK(v + 1);                    /* (p,z+1) -> (p,z), infinite */
+        if (z > 0 && flow_down[v] > 0) BACK(v - 1);    /* reverse of (p,z) -> (p,z-1) */
+        for (int k = 0; k < 4; ++k) {
+            const int64_t qx = x + mx[k], qy = y + my[k];
+            if (qx < 0 || qx >= nx || qy < 0 || qy >= ny) continue;
+            const int64_t q = qx * ny + qy;
+            /* q's lateral arc towards p landing on (p,z): tail (q,0) or (q,z+delta) */
+            const int64_t zq = z == 0 ? 0 : z + delta;
+            if (zq < K) BACK(q * K + zq);
+            /* reverse of v's own arc (p,z) -> (q, z - delta) carrying flow */
+            if ((z == 0 || z > delta) && flow_lat[(int64_t)k * N + v] > 0)
+                BACK(q * K + (z == 0 ? 0 : z - delta));
+        }
+    }
+#undef BACK
+    for (int64_t p = 0; p < P; ++p) {
+        int32_t top = -1;
+        for (int64_t z = 0; z < K; ++z)
+            if (!to_t[p * K + z]) top = (int32_t)z;
+        hmax[p] = top;
+    }
+    free(to_t); free(queue);
+    return 0;
+}

@@ -47,6 +47,7 @@ void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work 
 void launch_compact(const Geom &g, const Work &w, int *next_count, hipStream_t st);
 void launch_gap_find(const Geom &g, const State &sv, long long max_inst_nodes, hipStream_t st);
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st);
+void launch_hmax(const Geom &g, const State &sv, int *Hmax, hipStream_t st);
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st);
 void launch_finish(const int *cost, const Geom &g, const State &sv, int *H, hipStream_t st);
 }  // namespace smf
@@ -181,6 +182,7 @@ struct smf_handle {
     int *fill_dev = nullptr;      // n: fixup label of the running global relabel (-1: none)
     int *state = nullptr;         // 8 * Ntot int32
     int *H = nullptr;             // Ptot int32 surfaces
+    int *Hmax = nullptr;          // Ptot int32 highest optimal surfaces (param hmax)
     int *bfs = nullptr;           // 12 * Ptot int32: two per-column BFS records (threshold word,
                                   // LF[4]), the lowest active heights and the short-column list
     unsigned long long *bits = nullptr;   // kMasks * max_nch * Ptot BFS bit-mask words
@@ -219,6 +221,8 @@ struct smf_handle {
     int64_t block_search = 1;      // small single volumes: whole searches in one block
     int64_t verbose = 0;           // 1: progress lines on stderr
     int64_t gap_every = 0;         // sweeps between gap searches (0: off)
+    int64_t want_hmax = 0;         // 1: also read out the highest optimal surface
+    bool hmax_ready = false;       // the last solve computed Hmax
 
     // results and counters of the last solve
     bool solved = false;
@@ -235,7 +239,7 @@ static void release(smf_handle *h)
     if (!h) return;
     void *dev[] = {h->inst_dev, h->col_inst, h->cnt_dev, h->part_dev, h->fill_dev, h->state, h->H,
                    h->bfs, h->bits, h->wcount, h->hist, h->wmask, h->wlist, h->soft_flow, h->sbits,
-                   h->band_dev};
+                   h->band_dev, h->Hmax};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     for (int i = 0; i < kSnapSlots; ++i)
@@ -470,9 +474,12 @@ static bool shrink_cover(const smf_handle *h, const std::vector<char> &live, std
     return true;
 }
 
-static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> &part)
+static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> &part, bool complete = false)
 {
     const int n = h->n;
+    // a complete search runs until a level labels nothing, whatever
+    // bfs_early_stop says
+    const int64_t early_stop = complete ? 0 : h->bfs_early_stop;
     const size_t P = (size_t)h->g.Ptot;
     int *T[2] = {h->bfs, h->bfs + 5 * P};
     int *LF[2] = {h->bfs + P, h->bfs + 6 * P};
@@ -511,7 +518,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         // a small single volume: the whole search in one block, no polls
         {
             TimedScope ts(h->timer, KC_BFS, s);
-            launch_bfs_block(h->g, h->st, T[1], LF[1], (int)h->bfs_early_stop,
+            launch_bfs_block(h->g, h->st, T[1], LF[1], (int)early_stop,
                              (int)std::min<int64_t>(h->max_inst_nodes + 2, INT32_MAX), h->scr, s);
         }
         HIP_TRY(hipGetLastError());
@@ -536,7 +543,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
             }
         }
         // this poll's count goes to bfs_unsat[npoll & 1]
-        if (h->bfs_early_stop) launch_bfs_count(h->g, T[cur], npoll & 1, s);
+        if (early_stop) launch_bfs_count(h->g, T[cur], npoll & 1, s);
         HIP_TRY(hipGetLastError());
         int rc = post_snapshot(h, s, kSlotBfs + slot);
         if (rc) return rc;
@@ -552,7 +559,7 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
                 if (!live[i]) continue;
                 const InstScratch &r = h->is_host[i];
                 const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
-                const bool labelled = h->bfs_early_stop && r.bfs_unsat[Csnap[slot ^ 1]] == 0;
+                const bool labelled = early_stop && r.bfs_unsat[Csnap[slot ^ 1]] == 0;
                 if (complete || labelled) {
                     live[i] = 0;
                     ended = true;
@@ -608,6 +615,7 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
 {
     const int n = h->n;
     h->solved = false;
+    h->hmax_ready = false;
     h->sweeps = h->global_relabels = h->bfs_passes = h->mincut_passes = h->gap_relabels = 0;
     h->gap_searches = h->reset_nodes = h->reset_chunks = 0;
     h->flow.assign(n, 0);
@@ -709,6 +717,15 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
         slot ^= 1;
     }
 
+    if (h->want_hmax) {
+        // S_max, the source side of the maximal minimum cut, is the set of
+        // nodes that cannot reach t in the residual graph of any maximum
+        // preflow; a complete search leaves exactly those at kInf, and they
+        // form a prefix of each column
+        rc = global_relabel(h, s, all, true);
+        if (rc) return rc;
+        launch_hmax(h->g, h->st, h->Hmax, s);
+    }
     {
         TimedScope ts(h->timer, KC_MINCUT, s);
         launch_mincut_init(h->g, h->st, h->H, s);
@@ -751,6 +768,7 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     } else {
         h->work_bytes[0] = h->work_bytes[1] = h->work_bytes[2] = 0;
     }
+    h->hmax_ready = h->want_hmax != 0;
     h->solved = true;
     return SMF_OK;
 }
@@ -836,6 +854,16 @@ extern "C" int smf_surface(const smf_handle *h, int32_t *out_dev, void *stream)
 extern "C" int smf_batch_surfaces(const smf_handle *h, int32_t *packed_out_dev, void *stream)
 {
     return copy_surfaces(h, packed_out_dev, stream, "smf_batch_surfaces");
+}
+
+extern "C" int smf_surface_max(const smf_handle *h, int32_t *out_dev, void *stream)
+{
+    if (!h || !out_dev) return fail(SMF_ERR_ARG, "smf_surface_max: NULL argument");
+    if (!h->solved || !h->hmax_ready)
+        return fail(SMF_ERR_NOT_SOLVED, "smf_surface_max: the last solve did not read out h_max (param hmax)");
+    HIP_TRY(hipMemcpyAsync(out_dev, h->Hmax, sizeof(int) * (size_t)h->g.Ptot, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return SMF_OK;
 }
 
 extern "C" int smf_export_state(const smf_handle *h, int32_t *excess_dev, int32_t *sink_res_dev,
@@ -1006,6 +1034,16 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     else if (!strcmp(key, "count_work")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: count_work is 0 or 1");
         h->g.count_work = (int)value;
+        return SMF_OK;
+    }
+    else if (!strcmp(key, "hmax")) {
+        if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: hmax is 0 or 1");
+        if (value && !h->Hmax) {
+            HIP_TRY(hipSetDevice(h->device));
+            if (!dev_alloc(h->Hmax, (size_t)h->g.Ptot))
+                return fail(SMF_ERR_NOMEM, "smf_set_param: allocation of the h_max surface failed");
+        }
+        h->want_hmax = value;
         return SMF_OK;
     }
     else if (!strcmp(key, "verbose")) {

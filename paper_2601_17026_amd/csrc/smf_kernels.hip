@@ -1622,6 +1622,32 @@ __global__ __launch_bounds__(256) void k_mincut_init(Geom g, State st, int *H)
     }
 }
 
+// h_max(p) = the highest node of the column that cannot reach t, after a
+// complete search has left exactly those nodes at kInf (a prefix of the
+// column): one below the lowest node with a finite label, or the column's
+// top if there is none.  Heights of the volume with a band.  One wave per
+// column.
+__global__ __launch_bounds__(256) void k_hmax(Geom g, State st, int *Hmax)
+{
+    const int lane = lane_id();
+    int lo, hi;
+    wave_columns(g, lo, hi);
+    for (int p = lo; p < hi; ++p) {
+        const Col col = column_uniform(g, p);
+        const int ext = g.band ? g.bext[p] : col.I.K;
+        int hm = ext - 1;
+        for (int c = 0; c < col.I.nch; ++c) {
+            const int z = c * kWave + lane;
+            const unsigned long long b = __ballot(z < ext && st.d[col.base + z] < kInf);
+            if (b) {
+                hm = c * kWave + __ffsll((long long)b) - 2;
+                break;
+            }
+        }
+        if (lane == 0) Hmax[p] = hm + (g.band ? g.blo[p] : 0);
+    }
+}
+
 template <bool kSoft>
 __global__ __launch_bounds__(256) void k_mincut_pass(Geom g, State st, int *H, Scratch *s)
 {
@@ -1895,6 +1921,11 @@ void launch_relabel(const Geom &g, const State &sv, const Work &win, const Work 
 void launch_mincut_init(const Geom &g, const State &sv, int *H, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mincut_init, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, H);
+}
+
+void launch_hmax(const Geom &g, const State &sv, int *Hmax, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hmax, dim3(wave_blocks(g)), dim3(256), 0, st, g, sv, Hmax);
 }
 
 void launch_mincut_pass(const Geom &g, const State &sv, int *H, Scratch *s, hipStream_t st)

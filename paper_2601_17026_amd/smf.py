@@ -66,6 +66,8 @@ _lib.smf_tune_cache_save.argtypes = [ctypes.c_char_p]
 _lib.smf_tune_cache_clear.argtypes = []
 _lib.smf_tune_lookup.argtypes = [_I32, _I32, _I32, _I32, _PI64]
 _lib.smf_set_band.argtypes = [_P, _P, _P]
+_lib.smf_surface_max.argtypes = [_P, _P, _P]
+_lib.smf_surface_max.restype = ctypes.c_int
 _lib.smf_set_band.restype = ctypes.c_int
 _lib.smf_solve_noalloc.argtypes = [_P, _I32, _I32, _I32, _I32, _P, _PI64, _PI64, _P]
 _lib.smf_solve_noalloc.restype = ctypes.c_int
@@ -88,7 +90,7 @@ EXPORTED = ("smf_create", "smf_destroy", "smf_solve", "smf_flow_value", "smf_ene
             "smf_batch_energies", "smf_batch_surfaces", "smf_batch_set_param",
             "smf_batch_get_stat", "smf_autotune", "smf_tune_apply", "smf_tune_cache_load",
             "smf_tune_cache_save", "smf_tune_cache_clear", "smf_tune_lookup",
-            "smf_solve_noalloc", "smf_set_band")
+            "smf_solve_noalloc", "smf_set_band", "smf_surface_max")
 
 
 class SmfError(RuntimeError):
@@ -205,6 +207,17 @@ class Solver:
         _check(_lib.smf_surface(self._h, out.data_ptr(), _stream_ptr(stream, self.device)), "smf_surface")
         return out
 
+    def surface_max(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """The pointwise-highest optimal surface (needs set_param("hmax", 1)
+        before the solve)."""
+        nx, ny, _ = self.shape
+        if out is None:
+            out = _empty((nx, ny), torch.int32, self.device)
+        _dev_i32(out, (nx, ny), "out", self.device)
+        _check(_lib.smf_surface_max(self._h, out.data_ptr(), _stream_ptr(stream, self.device)),
+               "smf_surface_max")
+        return out
+
     def set_band(self, offset, extent) -> None:
         """Narrow band: column (x, y) holds the heights offset[x, y] ..
         offset[x, y] + extent[x, y] - 1 of the volume (host arrays of shape
@@ -315,6 +328,16 @@ class BatchSolver:
         _dev_i32(out, (total,), "out", self.device)
         _check(_lib.smf_batch_surfaces(self._h, out.data_ptr(), _stream_ptr(stream, self.device)),
                "smf_batch_surfaces")
+        return out
+
+    def surfaces_max(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Packed pointwise-highest optimal surfaces (set_param("hmax", 1))."""
+        total = sum(self.columns)
+        if out is None:
+            out = _empty((total,), torch.int32, self.device)
+        _dev_i32(out, (total,), "out", self.device)
+        _check(_lib.smf_surface_max(self._h, out.data_ptr(), _stream_ptr(stream, self.device)),
+               "smf_surface_max")
         return out
 
     def unpack_surfaces(self, packed: torch.Tensor) -> list:

@@ -19,7 +19,8 @@ def mods():
     return smf, autograd
 
 
-@pytest.mark.parametrize("n,nx,ny,K", [(1, 1, 1, 1), (2, 3, 5, 7), (3, 16, 9, 64), (2, 40, 33, 130)])
+@pytest.mark.parametrize("n,nx,ny,K", [(1, 1, 1, 1), (2, 3, 5, 7), (3, 16, 9, 64), (2, 40, 33, 130),
+                                       (1, 7, 6, 1029), (4, 33, 2, 256), (3, 5, 3, 2)])
 def test_onehot_backward_kernel(mods, n, nx, ny, K):
     smf, _ = mods
     g = torch.Generator(device="cpu").manual_seed(7)
@@ -124,9 +125,14 @@ def test_gradient_reaches_the_network(mods):
 
 
 def test_differentiable_workload_full_size(mods):
-    """8 volumes of 128x128x128, delta 2: certificates of every solve, the
-    backward against the indicator of the certified surface, and 200 sampled
-    +-1 finite differences of the exact energy (computed by the solver)."""
+    """8 volumes of 128x128x128, delta 2.  Every solve, perturbed ones
+    included, is certified optimal; h_max is read out on the GPU and must
+    equal the one read off the certified preflow; the backward must be the
+    indicator of the certified surface; and 200 integer +-1 finite
+    differences (100 voxels on the surface, 50 one height off it, 50
+    anywhere in the column), all in columns whose optimal height is unique
+    (h_min = h_max), must equal the gradient exactly: d_up == d_dn ==
+    [z == h(p)]."""
     smf, ag = mods
     cost, _, _ = synth.diff_costs(batch=8, n=128, K=128, device="cuda")
     cost = cost.clone().requires_grad_(True)
@@ -136,39 +142,51 @@ def test_differentiable_workload_full_size(mods):
     (E * gE).sum().backward()
     ci = ag.quantize(cost.detach())
     hs = h.cpu().numpy()
+    grad = cost.grad
+    ref = torch.zeros_like(grad)
+    ref.scatter_(3, h.long()[..., None], gE[:, None, None, None].expand(8, 128, 128, 1))
+    assert torch.equal(grad, ref)
+    kinds = ["on", "near", "on", "any"] * 50
+    rng = np.random.default_rng(11)
+    checked = 0
     with smf.Solver(128, 128, 128, 2) as s:
-        for b in range(8):
-            s.solve(ci[b])
+        s.set_param("hmax", 1)
+
+        def certified(c):
+            s.solve(c)
+            surf = s.surface().cpu().numpy()
             e, ts, fd, fl = (t.cpu().numpy() for t in s.export_state())
-            cert = oracle.certify(ci[b].cpu().numpy(), 2, e, ts, fd, fl, hs[b])
-            assert cert.ok, (b, cert)
-            assert cert.energy / 16.0 == E[b].item()
-        grad = cost.grad
-        ref = torch.zeros_like(grad)
-        ref.scatter_(3, h.long()[..., None], gE[:, None, None, None].expand(8, 128, 128, 1))
-        assert torch.equal(grad, ref)
-        # finite differences: 25 voxels per volume, 100 on the surface
-        rng = np.random.default_rng(11)
-        checked = 0
+            cert = oracle.certify(c.cpu().numpy(), 2, e, ts, fd, fl, surf)
+            assert cert.ok, cert
+            assert cert.energy == s.energy()
+            return s.energy(), surf, ts, fd, fl
+
         for b in range(8):
-            base = int(round(E[b].item() * 16))
+            base, surf, ts, fd, fl = certified(ci[b])
+            np.testing.assert_array_equal(surf, hs[b])
+            assert base / 16.0 == E[b].item()
+            hmax = s.surface_max().cpu().numpy()
+            np.testing.assert_array_equal(hmax, oracle.hmax_from_preflow(2, ts, fd, fl))
+            unique = np.argwhere(hmax == surf)
+            assert len(unique) > 1000, len(unique)
             c0 = ci[b].clone()
-            for i in range(25):
-                x, y = (int(v) for v in rng.integers(0, 128, 2))
-                z = int(hs[b, x, y]) if i % 2 == 0 else int(rng.integers(0, 128))
-                on = z == hs[b, x, y]
-                c0[x, y, z] += 1
-                s.solve(c0)
-                d_up = s.energy() - base
-                c0[x, y, z] -= 2
-                s.solve(c0)
-                d_dn = base - s.energy()
-                c0[x, y, z] += 1
-                # one-hot of the minimal surface: always a valid one-sided derivative
-                assert d_up in (0, 1) and d_dn in (0, 1)
-                if on:
-                    assert d_dn == 1
+            for i, j in enumerate(rng.choice(len(unique), 25, replace=False)):
+                x, y = (int(v) for v in unique[j])
+                hz = int(surf[x, y])
+                kind = kinds[25 * b + i]
+                if kind == "on":
+                    z = hz
+                elif kind == "near":
+                    z = hz + 1 if (hz + 1 < 128 and rng.integers(2)) or hz == 0 else hz - 1
                 else:
-                    assert d_up == 0
+                    z = int(rng.integers(0, 128))
+                c0[x, y, z] += 1
+                d_up = certified(c0)[0] - base
+                c0[x, y, z] -= 2
+                d_dn = base - certified(c0)[0]
+                c0[x, y, z] += 1
+                want = int(z == hz)
+                assert d_up == d_dn == want, (b, x, y, z, hz, d_up, d_dn)
+                assert grad[b, x, y, z].item() == want * gE[b].item()
                 checked += 1
-        assert checked == 200
+    assert checked == 200

@@ -133,3 +133,20 @@ def test_full_size_seismic_band(smf):
     _check(np.ascontiguousarray(bc), delta, np.ascontiguousarray(oc), np.ascontiguousarray(ec),
            _gpu_band(smf, np.ascontiguousarray(bc), delta, np.ascontiguousarray(oc),
                      np.ascontiguousarray(ec)))
+
+
+def test_band_hmax_matches_oracle(smf):
+    rng = np.random.default_rng(91)
+    nx, ny, K, delta = 14, 11, 50, 1
+    off, ext = _random_feasible_band(rng, nx, ny, K, delta, max_off=10, min_ext=5)
+    cost = rng.integers(0, 4, (nx, ny, K)).astype(np.int32)
+    c = torch.from_numpy(cost).cuda()
+    print("case: band hmax 14x11x50", flush=True)
+    with smf.Solver(nx, ny, K, delta) as s:
+        s.set_band(off, ext)
+        s.set_param("hmax", 1)
+        s.solve(c)
+        r = oracle.solve_band(cost, delta, off, ext)
+        np.testing.assert_array_equal(s.surface().cpu().numpy(), r.hmin)
+        np.testing.assert_array_equal(s.surface_max().cpu().numpy(), r.hmax)
+        assert (r.hmax > r.hmin).any()

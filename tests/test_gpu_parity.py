@@ -268,3 +268,33 @@ def test_extreme_costs_exact_or_range_error(smf, shape, delta):
         assert g["cert"].ok, g["cert"]
         outcomes.add("exact")
     print(f"outcomes {sorted(outcomes)}", flush=True)
+
+
+@pytest.mark.parametrize("case", ["small", "ties", "ties_levels", "random"])
+def test_hmax_matches_oracle(smf, case):
+    # the highest optimal surface from one complete search after
+    # termination; small cost ranges give many columns whose optimal height
+    # is not unique (h_min < h_max)
+    cost, delta, params = {
+        "small": (synth.config_small()[0], 2, {}),
+        "ties": (synth.random_cost(20, 24, 30, 0, 3, seed=81), 1, {}),
+        "ties_levels": (synth.random_cost(50, 40, 70, 0, 4, seed=82), 2, {"block_search": 0}),
+        "random": (synth.random_cost(9, 11, 140, 0, 1000, seed=83), 3, {}),
+    }[case]
+    print(f"case: hmax {case} {cost.shape} delta {delta}", flush=True)
+    c = torch.from_numpy(cost).cuda()
+    with smf.Solver(*cost.shape, delta) as s:
+        s.set_param("hmax", 1)
+        for k, v in params.items():
+            s.set_param(k, v)
+        s.solve(c)
+        hmin, hmax = s.surface().cpu().numpy(), s.surface_max().cpu().numpy()
+        r = oracle.solve(cost, delta)
+        np.testing.assert_array_equal(hmin, r.hmin)
+        np.testing.assert_array_equal(hmax, r.hmax)
+        if case.startswith("ties"):
+            assert (hmax > hmin).any()
+        s.set_param("hmax", 0)
+        s.solve(c)
+        with pytest.raises(smf.SmfError):
+            s.surface_max()

@@ -380,3 +380,19 @@ def test_second_oracle_random_shapes(shape, delta, alpha):
         assert F == r.flow
         np.testing.assert_array_equal(hmin, r.hmin)
         np.testing.assert_array_equal(hmax, r.hmax)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hmax_from_a_textbook_preflow(seed):
+    # the highest optimal surface read off an independent maximum preflow
+    # equals the oracle's h_max (and brute force on the tiny volumes)
+    rng = np.random.default_rng(900 + seed)
+    nx, ny, K = int(rng.integers(1, 4)), int(rng.integers(1, 4)), int(rng.integers(2, 6))
+    delta = int(rng.integers(0, 3))
+    cost = rng.integers(0, 6, (nx, ny, K)).astype(np.int32)   # small range: many ties
+    e, ts, fd, fl, flow = pins.reduced_preflow(cost, delta)
+    hm = oracle.hmax_from_preflow(delta, ts, fd, fl)
+    r = oracle.solve(cost, delta)
+    np.testing.assert_array_equal(hm, r.hmax)
+    _, _, bf_hmax = pins.brute_force(cost, delta)
+    np.testing.assert_array_equal(hm, bf_hmax)

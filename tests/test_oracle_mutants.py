@@ -106,6 +106,10 @@ MUTANTS = [
      "alpha + flow_soft[(int64_t)k * N + v] - flow_soft[(int64_t)kk * N + u] > 0"),
     ("cert_sink_reach_ignored", "certify.c",
      "if (sink_res[v] > 0) reached_sink = 1;", "if (sink_res[v] < 0) reached_sink = 1;"),
+    ("cert_hmax_reverse_down_dropped", "certify.c",
+     "if (z > 0 && flow_down[v] > 0) BACK(v - 1);", "if (0 && flow_down[v] > 0) BACK(v - 1);"),
+    ("cert_hmax_lateral_tail_height", "certify.c",
+     "const int64_t zq = z == 0 ? 0 : z + delta;", "const int64_t zq = z == 0 ? 0 : z + delta + 1;"),
     # --- narrow-band graphs (Section 3.4) --------------------------------------
     ("band_lower_rule_wrong_sign", "oracle.c",
      "if (lo[p] - delta > lo[q]) { lo[q] = lo[p] - delta; changed = 1; }",
