@@ -64,7 +64,10 @@ typedef struct smf_handle smf_handle;
  * smf_last_error).  Requires nx, ny, K >= 1, delta >= 0,
  * nx*ny*K <= 2^30 - 2 (every finite distance label then stays below the
  * solver's reserved label values).  The handle is a batch of one volume:
- * the smf_batch_* calls accept it too. */
+ * the smf_batch_* calls accept it too.  If the environment variable
+ * SMF_DEVICE_MEM_LIMIT holds a byte count, a handle that would need more
+ * device memory than that is refused with SMF_ERR_NOMEM before anything is
+ * allocated (also for smf_batch_create). */
 smf_handle *smf_create(int32_t nx, int32_t ny, int32_t K, int32_t delta);
 
 /* Allocates one handle for a batch of n independent volumes of uneven

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -325,6 +326,25 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
         max_nch = std::max(max_nch, I.nch);
         if (Ptot >= (1LL << 31)) {
             fail(SMF_ERR_RANGE, "smf_batch_create: more than 2^31 - 1 columns in the batch");
+            return nullptr;
+        }
+    }
+    // device memory of the handle (the allocations below), checked against
+    // the caller's budget before anything is allocated
+    const size_t need = sizeof(Inst) * (size_t)n + sizeof(int) * (size_t)Ptot + counter_bytes(n) +
+                        2 * sizeof(int) * (size_t)n + sizeof(int) * 8 * (size_t)Ntot +
+                        sizeof(int) * (size_t)Ptot + sizeof(int) * 12 * (size_t)Ptot +
+                        sizeof(unsigned long long) * kMasks * (size_t)max_nch * (size_t)Ptot +
+                        sizeof(unsigned long long) * 3 * kWorkSlots * kWorkStride +
+                        sizeof(int) * (size_t)n * kHistLen + sizeof(unsigned long long) * 2 * (size_t)Ptot +
+                        sizeof(int) * 2 * (size_t)Ptot;
+    if (const char *lim = getenv("SMF_DEVICE_MEM_LIMIT")) {
+        char *end = nullptr;
+        const unsigned long long cap = strtoull(lim, &end, 10);
+        if (end != lim && need > cap) {
+            fail(SMF_ERR_NOMEM, "smf_batch_create: the handle needs " + std::to_string(need) +
+                                    " bytes of device memory, more than SMF_DEVICE_MEM_LIMIT = " +
+                                    std::to_string(cap));
             return nullptr;
         }
     }

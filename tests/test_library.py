@@ -146,3 +146,17 @@ def test_no_gpu_fails_loudly():
         with pytest.raises(smf.SmfError) as ei:
             make()
         assert "no usable HIP device" in str(ei.value)
+
+
+def test_device_memory_budget_refuses_before_allocating(monkeypatch):
+    # SMF_DEVICE_MEM_LIMIT below what a handle needs: SMF_ERR_NOMEM from
+    # smf_create, decided before any device call (so also without a GPU)
+    from paper_2601_17026_amd import smf
+    monkeypatch.setenv("SMF_DEVICE_MEM_LIMIT", "1000000")   # 1 MB; 64x64x64 needs ~8.6 MB
+    for make in (lambda: smf.Solver(64, 64, 64, 1), lambda: smf.BatchSolver([(64, 64, 64, 1)] * 2)):
+        with pytest.raises(smf.SmfError) as ei:
+            make()
+        assert "SMF_DEVICE_MEM_LIMIT" in str(ei.value)
+    lib = smf._lib
+    assert lib.smf_create(64, 64, 64, 1) is None
+    assert b"more than SMF_DEVICE_MEM_LIMIT" in lib.smf_last_error()
