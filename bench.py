@@ -68,6 +68,8 @@ def parse():
                     help="keep the default relabel period instead of running the autotuner")
     ap.add_argument("--relabel-period", type=int, default=0, metavar="N",
                     help="use relabel period N for every volume instead of running the autotuner")
+    ap.add_argument("--push-phases", type=int, default=0, metavar="M",
+                    help="with --relabel-period: use M push phases per sweep (default: the solver's)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched leg (prints its JSON object)")
     ap.add_argument("--no-sequential", action="store_true",
@@ -151,6 +153,13 @@ def stored_traffic(kernel: str):
 
 
 
+def fixed_schedule(args, solver):
+    """--relabel-period (and --push-phases) instead of the autotuner."""
+    solver.set_param("relabel_period", args.relabel_period)
+    if args.push_phases > 0:
+        solver.set_param("push_phases", args.push_phases)
+
+
 def cpu_baseline(cost, delta, crop, alpha=0):
     import numpy as np
 
@@ -181,6 +190,11 @@ def soft_leg(args, torch, smf, cost, delta, stream):
     c = torch.from_numpy(cost).cuda()
     solver = smf.Solver(nx, ny, K, delta)
     solver.set_param("smooth_weight", args.smooth_weight)
+    if args.relabel_period > 0:
+        fixed_schedule(args, solver)
+    elif not args.no_tune:
+        progress("soft leg: tuning the schedule")
+        smf.autotune(solver, c, stream=stream)
     per_class = {k: {"ns": 0, "n": 0, "bytes": 0} for k in CLASSES}
     solver.set_param("kernel_timing", (1 << len(CLASSES)) - 1)
     solver.set_param("count_work", 1)
@@ -235,7 +249,7 @@ def band_leg(args, torch, smf, synth, seismic, stream):
     solver = smf.Solver(*band.shape, delta)
     solver.set_band(off, ext)
     if args.relabel_period > 0:
-        solver.set_param("relabel_period", args.relabel_period)
+        fixed_schedule(args, solver)
     solver.solve(c, stream)                       # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -329,9 +343,9 @@ def batched_leg(args, torch, smf, synth, stream):
     progress("batched leg: tuning the relabel periods")
     t0 = time.perf_counter()
     if args.relabel_period > 0:
-        batch.set_param("relabel_period", args.relabel_period)
+        fixed_schedule(args, batch)
         for s in plain:
-            s.set_param("relabel_period", args.relabel_period)
+            fixed_schedule(args, s)
     elif not args.no_tune:
         smf.autotune(batch, packed, stream=stream)
         for s in plain:
@@ -365,6 +379,7 @@ def batched_leg(args, torch, smf, synth, stream):
                "ms_sequential_plain": round(1e3 * t_seq, 2),
                "speedup_vs_sequential": round(t_seq / t_batch, 3),
                "flows_equal_plain": all(s.flow_value() == f for s, f in zip(plain, flows))}
+    phases = batch.stat("push_phases")
     for s in plain:
         s.close()
     batch.close()
@@ -379,6 +394,7 @@ def batched_leg(args, torch, smf, synth, stream):
         "batch_sweeps": sweeps,
         "autotune_seconds": round(t_tune, 2),
         "relabel_periods": {str(p): periods.count(p) for p in sorted(set(periods))},
+        "push_phases": phases,
         "workload": "64 volumes, nx, ny, K ~ U{64..256}, delta ~ U{1,2,3}, two layered "
                     "horizons, sigma 0.4, costs 0..255 (per-volume seeds)",
     }
@@ -436,13 +452,14 @@ def main():
     tune_s = 0.0
     progress("plain leg: tuning the relabel period")
     if args.relabel_period > 0:
-        solver.set_param("relabel_period", args.relabel_period)
+        fixed_schedule(args, solver)
     elif not args.no_tune:
-        # the autotuner times the candidate relabel periods (set-up, not timed)
+        # the autotuner times the candidate schedules (set-up, not timed)
         t0 = time.perf_counter()
         smf.autotune(solver, c, stream=stream)
         tune_s = time.perf_counter() - t0
     period = solver.stat_per_volume("relabel_period")[0]
+    phases = solver.stat("push_phases")
 
     # warm-up solves time every kernel class; the class with the most time is
     # the dominant kernel of the roofline
@@ -527,7 +544,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS.get(args.workload, WORKLOAD), "nx": nx, "ny": ny, "K": K,
                    "delta": delta,
-                   "voxels": V, "mode": "plain", "relabel_period": period,
+                   "voxels": V, "mode": "plain", "relabel_period": period, "push_phases": phases,
                    "autotune_seconds": round(tune_s, 2)},
         "roofline": roof,
         "result": {"flow": flow, "energy": energy, "surface_sha256": surface_sha},

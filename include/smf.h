@@ -200,10 +200,12 @@ int smf_export_soft_flows(const smf_handle *h, int32_t *flow_soft_dev, void *str
 int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *extent_host);
 
 /* Tuning and limits.  Keys:
- *   "relabel_period"  -- push/relabel sweeps between global relabels (>= 1,
- *                        default 4;
+ *   "relabel_period"  -- sweeps between global relabels (>= 1, default 2;
  *                        for a batch: of every volume, replacing any per-volume
  *                        periods)
+ *   "push_phases"     -- push phases per sweep, each followed by a list of the
+ *                        columns it left with excess; one relabel phase ends
+ *                        the sweep (1..8, default 3; for the whole handle)
  *   "max_sweeps"      -- sweep cap before SMF_ERR_NOT_CONVERGED (>= 1)
  *   "poll_every"      -- sweeps between host termination checks (>= 1)
  *   "bfs_poll_every"  -- BFS levels between host convergence checks (1..62)
@@ -263,7 +265,8 @@ int smf_batch_set_param(smf_handle *h, const char *key, const int64_t *values);
  * gap heuristic), "gap_searches", and with kernel_timing on,
  * "time_ns.<class>" (summed event time) and "launches.<class>" for the
  * kernel classes build, bfs_reset, bfs, push, relabel, mincut, finish, and
- * "band" (1 with a narrow band set), "bytes.<class>": algorithmic bytes of the
+ * "band" (1 with a narrow band set), the settings "push_phases" and
+ * "relabel_period" (the handle's), "bytes.<class>": algorithmic bytes of the
  * class over the solve (state words
  * read or written, each access counted once; counted on the device for the
  * data-dependent classes bfs, push and relabel), and the sizes "volumes",
@@ -278,36 +281,40 @@ int smf_get_stat(const smf_handle *h, const char *key, int64_t *out);
  * shape keys "nx", "ny", "K", "delta". */
 int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
 
-/* Autotuner of the relabel period (the paper tunes its relabel factor
- * empirically, Section 3.4).  Volumes fall into classes keyed by
- * (ceil log2 K, min(delta, 4), floor log2 (nx*ny), smooth_weight > 0).  For
- * every class of the handle's volumes that the process-wide tuning cache
- * does not hold yet, the largest volume of that class is solved (with its
- * smooth_weight) on a temporary handle with
- * each candidate period (2, 3, 4, 6, 8, 12), timed on the host clock (the
- * fastest of three runs when a solve takes under 0.25 s, of two under 2 s),
- * and the fastest
- * period is cached; then every volume of `h` gets
- * its class's period (smf_batch_set_param).  For a batch of more than one
- * volume the tuner then times whole solves of `h` with every volume's
- * period scaled by 1, 1.5, 2 and 3 and keeps the fastest scale (the volumes
- * of a batch share their searches, which favours longer periods than
- * solving each volume alone); the cache keeps the unscaled class periods.  `packed_cost_dev` and
- * `offsets_host` are as for smf_batch_solve (a plain handle: the volume,
- * NULL offsets).  Allocates and frees the temporary handles; work runs on
- * `stream`.  If the environment variable SMF_TUNE_CACHE names a file, the
- * cache is loaded from it on first use and saved to it after new timings.
- * The cache is shared by all host threads (calls serialise on a lock). */
+/* Autotuner of the schedule: the relabel period and the push phases per
+ * sweep (the paper tunes its relabel factor empirically, Section 3.4).
+ * Volumes fall into classes keyed by (ceil log2 K, min(delta, 4), floor log2
+ * (nx*ny), smooth_weight > 0).  For every class of the handle's volumes that
+ * the process-wide tuning cache does not hold yet, the largest volume of that
+ * class is solved (with its smooth_weight) on a temporary handle with each
+ * candidate (period, push phases) pair -- (4,1), (2,2), (1,3), (2,3), (3,3),
+ * (1,4), (2,4) -- timed on the host clock (the fastest of three runs when a
+ * solve takes under 0.25 s, of two under 2 s), and the fastest pair is
+ * cached; then every volume of `h` gets its class's period
+ * (smf_batch_set_param) and `h` the push phases of its cached class holding
+ * the most nodes (push phases are one value per handle).  For a batch of
+ * more than one volume the tuner then times whole solves of `h` with every
+ * volume's period scaled by 1, 1.5, 2 and 3 and keeps the fastest scale (the
+ * volumes of a batch share their searches, which favours longer periods
+ * than solving each volume alone); the cache keeps the unscaled class
+ * periods.  `packed_cost_dev` and `offsets_host` are as for smf_batch_solve
+ * (a plain handle: the volume, NULL offsets).  Allocates and frees the
+ * temporary handles; work runs on `stream`.  If the environment variable
+ * SMF_TUNE_CACHE names a file, the cache is loaded from it on first use and
+ * saved to it after new timings.  The cache is shared by all host threads
+ * (calls serialise on a lock).  SMF_ERR_ARG for a handle with a narrow band. */
 int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev, const int64_t *offsets_host,
                  void *stream);
 
-/* Gives every volume of `h` the cached period of its class, without timing
- * (volumes of unknown classes keep the handle's relabel_period). */
+/* Gives every volume of `h` the cached period of its class, and `h` the
+ * cached push phases of its largest class, without timing (volumes of
+ * unknown classes keep the handle's relabel_period). */
 int smf_tune_apply(smf_handle *h);
 
 /* Adds the entries of a tuning-cache text file (lines "kbits delta pbits
- * soft period best_ns"; lines "kbits delta pbits period best_ns" are
- * classes with soft = 0) to the cache, or writes the cache to one.
+ * soft period phases best_ns"; lines "kbits delta pbits soft period
+ * best_ns" are entries with one push phase, lines "kbits delta pbits period
+ * best_ns" classes with soft = 0) to the cache, or writes the cache to one.
  * SMF_ERR_ARG if the file cannot be opened. */
 int smf_tune_cache_load(const char *path);
 int smf_tune_cache_save(const char *path);

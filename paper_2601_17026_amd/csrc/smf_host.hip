@@ -35,7 +35,7 @@ void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, h
 void launch_bfs_begin(const Geom &g, hipStream_t st);
 void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, int c1, hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      int *Tout, int *LFout, const LevelRanges &R, hipStream_t st);
+                      int *Tout, int *LFout, const LevelRanges &R, const Inst *single, hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
 bool bfs_block_fits(const Geom &g);
 void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
@@ -210,10 +210,10 @@ struct smf_handle {
     int *part_up = nullptr;       // n
     int *fill_up = nullptr;       // n
     State st{};
-    Work work[2]{};               // push reads work[0] and writes work[1]; relabel the reverse
+    Work work[2]{};               // each phase reads one and fills the other (cur_work)
     unsigned long long work_bytes[3] = {};  // device byte counters after the last solve
     // parameters
-    int64_t relabel_period = 4;
+    int64_t relabel_period = 2;
     std::vector<int64_t> inst_period;       // per volume; 0: relabel_period
     int64_t max_sweeps = 2000000;
     int64_t poll_every = 1;
@@ -223,11 +223,14 @@ struct smf_handle {
     int64_t verbose = 0;           // 1: progress lines on stderr
     int64_t gap_every = 0;         // sweeps between gap searches (0: off)
     int64_t want_hmax = 0;         // 1: also read out the highest optimal surface
+    int64_t push_phases = 3;       // push phases per sweep (one relabel phase)
+    int cur_work = 0;              // work[cur_work] holds the columns of the next push phase
     bool hmax_ready = false;       // the last solve computed Hmax
 
     // results and counters of the last solve
     bool solved = false;
     std::vector<int64_t> flow, energy, inst_sweeps, inst_relabels, inst_gap;
+    int64_t pushes = 0;            // push phases of the running solve
     int64_t sweeps = 0, global_relabels = 0, bfs_passes = 0, mincut_passes = 0, gap_relabels = 0;
     int64_t gap_searches = 0;
     int64_t reset_nodes = 0;       // nodes swept by level-1 passes and fixups
@@ -558,7 +561,8 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         {
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
             for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L, cur ^= 1) {
-                launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], T[cur ^ 1], LF[cur ^ 1], R, s);
+                launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], T[cur ^ 1], LF[cur ^ 1], R,
+                                 n == 1 ? &h->inst[0] : nullptr, s);
                 h->bfs_passes++;
             }
         }
@@ -670,6 +674,8 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     for (int i = 0; i < n; ++i) period[i] = h->inst_period[i] > 0 ? h->inst_period[i] : h->relabel_period;
     // work lists: every column may hold excess anywhere before the first sweep
     launch_work_init(h->g, h->work[0], h->work[1], s);
+    h->cur_work = 0;
+    h->pushes = 0;
     // Sweeps are polled one batch behind, like the BFS levels: a batch
     // enqueued after the volumes have finished finds empty work lists.
     int slot = 0;
@@ -692,19 +698,25 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
                 for (int i = 0; i < n; ++i)
                     if (part[i]) since[i] = 0;
             }
-            // push clears work[1]'s list size; compaction clears work[0]'s
-            // and the active counts that the relabel phase fills
-            {
-                TimedScope ts(h->timer, KC_PUSH, s);
-                launch_push(h->g, h->st, h->work[0], h->work[1], h->scr, (h->sweeps & 1) == 0, s);
+            // each push phase reads the list of work[a] and marks work[a^1],
+            // whose list the compaction then builds (clearing the size of the
+            // list filled next, and the active counts); the relabel phase
+            // reads the last list and fills the other one
+            int a = h->cur_work;
+            for (int64_t j = 0; j < h->push_phases; ++j, a ^= 1) {
+                {
+                    TimedScope ts(h->timer, KC_PUSH, s);
+                    launch_push(h->g, h->st, h->work[a], h->work[a ^ 1], h->scr, (h->pushes++ & 1) == 0, s);
+                }
+                launch_compact(h->g, h->work[a ^ 1], h->work[a].count, s);
             }
-            launch_compact(h->g, h->work[1], h->work[0].count, s);
             {
                 TimedScope ts(h->timer, KC_RELABEL, s);
                 // a gap holds only for the labels it was found on: the
                 // relabel phase right after its search uses it, no later one
-                launch_relabel(h->g, h->st, h->work[1], h->work[0], gap_fresh, s);
+                launch_relabel(h->g, h->st, h->work[a], h->work[a ^ 1], gap_fresh, s);
             }
+            h->cur_work = a ^ 1;
             gap_fresh = false;
             h->sweeps++;
             for (int i = 0; i < n; ++i)
@@ -1056,6 +1068,11 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
         h->g.count_work = (int)value;
         return SMF_OK;
     }
+    else if (!strcmp(key, "push_phases")) {
+        if (value < 1 || value > 8) return fail(SMF_ERR_ARG, "smf_set_param: push_phases lies in [1, 8]");
+        h->push_phases = value;
+        return SMF_OK;
+    }
     else if (!strcmp(key, "hmax")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: hmax is 0 or 1");
         if (value && !h->Hmax) {
@@ -1131,6 +1148,8 @@ extern "C" int smf_get_stat(const smf_handle *h, const char *key, int64_t *out)
     else if (!strcmp(key, "columns")) *out = h->g.Ptot;
     else if (!strcmp(key, "nodes")) *out = h->g.Ntot;
     else if (!strcmp(key, "band")) *out = h->g.band;
+    else if (!strcmp(key, "push_phases")) *out = h->push_phases;
+    else if (!strcmp(key, "relabel_period")) *out = h->relabel_period;
     else if (!strncmp(key, "bytes.", 6)) {
         // algorithmic bytes of the last solve per kernel class: counted on the
         // device for the data-dependent kernels, by formula for the others

@@ -1041,9 +1041,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // the thresholds of columns next to a change plus the nodes it labels.
 //
 // Per-column BFS record, double-buffered by level parity (global columns):
-//   T[p]      threshold T_L(p) (K when no node of the column is labelled) in
-//             bits 0-30, and in bit 31 whether the record changed when
-//             level L was produced (so one load gives both);
+//   T[p]      threshold T_L(p) (the column's extent when no node of it is
+//             labelled) in bits 0-29, in bit 30 whether the down arc into
+//             (p, T_L(p)) carries flow (the one per-node fact the next level
+//             needs at the threshold), and in bit 31 whether the record
+//             changed when level L was produced (so one load gives all three);
 //   LF[k][p]  lowest z' >= T_L(p) whose lateral arc in direction k carries
 //             flow (K if none) -- the reverse-arc term seen by neighbour k;
 // Volumes that do not take part in a search keep CH = 0 on all their
@@ -1052,6 +1054,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 __device__ __forceinline__ int lat_head_of(int zp, int dl) { return zp == 0 ? 0 : zp - dl; }
 
 constexpr int kChanged = (int)0x80000000u;   // change flag of a threshold word
+constexpr int kFdAtT = 0x40000000;           // flow on the down arc into (p, T)
+constexpr int kTMask = 0x3fffffff;           // the threshold bits
 
 // Word w of bit mask m of column p.
 __device__ __forceinline__ unsigned long long mask_word(const Geom &g, int m, int w, int p)
@@ -1156,6 +1160,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         const int K = vc.I.K, nch = vc.I.nch, Kc = g.band ? g.bext[p] : K;
         const size_t base = vc.base(p);
         int t1 = Kc, la = Kc;
+        unsigned long long fd1 = 0;   // flow on the down arc into (p, t1)
         int lf[4] = {K, K, K, K};
         for (int cg = 0; cg < nch; cg += kInitGroup) {
             InitWords w[kInitGroup];
@@ -1182,7 +1187,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 if (lane < kMasks) g.bits[((size_t)lane * g.max_nch + c) * Ptot + p] = mine;
                 if (t1 == Kc) {
                     const unsigned long long sm = __ballot(in && w[j].ts > 0);
-                    if (sm) t1 = c * kWave + __ffsll((long long)sm) - 1;
+                    if (sm) {
+                        t1 = c * kWave + __ffsll((long long)sm) - 1;
+                        fd1 = (wm[kMaskFd] >> (t1 - c * kWave)) & 1ULL;
+                    }
                 }
                 const bool lab = in && z >= t1;
                 const int dv = w[j].d;
@@ -1227,7 +1235,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         // keeps the search from stopping early until a level reaches it
         if (la < t1) shortm |= 1ULL << (p - sbase);
         if (lane == 0) {
-            T[p] = t1 | kChanged;
+            T[p] = t1 | (fd1 ? kFdAtT : 0) | kChanged;
             g.low_act[p] = la;
 #pragma unroll
             for (int k = 0; k < 4; ++k) LF[(size_t)k * Ptot + p] = lf[k];
@@ -1255,7 +1263,7 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
         if (i < n) {
             const int p = g.short_list[i];
             ii = g.col_inst[p];
-            unsat = (T[p] & ~kChanged) > g.low_act[p];
+            unsat = (T[p] & kTMask) > g.low_act[p];
         }
         // list entries come in wave-sized runs of one volume's columns
         const int first = uniform(ii);
@@ -1277,10 +1285,12 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
 // arc heights and the column's extent from bc); lf[]
 // (the column's lowest flow-carrying lateral arc per direction at or above
 // its threshold) is lowered over the newly reached heights [cand, T) from
-// the bit masks.  Returns the mask words read.
+// the bit masks.  fdT: the down arc into (p, T) carries flow; fd_new gets
+// the same fact for the new threshold.  Returns the mask words read.
 template <bool kSoft>
 __device__ __forceinline__ int level_update(const Geom &g, int p, int K, const BandCol &bc, int alpha,
-                                           int T, const int tq[4], const int lq[4], int lf[4], int &cand)
+                                           int T, bool fdT, const int tq[4], const int lq[4], int lf[4],
+                                           int &cand, bool &fd_new)
 {
     cand = T;
     int words = 0;
@@ -1311,9 +1321,12 @@ __device__ __forceinline__ int level_update(const Geom &g, int p, int K, const B
             }
         }
     }
-    if (T >= 1 && T < bc.ext) {
+    if (fdT && T >= 1 && T < bc.ext) cand = min(cand, T - 1);
+    fd_new = fdT;
+    if (cand < T) {
+        // the word the scan below starts in holds the new threshold's bit
         ++words;
-        if ((mask_word(g, kMaskFd, T >> 6, p) >> (T & 63)) & 1ULL) cand = min(cand, T - 1);
+        fd_new = (mask_word(g, kMaskFd, cand >> 6, p) >> (cand & 63)) & 1ULL;
     }
     // an lf below T was found in an earlier word
     for (int w = cand >> 6; cand < T && w <= (T - 1) >> 6; ++w) {
@@ -1393,46 +1406,48 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
 
 // One column's step of level L -> L+1: reads the threshold words of column
 // p and of its neighbours from Tin (P columns per array), sets T (the old
-// threshold), cand (the new one when the column moved) and `self` (the
-// column changed at level L-1), and returns whether the threshold moved.
-// The change flags in the threshold words give the frontier: with no change
-// at level L-1 around p none of p's inputs moved, and both record buffers
-// already hold p's record, so only a column next to a change loads its
-// lowest-flow record lf[] and its neighbours' words of it (LFin) and scans
-// its masks.  `bytes` gets the column's algorithmic bytes: its own threshold
+// threshold), cand (the new one when the column moved), `self` (the column
+// changed at level L-1) and tword (the column's threshold word for Tout),
+// and returns whether the threshold moved.  The change flags in the
+// threshold words give the frontier: with no change at level L-1 around p
+// none of p's inputs moved, and both record buffers already hold p's
+// record.  The lowest-flow records lf[] of the column and lq[] of its
+// neighbours (LFin) are loaded in the same round as the threshold words, so
+// that a column next to a change waits for one round of loads before its
+// mask scan; `bytes` counts the column's algorithmic bytes: its threshold
 // word read and rewritten, and when near a change its 16-byte record and the
-// mask words scanned.  Neighbours' words are their own records, counted with
-// their own column.
+// mask words scanned (a quiet column does not need its record; neighbours'
+// words are their own records, counted with their own column).
 template <bool kSoft>
 __device__ __forceinline__ bool column_step(const Geom &g, const Col &col, int p, const int *Tin,
                                             const int *LFin, int P, int &T, int &cand, int lf[4],
-                                            bool &self, long long &bytes)
+                                            bool &self, int &tword, long long &bytes)
 {
     const int K = col.I.K;
-    int q[4], tq[4];
+    int q[4], tq[4], lq[4];
     const int tw = Tin[p];
-    self = tw < 0;
-    T = tw & ~kChanged;
-    bool near = self;
+    bool near = tw < 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         q[k] = nbr(col.I.nx, col.I.ny, col.x, col.y, p, k);
         const int w = q[k] >= 0 ? Tin[q[k]] : -1;
+        lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
+        lf[k] = LFin[(size_t)k * P + p];
         near = near || (q[k] >= 0 && w < 0);
-        tq[k] = q[k] >= 0 ? (w & ~kChanged) : -1;
+        tq[k] = q[k] >= 0 ? (w & kTMask) : -1;
     }
+    self = tw < 0;
+    T = tw & kTMask;
+    tword = tw & ~kChanged;
     bytes = 8;
     cand = T;
     if (!near) return false;
-    int lq[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        lq[k] = q[k] >= 0 ? LFin[(size_t)(k ^ 1) * P + q[k]] : K;
-        lf[k] = LFin[(size_t)k * P + p];
-    }
     BandCol bc;
     band_col(g, p, q, K, col.I.delta, bc);
-    bytes += 16 + 8 * level_update<kSoft>(g, p, K, bc, col.I.alpha, T, tq, lq, lf, cand);
+    bool fd_new = false;
+    bytes += 16 + 8 * level_update<kSoft>(g, p, K, bc, col.I.alpha, T, (tw & kFdAtT) != 0, tq, lq, lf,
+                                          cand, fd_new);
+    if (cand < T) tword = cand | (fd_new ? kFdAtT : 0) | kChanged;
     return cand < T;
 }
 
@@ -1444,7 +1459,7 @@ template <bool kSoft>
 __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d, int L,
                                                    const int *__restrict__ Tin,
                                                    const int *__restrict__ LFin, int *__restrict__ Tout,
-                                                   int *__restrict__ LFout, LevelRanges R)
+                                                   int *__restrict__ LFout, LevelRanges R, Inst I0, int single)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     // the flags of the next level are cleared here; stream order puts this
@@ -1456,26 +1471,34 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
     const bool valid = t < R.pre[R.n];
     const int p = valid ? R.lo[r] + (t - R.pre[r]) : 0;
     bool self = false, need = false;
-    int T = 0, cand = 0, ii = 0;
+    int T = 0, cand = 0, ii = 0, tword = 0;
     long long base = 0;
     int lf[4] = {0, 0, 0, 0};
     long long bytes = 0;
     if (valid) {
-        const Col col = column(g, p);
+        // a single volume's geometry comes with the launch (no table loads
+        // ahead of the column's own)
+        const Col col = single ? column_in(I0, 0, p) : column(g, p);
         ii = col.ii;
         base = (long long)col.base;
-        need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, bytes);
+        need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, tword, bytes);
     }
     if (valid) {
-        Tout[p] = need ? (cand | kChanged) : T;
+        Tout[p] = tword;
         if (need || self) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) LFout[(size_t)k * P + p] = lf[k];
             bytes += 16;
         }
     }
-    // level L labelled something in the volumes of the lanes with `need`
-    set_level_flag(g, ii, need, L % kLvlSlots);
+    // level L labelled something in the volumes of the lanes with `need`:
+    // for a single volume one store per block (thousands of waves storing to
+    // one word serialise in the memory system), else per volume and wave
+    if (single) {
+        if (__syncthreads_or(need) && threadIdx.x == 0) g.is[0].lvl_changed[L % kLvlSlots] = 1;
+    } else {
+        set_level_flag(g, ii, need, L % kLvlSlots);
+    }
     bytes += label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, base);
     if (g.count_work) count_bytes(g, 0, bytes);
 }
@@ -1524,14 +1547,14 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
             const int p = slot * (int)blockDim.x + (int)threadIdx.x;
             const bool valid = p < P;
             bool self = false, need = false;
-            int T = 0, cand = 0;
+            int T = 0, cand = 0, tword = 0;
             long long base = 0, b = 0;
             int lf[4] = {0, 0, 0, 0};
             if (valid) {
                 const Col col = column_in(I, 0, p);
                 base = (long long)col.base;
-                need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, b);
-                Tout[p] = need ? (cand | kChanged) : T;
+                need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, tword, b);
+                Tout[p] = tword;
                 if (need || self)
 #pragma unroll
                     for (int k = 0; k < 4; ++k) LFout[(size_t)k * P + p] = lf[k];
@@ -1549,7 +1572,7 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
         if (early_stop) {
             bool short_col = false;
             for (int p = threadIdx.x; p < P; p += blockDim.x)
-                short_col = short_col || (sT[cur ^ 1][p] & ~kChanged) > g.low_act[p];
+                short_col = short_col || (sT[cur ^ 1][p] & kTMask) > g.low_act[p];
             if (!__syncthreads_or(short_col)) {
                 ++L;   // levels <= L are done: unreached nodes lie beyond L + 1
                 break;
@@ -1840,17 +1863,19 @@ void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st)
 }
 
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      int *Tout, int *LFout, const LevelRanges &R, hipStream_t st)
+                      int *Tout, int *LFout, const LevelRanges &R, const Inst *single, hipStream_t st)
 {
     const long long cols = R.pre[R.n];
     const long long n = cols > g.n ? cols : g.n;
     const int b = g.level_block;
+    const Inst I0 = single ? *single : Inst{};
+    const int one = single ? 1 : 0;
     if (g.soft)
         hipLaunchKernelGGL(k_bfs_level<true>, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d,
-                           L, Tin, LFin, Tout, LFout, R);
+                           L, Tin, LFin, Tout, LFout, R, I0, one);
     else
         hipLaunchKernelGGL(k_bfs_level<false>, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, g, sv.d,
-                           L, Tin, LFin, Tout, LFout, R);
+                           L, Tin, LFin, Tout, LFout, R, I0, one);
 }
 
 // Deep columns make a level of one block longer than a level launched

@@ -10,9 +10,9 @@
 // handed to kernels.
 //
 // The kernels are those of smf_solve.  The host driver here runs the same
-// method with the default schedule (a global relabel every 4 sweeps, search
-// levels polled every 16, early-stopping searches, one-block searches for
-// small volumes) and no soft smoothness term; it reads the device counters
+// method with the default schedule (sweeps of three push phases and one
+// relabel phase, a global relabel every 2 sweeps, search levels polled every
+// 16, early-stopping searches, one-block searches for small volumes) and no soft smoothness term; it reads the device counters
 // with blocking copies into a stack buffer instead of pinned snapshots, so
 // it uses no events and no pinned memory.  Every call on a GPU shares that
 // GPU's array and leaves its contents behind; every word a solve reads is
@@ -35,7 +35,7 @@ void launch_build(const int *cost, const Geom &g, const State &sv, Scratch *s, h
 void launch_bfs_begin(const Geom &g, hipStream_t st);
 void launch_bfs_init(const Geom &g, const State &sv, int *T, int *LF, int c0, int c1, hipStream_t st);
 void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, const int *LFin,
-                      int *Tout, int *LFout, const LevelRanges &R, hipStream_t st);
+                      int *Tout, int *LFout, const LevelRanges &R, const Inst *single, hipStream_t st);
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
 bool bfs_block_fits(const Geom &g);
 void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
@@ -61,7 +61,8 @@ static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 namespace {
 
 constexpr int kMaxDevices = 64;
-constexpr int kPeriod = 4;             // sweeps between global relabels
+constexpr int kPeriod = 2;             // sweeps between global relabels
+constexpr int kPushPhases = 3;         // push phases per sweep
 constexpr int kLevelsPerPoll = 16;     // search levels between host checks
 constexpr long long kMaxSweeps = 2000000;
 constexpr long long kMaxInstNodes = (1LL << 30) - 2;
@@ -124,6 +125,7 @@ struct Run {
     int *LF[2] = {};
     hipStream_t s = nullptr;
     long long N = 0;
+    Inst I{};   // the volume (also handed to every level launch)
     // counters read by the last poll
     alignas(8) unsigned char snap[kScratchHead + sizeof(InstScratch)];
     const Scratch &host() const { return *reinterpret_cast<const Scratch *>(snap); }
@@ -170,7 +172,7 @@ int search(Run &r)
     int L = 1, cur = 1, fill = kInf;
     for (int npoll = 0;; ++npoll) {
         for (int i = 0; i < kLevelsPerPoll; ++i, ++L, cur ^= 1)
-            launch_bfs_level(g, r.st, L, r.T[cur], r.LF[cur], r.T[cur ^ 1], r.LF[cur ^ 1], R, r.s);
+            launch_bfs_level(g, r.st, L, r.T[cur], r.LF[cur], r.T[cur ^ 1], r.LF[cur ^ 1], R, &r.I, r.s);
         launch_bfs_count(g, r.T[cur], npoll & 1, r.s);
         const int rc = poll(r);
         if (rc) return rc;
@@ -198,7 +200,8 @@ int solve(Run &r, const int32_t *cost, int32_t *surface, int64_t *flow_out, int6
     int rc = search(r);
     if (rc) return rc;
     launch_work_init(g, r.work[0], r.work[1], r.s);
-    int since = 0;
+    int since = 0, cur = 0;
+    long long pushes = 0;
     for (long long sweeps = 0;; ++sweeps) {
         if (sweeps >= kMaxSweeps) return set_error_text(SMF_ERR_NOT_CONVERGED, "smf_solve_noalloc: sweep cap reached");
         if (since >= kPeriod) {
@@ -206,10 +209,15 @@ int solve(Run &r, const int32_t *cost, int32_t *surface, int64_t *flow_out, int6
             if (rc) return rc;
             since = 0;
         }
-        // push (labels fixed), list of the columns it marked, relabel (flows fixed)
-        launch_push(g, r.st, r.work[0], r.work[1], r.scr, (sweeps & 1) == 0, r.s);
-        launch_compact(g, r.work[1], r.work[0].count, r.s);
-        launch_relabel(g, r.st, r.work[1], r.work[0], false, r.s);
+        // push phases (labels fixed), each followed by the list of the
+        // columns it marked, then relabel (flows fixed); the lists alternate
+        int a = cur;
+        for (int j = 0; j < kPushPhases; ++j, a ^= 1) {
+            launch_push(g, r.st, r.work[a], r.work[a ^ 1], r.scr, (pushes++ & 1) == 0, r.s);
+            launch_compact(g, r.work[a ^ 1], r.work[a].count, r.s);
+        }
+        launch_relabel(g, r.st, r.work[a], r.work[a ^ 1], false, r.s);
+        cur = a ^ 1;
         ++since;
         rc = poll(r);
         if (rc) return rc;
@@ -270,7 +278,7 @@ extern "C" int smf_solve_noalloc(const int32_t *cost_dev, int32_t nx, int32_t ny
     Run r;
     r.s = (hipStream_t)stream;
     r.N = N;
-    Inst I{};
+    Inst &I = r.I;
     I.nx = nx; I.ny = ny; I.K = K; I.delta = delta;
     I.P = (int)P;
     I.nch = nch;

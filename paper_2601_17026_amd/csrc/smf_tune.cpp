@@ -1,16 +1,18 @@
-// Autotuner of the solver's relabel period (include/smf.h, smf_autotune).
+// Autotuner of the solver's schedule (include/smf.h, smf_autotune): the
+// relabel period and the push phases per sweep.
 //
 // The frequency of global relabelling trades the cost of one search against
 // the sweeps it saves; the paper settles it empirically (Section 3.4, the
-// relabel factor of the global-relabel sweep).  Here the period is chosen
-// per class of volume -- key (ceil log2 K, min(delta, 4), floor log2 of the
-// column count, whether the soft smoothness weight is positive) -- by
-// timing complete solves of the largest volume of each class with every
-// candidate period (the fastest of three runs for short solves), and
-// remembered in a process-wide cache that can be saved to and loaded from a
-// text file (one line per class: "kbits delta pbits soft period best_ns";
-// lines of five fields, written before the soft flag existed, are classes
-// without the soft term).
+// relabel factor of the global-relabel sweep).  Push phases between relabel
+// phases move excess more hops per sweep.  Here the pair is chosen per class
+// of volume -- key (ceil log2 K, min(delta, 4), floor log2 of the column
+// count, whether the soft smoothness weight is positive) -- by timing
+// complete solves of the largest volume of each class with every candidate
+// pair (the fastest of three runs for short solves), and remembered in a
+// process-wide cache that can be saved to and loaded from a text file (one
+// line per class: "kbits delta pbits soft period phases best_ns"; lines of
+// six fields are entries with one push phase, lines of five fields entries
+// without the soft flag).
 //
 // The tuner is a client of the C-ABI: it solves the representative volume
 // on a temporary handle of its own and writes the chosen periods into the
@@ -39,6 +41,7 @@ using Key = std::tuple<int, int, int, int>;
 
 struct Choice {
     int64_t period;
+    int64_t phases;
     int64_t best_ns;
 };
 
@@ -46,7 +49,9 @@ std::mutex g_mu;
 std::map<Key, Choice> g_cache;
 bool g_env_loaded = false;
 
-const int64_t kCandidates[] = {2, 3, 4, 6, 8, 12};
+// (relabel period, push phases) pairs: the measured optima of the 32x32x64,
+// 256^3 and 512x512x384 workloads lie among them
+const int64_t kCandidates[][2] = {{4, 1}, {2, 2}, {1, 3}, {2, 3}, {3, 3}, {1, 4}, {2, 4}};
 // scale factors 1, 1.5, 2 and 3 (doubled) of the whole-batch step
 const int kBatchScale2[] = {2, 3, 4, 6};
 // Repeats per candidate: the run-to-run spread of a solve is a few
@@ -83,8 +88,9 @@ int load_locked(const char *path)
         int a, b, c, d;
         long long v[3];
         const int got = sscanf(line, "%d %d %d %d %lld %lld %lld", &a, &b, &c, &d, &v[0], &v[1], &v[2]);
-        if (got == 6 && v[0] >= 1) g_cache[Key(a, b, c, d)] = Choice{v[0], v[1]};
-        else if (got == 5 && (long long)d >= 1) g_cache[Key(a, b, c, 0)] = Choice{d, v[0]};
+        if (got == 7 && v[0] >= 1 && v[1] >= 1 && v[1] <= 8) g_cache[Key(a, b, c, d)] = Choice{v[0], v[1], v[2]};
+        else if (got == 6 && v[0] >= 1) g_cache[Key(a, b, c, d)] = Choice{v[0], 1, v[1]};
+        else if (got == 5 && (long long)d >= 1) g_cache[Key(a, b, c, 0)] = Choice{d, 1, v[0]};
     }
     fclose(f);
     return SMF_OK;
@@ -95,9 +101,9 @@ int save_locked(const char *path)
     FILE *f = fopen(path, "w");
     if (!f) return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_save: cannot open ") + path);
     for (const auto &kv : g_cache)
-        fprintf(f, "%d %d %d %d %lld %lld\n", std::get<0>(kv.first), std::get<1>(kv.first),
+        fprintf(f, "%d %d %d %d %lld %lld %lld\n", std::get<0>(kv.first), std::get<1>(kv.first),
                 std::get<2>(kv.first), std::get<3>(kv.first), (long long)kv.second.period,
-                (long long)kv.second.best_ns);
+                (long long)kv.second.phases, (long long)kv.second.best_ns);
     if (fclose(f) != 0)
         return smf::set_error(SMF_ERR_ARG, std::string("smf_tune_cache_save: cannot write ") + path);
     return SMF_OK;
@@ -126,16 +132,38 @@ int shapes_of(smf_handle *h, std::vector<int64_t> s[5])
     return SMF_OK;
 }
 
-// Periods for the handle's volumes from the cache (0 where no entry).
-std::vector<int64_t> periods_locked(const std::vector<int64_t> s[5])
+// Periods for the handle's volumes from the cache (0 where no entry), and
+// the push phases of the cached class holding the most nodes (0 if none).
+std::vector<int64_t> periods_locked(const std::vector<int64_t> s[5], int64_t *phases)
 {
     std::vector<int64_t> out(s[0].size(), 0);
+    std::map<Key, int64_t> nodes;
     for (size_t i = 0; i < out.size(); ++i) {
-        auto it = g_cache.find(key_of((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i],
-                                      (int32_t)s[3][i], s[4][i]));
-        if (it != g_cache.end()) out[i] = it->second.period;
+        const Key k = key_of((int32_t)s[0][i], (int32_t)s[1][i], (int32_t)s[2][i], (int32_t)s[3][i], s[4][i]);
+        auto it = g_cache.find(k);
+        if (it == g_cache.end()) continue;
+        out[i] = it->second.period;
+        nodes[k] += s[0][i] * s[1][i] * s[2][i];
     }
+    *phases = 0;
+    int64_t most = -1;
+    for (const auto &kv : nodes)
+        if (kv.second > most) {
+            most = kv.second;
+            *phases = g_cache[kv.first].phases;
+        }
     return out;
+}
+
+// The cached choices into the handle: per-volume periods, and the push
+// phases (one value for the whole handle) of its largest cached class.
+int apply_locked(smf_handle *h, const std::vector<int64_t> s[5])
+{
+    int64_t phases = 0;
+    const std::vector<int64_t> per = periods_locked(s, &phases);
+    const int rc = smf_batch_set_param(h, "relabel_period", per.data());
+    if (rc || phases < 1) return rc;
+    return smf_set_param(h, "push_phases", phases);
 }
 
 }  // namespace
@@ -177,10 +205,12 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
         const int32_t *cost = packed_cost_dev + off[i];
         rc = smf_set_param(t, "smooth_weight", s[4][i]);
         if (!rc) rc = smf_solve(t, cost, stream);   // warm-up
-        Choice best{0, 0};
-        for (int64_t p : kCandidates) {
+        Choice best{0, 0, 0};
+        for (const auto &cand : kCandidates) {
             if (rc) break;
+            const int64_t p = cand[0], m = cand[1];
             rc = smf_set_param(t, "relabel_period", p);
+            if (!rc) rc = smf_set_param(t, "push_phases", m);
             if (rc) break;
             int64_t ns = -1;
             for (int rep = 0; rep < 3 && !rc; ++rep) {
@@ -191,7 +221,7 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
                 ns = ns < 0 ? d : std::min(ns, d);
                 if (d >= kLongSolveNs || (rep == 1 && d >= kShortSolveNs)) break;
             }
-            if (!rc && (best.period == 0 || ns < best.best_ns)) best = Choice{p, ns};
+            if (!rc && (best.period == 0 || ns < best.best_ns)) best = Choice{p, m, ns};
         }
         smf_destroy(t);
         if (rc) return rc;
@@ -199,8 +229,7 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
     }
     const char *path = getenv("SMF_TUNE_CACHE");
     if (path && *path && !todo.empty()) (void)save_locked(path);
-    const std::vector<int64_t> per = periods_locked(s);
-    rc = smf_batch_set_param(h, "relabel_period", per.data());
+    rc = apply_locked(h, s);
     if (rc || n == 1) return rc;
     // The volumes of a batch share their searches (a level costs one launch
     // however many volumes take part), which favours longer periods than
@@ -241,8 +270,7 @@ extern "C" int smf_tune_apply(smf_handle *h)
     if (rc) return rc;
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_locked();
-    const std::vector<int64_t> per = periods_locked(s);
-    return smf_batch_set_param(h, "relabel_period", per.data());
+    return apply_locked(h, s);
 }
 
 extern "C" int smf_tune_cache_load(const char *path)

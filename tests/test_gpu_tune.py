@@ -1,7 +1,9 @@
-"""GPU checks of the relabel-period autotuner (smf_autotune): it picks a
-candidate period per volume class, applies it (scaled by one factor chosen
-on the whole batch) to every volume of the class, the cache round-trips
-through a file, and tuned solves stay exact."""
+"""GPU checks of the schedule autotuner (smf_autotune): it picks a candidate
+(relabel period, push phases) pair per volume class, applies the period
+(scaled by one factor chosen on the whole batch) to every volume of the
+class and the push phases of the largest class to the handle, the cache
+round-trips through a file (old entries without push phases load with one),
+and tuned solves stay exact."""
 import numpy as np
 import pytest
 
@@ -11,7 +13,8 @@ from paper_2601_17026_amd import synth
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-CANDIDATES = {2, 3, 4, 6, 8, 12}
+CANDIDATES = {1, 2, 3, 4}            # periods of the candidate pairs
+PHASES = {1, 2, 3, 4}
 
 
 @pytest.fixture(scope="module")
@@ -59,6 +62,16 @@ def test_autotune_batch(smf, tmp_path):
     with smf.BatchSolver(shapes[:1]) as b1:
         smf.tune_apply(b1)
         assert b1.stat_per_volume("relabel_period") == [classes[0]]
+        assert b1.stat("push_phases") in PHASES
+    lines = [line.split() for line in open(path).read().splitlines()]
+    assert all(len(f) == 7 and int(f[5]) in PHASES for f in lines)
+    # an entry written without push phases loads with one push phase
+    legacy = tmp_path / "legacy.txt"
+    legacy.write_text(" ".join(lines[0][:5] + lines[0][6:]) + "\n")
+    smf.tune_cache_clear()
+    smf.tune_cache_load(str(legacy))
+    smf.tune_cache_save(path)
+    assert open(path).read().split()[5] == "1"
 
 
 def test_autotune_plain_handle(smf):
@@ -69,6 +82,7 @@ def test_autotune_plain_handle(smf):
         print("case: autotune of a plain handle", flush=True)
         smf.autotune(s, c)
         assert smf.tune_lookup(*cost.shape, delta) in CANDIDATES
+        assert s.stat("push_phases") in PHASES
         s.solve(c)
         r = oracle.solve(cost, delta)
         assert s.flow_value() == r.flow and s.energy() == r.energy

@@ -111,7 +111,7 @@ def test_tune_cache_roundtrip_without_gpu(tmp_path):
     dst = tmp_path / "out.txt"
     assert lib.smf_tune_cache_save(str(dst).encode()) == 0
     assert sorted(dst.read_text().split("\n")) == sorted(
-        ["", "7 2 14 0 8 12345", "7 2 14 1 4 777", "9 4 18 0 3 999"])
+        ["", "7 2 14 0 8 1 12345", "7 2 14 1 4 1 777", "9 4 18 0 3 1 999"])
     assert lib.smf_tune_cache_load(str(tmp_path / "missing.txt").encode()) == -1
     assert b"cannot open" in lib.smf_last_error()
     out = ctypes.c_int64()
