@@ -497,68 +497,105 @@ static bool shrink_cover(const smf_handle *h, const std::vector<char> &live, std
     return true;
 }
 
-static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> &part, bool complete = false)
-{
-    const int n = h->n;
-    // a complete search runs until a level labels nothing, whatever
-    // bfs_early_stop says
-    const int64_t early_stop = complete ? 0 : h->bfs_early_stop;
-    const size_t P = (size_t)h->g.Ptot;
-    int *T[2] = {h->bfs, h->bfs + 5 * P};
-    int *LF[2] = {h->bfs + P, h->bfs + 6 * P};
-    // the searches' launches cover the columns [c0, c1) spanned by the
-    // volumes that take part (volumes are packed in order)
-    int c0 = h->g.Ptot, c1 = 0;
-    for (int i = 0; i < n; ++i) {
-        h->part_up[i] = part[i] ? 1 : 0;
-        if (part[i]) {
-            h->reset_nodes += h->inst[i].N;
-            h->reset_chunks += (int64_t)h->inst[i].P * h->inst[i].nch;
-            c0 = std::min(c0, h->inst[i].col_base);
-            c1 = std::max(c1, h->inst[i].col_base + h->inst[i].P);
-        }
-    }
-    if (c0 >= c1) return SMF_OK;
-    // The levels cover the volumes of [c0, c1) that take part (others only
-    // where more than kMaxRanges column ranges would be needed); a volume
-    // whose search has ended drops out of the later levels, with its fill
-    // label fixed when it leaves (fill_out).
-    std::vector<char> live(part.begin(), part.end()), cover((size_t)n, 0);
-    std::vector<int> fill_out((size_t)n, -1);
-    for (int i = 0; i < n; ++i)
-        cover[i] = h->inst[i].col_base >= c0 && h->inst[i].col_base < c1;
-    LevelRanges R;
-    if (!shrink_cover(h, live, cover, R))
-        return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
-    HIP_TRY(hipMemcpyAsync(h->part_dev, h->part_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
-    launch_bfs_begin(h->g, s);
-    launch_set_int(&h->scr->short_count, 0, s);
+// One global relabel (reverse breadth-first search from t) of the volumes
+// with part[i], as a resumable state on one stream: begin() enqueues level 1
+// (or, for a small single volume, the whole search in one block), step() the
+// next batch of bfs_poll_every levels with the early-stop count and a
+// counter snapshot, examine() reads the oldest snapshot in flight and
+// decides which volumes' searches have ended, and finish() enqueues the
+// fix-up.  A volume's search ends when a level labelled nothing in it (exact
+// distances: unreached nodes get kInf) or, with early stop, when every node
+// holding excess is labelled (unreached nodes get the first level not run, a
+// valid lower bound).  The host reads the counters one batch of levels
+// behind the device, so the device never waits for the host; levels after a
+// volume's search ended are no-ops for it, or label more nodes exactly.
+struct Search {
+    smf_handle *h = nullptr;
+    hipStream_t s = nullptr;
+    int64_t early_stop = 0;
+    std::vector<char> part, live, cover;
+    std::vector<int> fill_out;
+    LevelRanges R{};
+    int c0 = 0, c1 = 0;
+    int L = 1, cur = 1, slot = 0, npoll = 0, inflight = 0;
+    int Lsnap[2] = {0, 0}, Csnap[2] = {0, 0};
+    bool whole = false;   // nothing to do, or the one-block search already ran
+    int *T[2] = {}, *LF[2] = {};
+
+    int begin(smf_handle *hh, hipStream_t ss, const std::vector<char> &p, bool complete)
     {
-        TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_init(h->g, h->st, T[1], LF[1], c0, c1, s);   // level 1 lives in buffer 1
-    }
-    if (h->block_search && bfs_block_fits(h->g)) {
-        // a small single volume: the whole search in one block, no polls
-        {
-            TimedScope ts(h->timer, KC_BFS, s);
-            launch_bfs_block(h->g, h->st, T[1], LF[1], (int)early_stop,
-                             (int)std::min<int64_t>(h->max_inst_nodes + 2, INT32_MAX), h->scr, s);
+        h = hh;
+        s = ss;
+        const int n = h->n;
+        // a complete search runs until a level labels nothing, whatever
+        // bfs_early_stop says
+        early_stop = complete ? 0 : h->bfs_early_stop;
+        const size_t P = (size_t)h->g.Ptot;
+        T[0] = h->bfs;
+        T[1] = h->bfs + 5 * P;
+        LF[0] = h->bfs + P;
+        LF[1] = h->bfs + 6 * P;
+        part = p;
+        L = 1;
+        cur = 1;
+        slot = 0;
+        npoll = 0;
+        inflight = 0;
+        whole = false;
+        // the launches cover the columns [c0, c1) spanned by the volumes that
+        // take part (volumes are packed in order)
+        c0 = h->g.Ptot;
+        c1 = 0;
+        for (int i = 0; i < n; ++i) {
+            h->part_up[i] = part[i] ? 1 : 0;
+            if (part[i]) {
+                h->reset_nodes += h->inst[i].N;
+                h->reset_chunks += (int64_t)h->inst[i].P * h->inst[i].nch;
+                c0 = std::min(c0, h->inst[i].col_base);
+                c1 = std::max(c1, h->inst[i].col_base + h->inst[i].P);
+            }
         }
-        HIP_TRY(hipGetLastError());
-        h->inst_relabels[0]++;
-        h->global_relabels++;
+        if (c0 >= c1) {
+            whole = true;
+            return SMF_OK;
+        }
+        // The levels cover the volumes of [c0, c1) that take part (others
+        // only where more than kMaxRanges column ranges would be needed); a
+        // volume whose search has ended drops out of the later levels, with
+        // its fill label fixed when it leaves (fill_out).
+        live.assign(part.begin(), part.end());
+        cover.assign((size_t)n, 0);
+        fill_out.assign((size_t)n, -1);
+        for (int i = 0; i < n; ++i)
+            cover[i] = h->inst[i].col_base >= c0 && h->inst[i].col_base < c1;
+        if (!shrink_cover(h, live, cover, R))
+            return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
+        HIP_TRY(hipMemcpyAsync(h->part_dev, h->part_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
+        launch_bfs_begin(h->g, s);
+        launch_set_int(&h->scr->short_count, 0, s);
+        {
+            TimedScope ts(h->timer, KC_BFS_RESET, s);
+            launch_bfs_init(h->g, h->st, T[1], LF[1], c0, c1, s);   // level 1 lives in buffer 1
+        }
+        if (h->block_search && bfs_block_fits(h->g)) {
+            // a small single volume: the whole search in one block, no polls
+            {
+                TimedScope ts(h->timer, KC_BFS, s);
+                launch_bfs_block(h->g, h->st, T[1], LF[1], (int)early_stop,
+                                 (int)std::min<int64_t>(h->max_inst_nodes + 2, INT32_MAX), h->scr, s);
+            }
+            HIP_TRY(hipGetLastError());
+            whole = true;
+        }
         return SMF_OK;
     }
-    // The host reads the counters one batch of levels behind the device:
-    // batch k+1 is enqueued before batch k's snapshot is examined, so the
-    // device never waits for the host.  Levels after a volume's search has
-    // ended are no-ops for it, or label more nodes exactly.
-    int L = 1, cur = 1, slot = 0, Lsnap[2] = {0, 0}, Csnap[2] = {0, 0};   // slot: 0 or 1 of this loop's pair
-    int npoll = 0;
-    bool inflight = false;
-    for (;;) {
-        // cur: the record buffer that holds every column's record of level L
+
+    // Enqueues the next batch of levels, the early-stop count and a snapshot.
+    int step()
+    {
+        const int n = h->n;
         {
+            // cur: the record buffer that holds every column's record of level L
             TimedScope ts(h->timer, KC_BFS, s, (int)h->bfs_poll_every);
             for (int64_t i = 0; i < h->bfs_poll_every; ++i, ++L, cur ^= 1) {
                 launch_bfs_level(h->g, h->st, L, T[cur], LF[cur], T[cur ^ 1], LF[cur ^ 1], R,
@@ -569,68 +606,133 @@ static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> 
         // this poll's count goes to bfs_unsat[npoll & 1]
         if (early_stop) launch_bfs_count(h->g, T[cur], npoll & 1, s);
         HIP_TRY(hipGetLastError());
-        int rc = post_snapshot(h, s, kSlotBfs + slot);
+        const int sl = (slot + inflight) & 1;
+        const int rc = post_snapshot(h, s, kSlotBfs + sl);
         if (rc) return rc;
-        Lsnap[slot] = L;
-        Csnap[slot] = npoll++ & 1;
-        if (inflight) {
-            rc = wait_snapshot(h, kSlotBfs + (slot ^ 1));
-            if (rc) return rc;
-            // at that snapshot the last level launched had produced level Lp
-            const int Lp = Lsnap[slot ^ 1];
-            bool all = true, ended = false;
-            for (int i = 0; i < n; ++i) {
-                if (!live[i]) continue;
-                const InstScratch &r = h->is_host[i];
-                const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
-                const bool labelled = early_stop && r.bfs_unsat[Csnap[slot ^ 1]] == 0;
-                if (complete || labelled) {
-                    live[i] = 0;
-                    ended = true;
-                    // levels < L have run over it: unreached nodes are > L away
-                    fill_out[i] = complete ? kInf : L + 1;
-                } else {
-                    all = false;
-                }
-            }
-            if (all) {
-                // levels < L are complete now (the batch after the snapshot
-                // included); a volume still covered takes the latest fill
-                for (int i = 0; i < n; ++i) {
-                    const bool complete = !h->is_host[i].lvl_changed[(Lp - 1) % kLvlSlots];
-                    h->fill_up[i] = !part[i] ? -1 : !cover[i] ? fill_out[i] : (complete ? kInf : L + 1);
-                }
-                break;
-            }
-            if (ended && !shrink_cover(h, live, cover, R))
-                return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
-        }
-        inflight = true;
-        slot ^= 1;
+        Lsnap[sl] = L;
+        Csnap[sl] = npoll++ & 1;
+        ++inflight;
         // every productive level lowers at least one threshold by >= 1
         if ((int64_t)L > h->max_inst_nodes + 2 + 2 * h->bfs_poll_every)
             return fail(SMF_ERR_NOT_CONVERGED, "smf_solve: breadth-first search did not settle");
+        return SMF_OK;
     }
-    HIP_TRY(hipMemcpyAsync(h->fill_dev, h->fill_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
+
+    // The oldest snapshot in flight is complete (hipEventQuery).
+    bool ready() const { return inflight > 0 && hipEventQuery(h->snap_ev[kSlotBfs + slot]) == hipSuccess; }
+
+    // Waits for the oldest snapshot in flight and decides which volumes'
+    // searches have ended; all: every volume's search has ended (the fill
+    // labels are then set in fill_up).
+    int examine(bool &all)
     {
-        TimedScope ts(h->timer, KC_BFS_RESET, s);
-        launch_bfs_fixup(h->g, h->st, c0, c1, s);
-    }
-    if (h->verbose) {
-        int npart = 0, act = 0, lab = 0;
-        for (int i = 0; i < n; ++i)
-            if (part[i]) {
-                ++npart;
-                act += h->is_host[i].bfs_active;
-                lab += std::min(h->is_host[i].bfs_unsat[0], h->is_host[i].bfs_unsat[1]);
+        const int n = h->n;
+        all = false;
+        const int rc = wait_snapshot(h, kSlotBfs + slot);
+        if (rc) return rc;
+        // at that snapshot the last level launched had produced level Lp
+        const int Lp = Lsnap[slot], cslot = Csnap[slot];
+        slot ^= 1;
+        --inflight;
+        bool ended = false;
+        all = true;
+        for (int i = 0; i < n; ++i) {
+            if (!live[i]) continue;
+            const InstScratch &r = h->is_host[i];
+            const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
+            const bool labelled = early_stop && r.bfs_unsat[cslot] == 0;
+            if (complete || labelled) {
+                live[i] = 0;
+                ended = true;
+                // levels < L have run over it: unreached nodes are > L away
+                fill_out[i] = complete ? kInf : L + 1;
+            } else {
+                all = false;
             }
-        fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d volumes, %d levels, active %d, columns short %d\n",
-                (long long)h->global_relabels, (long long)h->sweeps, npart, L - 1, act, lab);
+        }
+        if (all) {
+            // levels < L are complete now (the batches after the snapshot
+            // included); a volume still covered takes the latest fill
+            for (int i = 0; i < n; ++i) {
+                const bool complete = !h->is_host[i].lvl_changed[(Lp - 1) % kLvlSlots];
+                h->fill_up[i] = !part[i] ? -1 : !cover[i] ? fill_out[i] : (complete ? kInf : L + 1);
+            }
+            return SMF_OK;
+        }
+        if (ended && !shrink_cover(h, live, cover, R))
+            return fail(SMF_ERR_HIP, "smf_solve: internal error in the level ranges");
+        return SMF_OK;
     }
-    for (int i = 0; i < n; ++i)
-        if (part[i]) h->inst_relabels[i]++;
-    h->global_relabels++;
-    return SMF_OK;
+
+    // Enqueues the fix-up (nothing for a one-block search, which fixes its
+    // own labels) and books the search.
+    int finish()
+    {
+        const int n = h->n;
+        if (c0 < c1 && !(h->block_search && bfs_block_fits(h->g))) {
+            HIP_TRY(hipMemcpyAsync(h->fill_dev, h->fill_up, sizeof(int) * n, hipMemcpyHostToDevice, s));
+            TimedScope ts(h->timer, KC_BFS_RESET, s);
+            launch_bfs_fixup(h->g, h->st, c0, c1, s);
+        }
+        if (c0 >= c1) return SMF_OK;
+        if (h->verbose) {
+            int npart = 0, act = 0, lab = 0;
+            for (int i = 0; i < n; ++i)
+                if (part[i]) {
+                    ++npart;
+                    act += h->is_host[i].bfs_active;
+                    lab += std::min(h->is_host[i].bfs_unsat[0], h->is_host[i].bfs_unsat[1]);
+                }
+            fprintf(stderr, "smf: global relabel %lld at sweep %lld: %d volumes, %d levels, active %d, columns short %d\n",
+                    (long long)h->global_relabels, (long long)h->sweeps, npart, L - 1, act, lab);
+        }
+        for (int i = 0; i < n; ++i)
+            if (part[i]) h->inst_relabels[i]++;
+        h->global_relabels++;
+        return SMF_OK;
+    }
+};
+
+// A whole global relabel on one stream: levels are enqueued one batch ahead
+// of the host's reading of the counters.
+static int global_relabel(smf_handle *h, hipStream_t s, const std::vector<char> &part, bool complete = false)
+{
+    Search S;
+    int rc = S.begin(h, s, part, complete);
+    if (rc) return rc;
+    if (!S.whole) {
+        rc = S.step();
+        for (bool all = false; !rc && !all;) {
+            rc = S.step();
+            if (!rc) rc = S.examine(all);
+        }
+        if (rc) return rc;
+    }
+    return S.finish();
+}
+
+// One sweep: push phases, each reading the list of work[a] and marking
+// work[a^1], whose list the compaction then builds (clearing the size of the
+// list filled next, and the active counts); then the relabel phase, which
+// reads the last list and fills the other one.
+static void enqueue_sweep(smf_handle *h, hipStream_t s, bool use_gap)
+{
+    int a = h->cur_work;
+    for (int64_t j = 0; j < h->push_phases; ++j, a ^= 1) {
+        {
+            TimedScope ts(h->timer, KC_PUSH, s);
+            launch_push(h->g, h->st, h->work[a], h->work[a ^ 1], h->scr, (h->pushes++ & 1) == 0, s);
+        }
+        launch_compact(h->g, h->work[a ^ 1], h->work[a].count, s);
+    }
+    {
+        TimedScope ts(h->timer, KC_RELABEL, s);
+        // a gap holds only for the labels it was found on: the relabel
+        // phase right after its search uses it, no later one
+        launch_relabel(h->g, h->st, h->work[a], h->work[a ^ 1], use_gap, s);
+    }
+    h->cur_work = a ^ 1;
+    h->sweeps++;
 }
 
 // Solve of every volume of the batch; costs of volume i start at
@@ -667,11 +769,11 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
     }
     HIP_TRY(hipGetLastError());
     std::vector<char> all((size_t)n, 1), part((size_t)n, 0), done((size_t)n, 0);
-    int rc = global_relabel(h, s, all);
-    if (rc) return rc;
-
     std::vector<int64_t> since((size_t)n, 0), period((size_t)n);
     for (int i = 0; i < n; ++i) period[i] = h->inst_period[i] > 0 ? h->inst_period[i] : h->relabel_period;
+    int rc = SMF_OK;
+    rc = global_relabel(h, s, all);
+    if (rc) return rc;
     // work lists: every column may hold excess anywhere before the first sweep
     launch_work_init(h->g, h->work[0], h->work[1], s);
     h->cur_work = 0;
@@ -698,27 +800,8 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
                 for (int i = 0; i < n; ++i)
                     if (part[i]) since[i] = 0;
             }
-            // each push phase reads the list of work[a] and marks work[a^1],
-            // whose list the compaction then builds (clearing the size of the
-            // list filled next, and the active counts); the relabel phase
-            // reads the last list and fills the other one
-            int a = h->cur_work;
-            for (int64_t j = 0; j < h->push_phases; ++j, a ^= 1) {
-                {
-                    TimedScope ts(h->timer, KC_PUSH, s);
-                    launch_push(h->g, h->st, h->work[a], h->work[a ^ 1], h->scr, (h->pushes++ & 1) == 0, s);
-                }
-                launch_compact(h->g, h->work[a ^ 1], h->work[a].count, s);
-            }
-            {
-                TimedScope ts(h->timer, KC_RELABEL, s);
-                // a gap holds only for the labels it was found on: the
-                // relabel phase right after its search uses it, no later one
-                launch_relabel(h->g, h->st, h->work[a], h->work[a ^ 1], gap_fresh, s);
-            }
-            h->cur_work = a ^ 1;
+            enqueue_sweep(h, s, gap_fresh);
             gap_fresh = false;
-            h->sweeps++;
             for (int i = 0; i < n; ++i)
                 if (!done[i]) { since[i]++; h->inst_sweeps[i]++; }
             if (h->gap_every > 0 && h->sweeps % h->gap_every == 0) {
@@ -810,7 +893,9 @@ static int solve_batch(smf_handle *h, const int32_t *cost_dev, const int64_t *of
 static int solve_checked(smf_handle *h, const int32_t *cost_dev, const int64_t *off, hipStream_t s)
 {
     const int rc = solve_batch(h, cost_dev, off, s);
-    if (rc != SMF_OK) (void)hipStreamSynchronize(s);
+    if (rc != SMF_OK) {
+        (void)hipStreamSynchronize(s);
+    }
     return rc;
 }
 
