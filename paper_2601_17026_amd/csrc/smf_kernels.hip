@@ -1058,10 +1058,18 @@ constexpr int kFdAtT = 0x40000000;           // flow on the down arc into (p, T)
 constexpr int kTMask = 0x3fffffff;           // the threshold bits
 
 // Word w of bit mask m of column p.
-__device__ __forceinline__ unsigned long long mask_word(const Geom &g, int m, int w, int p)
-{
-    return g.bits[((size_t)m * g.max_nch + w) * g.Ptot + p];
-}
+// Where a level reads the bit masks: word w of mask m of column p is
+// bits[(m * nch + w) * P + p] (the global masks, or a copy in LDS).
+struct MaskSrc {
+    const unsigned long long *bits;
+    int nch, P;
+    __device__ unsigned long long word(int m, int w, int p) const
+    {
+        return bits[((size_t)m * nch + w) * P + p];
+    }
+};
+
+__device__ __forceinline__ MaskSrc global_masks(const Geom &g) { return MaskSrc{g.bits, g.max_nch, g.Ptot}; }
 
 // Bits [lo, hi) of the heights 64w..64w+63 (lo < 64(w+1), hi > 64w).
 __device__ __forceinline__ unsigned long long range_bits(int w, int lo, int hi)
@@ -1194,7 +1202,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 }
                 const bool lab = in && z >= t1;
                 const int dv = w[j].d;
-                if (in) st.d[base + z] = lab ? 1 : (dv >= kInf ? kInf : kUnl);
+                // labels that keep their value (kInf stays kInf) are not rewritten
+                const int dn = lab ? 1 : (dv >= kInf ? kInf : kUnl);
+                if (in && dn != dv) st.d[base + z] = dn;
                 const bool isact = in && w[j].e > 0 && dv < kInf;
                 if (isact) ++act.acc;
                 if (la == Kc) {
@@ -1288,7 +1298,7 @@ __global__ __launch_bounds__(256) void k_bfs_count(Geom g, const int *__restrict
 // the bit masks.  fdT: the down arc into (p, T) carries flow; fd_new gets
 // the same fact for the new threshold.  Returns the mask words read.
 template <bool kSoft>
-__device__ __forceinline__ int level_update(const Geom &g, int p, int K, const BandCol &bc, int alpha,
+__device__ __forceinline__ int level_update(const Geom &g, const MaskSrc &ms, int p, int K, const BandCol &bc, int alpha,
                                            int T, bool fdT, const int tq[4], const int lq[4], int lf[4],
                                            int &cand, bool &fd_new)
 {
@@ -1326,7 +1336,7 @@ __device__ __forceinline__ int level_update(const Geom &g, int p, int K, const B
     if (cand < T) {
         // the word the scan below starts in holds the new threshold's bit
         ++words;
-        fd_new = (mask_word(g, kMaskFd, cand >> 6, p) >> (cand & 63)) & 1ULL;
+        fd_new = (ms.word(kMaskFd, cand >> 6, p) >> (cand & 63)) & 1ULL;
     }
     // an lf below T was found in an earlier word
     for (int w = cand >> 6; cand < T && w <= (T - 1) >> 6; ++w) {
@@ -1335,7 +1345,7 @@ __device__ __forceinline__ int level_update(const Geom &g, int p, int K, const B
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (lf[k] < T) continue;
-            const unsigned long long fm = mask_word(g, kMaskFl + k, w, p) & r;
+            const unsigned long long fm = ms.word(kMaskFl + k, w, p) & r;
             if (fm) lf[k] = w * kWave + __ffsll((long long)fm) - 1;
         }
         words += 4;
@@ -1419,7 +1429,7 @@ __device__ __forceinline__ void set_level_flag(const Geom &g, int ii, bool flag,
 // mask words scanned (a quiet column does not need its record; neighbours'
 // words are their own records, counted with their own column).
 template <bool kSoft>
-__device__ __forceinline__ bool column_step(const Geom &g, const Col &col, int p, const int *Tin,
+__device__ __forceinline__ bool column_step(const Geom &g, const MaskSrc &ms, const Col &col, int p, const int *Tin,
                                             const int *LFin, int P, int &T, int &cand, int lf[4],
                                             bool &self, int &tword, long long &bytes)
 {
@@ -1445,7 +1455,7 @@ __device__ __forceinline__ bool column_step(const Geom &g, const Col &col, int p
     BandCol bc;
     band_col(g, p, q, K, col.I.delta, bc);
     bool fd_new = false;
-    bytes += 16 + 8 * level_update<kSoft>(g, p, K, bc, col.I.alpha, T, (tw & kFdAtT) != 0, tq, lq, lf,
+    bytes += 16 + 8 * level_update<kSoft>(g, ms, p, K, bc, col.I.alpha, T, (tw & kFdAtT) != 0, tq, lq, lf,
                                           cand, fd_new);
     if (cand < T) tword = cand | (fd_new ? kFdAtT : 0) | kChanged;
     return cand < T;
@@ -1481,7 +1491,7 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
         const Col col = single ? column_in(I0, 0, p) : column(g, p);
         ii = col.ii;
         base = (long long)col.base;
-        need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, tword, bytes);
+        need = column_step<kSoft>(g, global_masks(g), col, p, Tin, LFin, P, T, cand, lf, self, tword, bytes);
     }
     if (valid) {
         Tout[p] = tword;
@@ -1515,23 +1525,68 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
 // labels are the same.
 constexpr int kBlockSearchCols = 1536;
 
-template <bool kSoft>
+constexpr int kBlockSearchSlots = 2;   // columns per thread
+static_assert(kBlockSearchCols <= kBlockSearchSlots * 1024, "a one-block search takes 2 columns a thread");
+
+template <bool kSoft, bool kStage>
 __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d, const int *__restrict__ T1,
                                                    const int *__restrict__ LF1, int early_stop,
                                                    int max_level, Scratch *s)
 {
-    extern __shared__ int sm[];
+    extern __shared__ unsigned long long sml[];
+    int *const sm = reinterpret_cast<int *>(sml);
     const int P = g.Ptot;
-    int *const sT[2] = {sm, sm + P};
-    int *const sLF[2] = {sm + 2 * P, sm + 6 * P};
+    // records of level L in buffer L & 1: thresholds at sm + (L & 1) P,
+    // lowest-flow records at sm + 2P + 4P (L & 1); the buffers are picked by
+    // arithmetic on the LDS base, so the compiler keeps LDS accesses
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        sT[1][i] = T1[i];
+        sm[P + i] = T1[i];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sLF[1][(size_t)k * P + i] = LF1[(size_t)k * P + i];
+        for (int k = 0; k < 4; ++k) sm[6 * P + k * P + i] = LF1[(size_t)k * P + i];
+    }
+    const Inst I = g.inst[0];
+    // kStage: the level-1 bit masks are copied into LDS after the records
+    // (40 bytes per column and chunk), so that a level reads no global
+    // memory and only writes its labels there
+    unsigned long long *const sb = sml + 5 * (size_t)P;
+    if constexpr (kStage) {
+        const int per = I.nch * P;
+        for (int i = threadIdx.x; i < kMasks * per; i += blockDim.x) {
+            const int m = i / per, r = i - m * per, w = r / P, p = r - w * P;
+            sb[i] = g.bits[((size_t)m * g.max_nch + w) * P + p];
+        }
+    }
+    const MaskSrc ms = kStage ? MaskSrc{sb, I.nch, P} : global_masks(g);
+    // each thread's lowest active heights, for the early stop
+    int la[kBlockSearchSlots];
+#pragma unroll
+    for (int j = 0; j < kBlockSearchSlots; ++j) {
+        const int p = j * (int)blockDim.x + (int)threadIdx.x;
+        la[j] = p < P ? g.low_act[p] : 0;
     }
     __syncthreads();
     const int slots = (P + (int)blockDim.x - 1) / (int)blockDim.x;
-    const Inst I = g.inst[0];
+    // per level L, red[L % 3] gathers bit 0: a column moved, bit 1: a column
+    // is still short of its lowest active node
+    __shared__ int red[3];
+    if (threadIdx.x < 3) red[threadIdx.x] = 0;
+    __syncthreads();
+    // the geometry of the thread's columns, fixed for the whole search:
+    // node (p, 0), the neighbours and the band shifts
+    long long cbase[kBlockSearchSlots];
+    int cq[kBlockSearchSlots][4];
+    BandCol cbc[kBlockSearchSlots];
+#pragma unroll
+    for (int j = 0; j < kBlockSearchSlots; ++j) {
+        // a slot past the last column takes column 0's geometry, unused
+        const int pj = j * (int)blockDim.x + (int)threadIdx.x;
+        const int p = pj < P ? pj : 0;
+        const Col col = column_in(I, 0, p);
+        cbase[j] = (long long)col.base;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cq[j][k] = nbr(I.nx, I.ny, col.x, col.y, p, k);
+        band_col(g, p, cq[j], I.K, I.delta, cbc[j]);
+    }
     long long bytes = 0;
     int L = 1, cur = 1, run = 0;
     bool complete = false;
@@ -1540,43 +1595,80 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
             if (threadIdx.x == 0) atomicOr(&s->err, kErrSearch);
             break;
         }
-        const int *Tin = sT[cur], *LFin = sLF[cur];
-        int *Tout = sT[cur ^ 1], *LFout = sLF[cur ^ 1];
+        const int *Tin = sm + cur * P, *LFin = sm + 2 * P + 4 * P * cur;
+        int *Tout = sm + (cur ^ 1) * P, *LFout = sm + 2 * P + 4 * P * (cur ^ 1);
         bool moved = false;
-        for (int slot = 0; slot < slots; ++slot) {
-            const int p = slot * (int)blockDim.x + (int)threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < kBlockSearchSlots; ++j) {
+            if (j >= slots) break;
+            const int p = j * (int)blockDim.x + (int)threadIdx.x;
             const bool valid = p < P;
-            bool self = false, need = false;
-            int T = 0, cand = 0, tword = 0;
-            long long base = 0, b = 0;
-            int lf[4] = {0, 0, 0, 0};
+            bool need = false;
+            int T = 0, cand = 0;
+            long long b = 0;
             if (valid) {
-                const Col col = column_in(I, 0, p);
-                base = (long long)col.base;
-                need = column_step<kSoft>(g, col, p, Tin, LFin, P, T, cand, lf, self, tword, b);
+                // the step of column_step, on the hoisted geometry
+                int tq[4], lq[4], lf[4];
+                const int tw = Tin[p];
+                bool near = tw < 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int q = cq[j][k];
+                    const int w = q >= 0 ? Tin[q] : -1;
+                    lq[k] = q >= 0 ? LFin[(k ^ 1) * P + q] : I.K;
+                    lf[k] = LFin[k * P + p];
+                    near = near || (q >= 0 && w < 0);
+                    tq[k] = q >= 0 ? (w & kTMask) : -1;
+                }
+                const bool self = tw < 0;
+                T = tw & kTMask;
+                cand = T;
+                int tword = tw & ~kChanged;
+                b = 8;
+                if (near) {
+                    bool fd_new = false;
+                    b += 16 + 8 * level_update<kSoft>(g, ms, p, I.K, cbc[j], I.alpha, T, (tw & kFdAtT) != 0, tq,
+                                                      lq, lf, cand, fd_new);
+                    need = cand < T;
+                    if (need) tword = cand | (fd_new ? kFdAtT : 0) | kChanged;
+                }
                 Tout[p] = tword;
                 if (need || self)
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) LFout[(size_t)k * P + p] = lf[k];
+                    for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
             }
-            bytes += b + label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, base);
+            bytes += b + label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, cbase[j]);
             moved = moved || need;
         }
         ++run;
-        // every record of level L+1 is written before any is read or counted
+        // early stop: a column of this thread (its record was written by
+        // this thread) still short of its lowest active node
+        bool short_col = false;
+        if (early_stop) {
+#pragma unroll
+            for (int j = 0; j < kBlockSearchSlots; ++j) {
+                const int p = j * (int)blockDim.x + (int)threadIdx.x;
+                short_col = short_col || (p < P && (Tout[p] & kTMask) > la[j]);
+            }
+        }
+        // each wave ORs its two flags into red[L % 3], and one barrier both
+        // publishes them and puts every record of level L+1 before any read
+        // of the next level.  red[(L + 1) % 3] is cleared for the next level
+        // before this barrier: it was last read between the barriers of
+        // levels L - 2 and L - 1
+        const int wf = (__ballot(moved) ? 1 : 0) | (__ballot(short_col) ? 2 : 0);
+        if (lane_id() == 0 && wf) atomicOr(&red[L % 3], wf);
+        if (threadIdx.x == 0) red[(L + 1) % 3] = 0;
         __syncthreads();
-        if (!__syncthreads_or(moved)) {
+        const int f = red[L % 3];
+        const bool any_m = f & 1, any_s = f & 2;
+        if (!any_m) {
             complete = true;   // level L labelled nothing
             break;
         }
-        if (early_stop) {
-            bool short_col = false;
-            for (int p = threadIdx.x; p < P; p += blockDim.x)
-                short_col = short_col || (sT[cur ^ 1][p] & kTMask) > g.low_act[p];
-            if (!__syncthreads_or(short_col)) {
-                ++L;   // levels <= L are done: unreached nodes lie beyond L + 1
-                break;
-            }
+        if (early_stop && !any_s) {
+            ++L;   // levels <= L are done: unreached nodes lie beyond L + 1
+            break;
         }
     }
     // fix-up: L is the first level whose labels were not all written
@@ -1878,6 +1970,9 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
                            L, Tin, LFin, Tout, LFout, R, I0, one);
 }
 
+// LDS of a one-block search (gfx950: 160 KB per workgroup).
+constexpr size_t kBlockSearchLds = 160 * 1024;
+
 // Deep columns make a level of one block longer than a level launched
 // over the grid (measured: 32x48x500 5% slower, 24x64x256 even), so the
 // block search also needs few 64-height chunks.
@@ -1891,13 +1986,37 @@ bool bfs_block_fits(const Geom &g)
 void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
                       int max_level, Scratch *s, hipStream_t st)
 {
-    const size_t lds = sizeof(int) * 10 * (size_t)g.Ptot;
+    // records, and the masks when they fit beside them
+    const size_t rec = sizeof(int) * 10 * (size_t)g.Ptot;
+    const size_t masks = sizeof(unsigned long long) * kMasks * (size_t)g.max_nch * g.Ptot;
+    const int stage = rec + masks <= kBlockSearchLds ? 1 : 0;
+    const size_t lds = rec + (stage ? masks : 0);
+    // gfx950 gives a workgroup up to 160 KB of LDS; the limit is raised once
+    // per kernel (a runtime that refuses reports it at the launch)
+    static const bool raised = [] {
+        for (const void *f : {reinterpret_cast<const void *>(k_bfs_block<true, true>),
+                              reinterpret_cast<const void *>(k_bfs_block<false, true>)})
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBlockSearchLds) !=
+                hipSuccess)
+                (void)hipGetLastError();
+        return true;
+    }();
+    (void)raised;
+    if (stage) {
+        if (g.soft)
+            hipLaunchKernelGGL((k_bfs_block<true, true>), dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1,
+                               early_stop, max_level, s);
+        else
+            hipLaunchKernelGGL((k_bfs_block<false, true>), dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1,
+                               early_stop, max_level, s);
+        return;
+    }
     if (g.soft)
-        hipLaunchKernelGGL(k_bfs_block<true>, dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1, early_stop,
+        hipLaunchKernelGGL((k_bfs_block<true, false>), dim3(1), dim3(1024), rec, st, g, sv.d, T1, LF1, early_stop,
                            max_level, s);
     else
-        hipLaunchKernelGGL(k_bfs_block<false>, dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1, early_stop,
-                           max_level, s);
+        hipLaunchKernelGGL((k_bfs_block<false, false>), dim3(1), dim3(1024), rec, st, g, sv.d, T1, LF1,
+                           early_stop, max_level, s);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)
