@@ -1597,14 +1597,14 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
         }
         const int *Tin = sm + cur * P, *LFin = sm + 2 * P + 4 * P * cur;
         int *Tout = sm + (cur ^ 1) * P, *LFout = sm + 2 * P + 4 * P * (cur ^ 1);
-        bool moved = false;
+        bool moved = false, shortc = false;
 #pragma unroll
         for (int j = 0; j < kBlockSearchSlots; ++j) {
             if (j >= slots) break;
             const int p = j * (int)blockDim.x + (int)threadIdx.x;
             const bool valid = p < P;
             bool need = false;
-            int T = 0, cand = 0;
+            int T = 0, cand = 0, tout = 0;
             long long b = 0;
             if (valid) {
                 // the step of column_step, on the hoisted geometry
@@ -1633,24 +1633,28 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
                     if (need) tword = cand | (fd_new ? kFdAtT : 0) | kChanged;
                 }
                 Tout[p] = tword;
+                tout = tword;
                 if (need || self)
 #pragma unroll
                     for (int k = 0; k < 4; ++k) LFout[k * P + p] = lf[k];
             }
-            bytes += b + label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, cbase[j]);
+            // labels: short ranges (at most 8 heights in every lane) one
+            // store per height, longer ones spread over the wave
+            const int len = need ? T - cand : 0;
+            if (__ballot(len > 8)) {
+                bytes += b + label_ranges(d, L + 1, need ? cand : 0, need ? T : 0, cbase[j]);
+            } else {
+                for (int i = 0; __ballot(i < len); ++i)
+                    if (i < len) d[(size_t)cbase[j] + cand + i] = L + 1;
+                bytes += b + 4LL * len;
+            }
             moved = moved || need;
+            shortc = shortc || (valid && (tout & kTMask) > la[j]);
         }
         ++run;
-        // early stop: a column of this thread (its record was written by
-        // this thread) still short of its lowest active node
-        bool short_col = false;
-        if (early_stop) {
-#pragma unroll
-            for (int j = 0; j < kBlockSearchSlots; ++j) {
-                const int p = j * (int)blockDim.x + (int)threadIdx.x;
-                short_col = short_col || (p < P && (Tout[p] & kTMask) > la[j]);
-            }
-        }
+        // early stop: a column of this thread still short of its lowest
+        // active node (shortc, from the records just written)
+        const bool short_col = early_stop && shortc;
         // each wave ORs its two flags into red[L % 3], and one barrier both
         // publishes them and puts every record of level L+1 before any read
         // of the next level.  red[(L + 1) % 3] is cleared for the next level
