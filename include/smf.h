@@ -218,11 +218,16 @@ int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *exten
  *                        at most one per column)
  *   "bfs_early_stop"  -- 1 (default): end a global relabel once every node
  *                        with excess is labelled; 0: always run it to the end
+ *   "search_quorum"   -- for a batch: a global relabel ends for all of its
+ *                        volumes once this percentage of them has ended (1..100,
+ *                        default 90); the nodes of the others that no level
+ *                        reached get the first level not run as their label,
+ *                        a valid lower bound of their distance to t
  *   "block_search"    -- 1 (default): a plain handle of at most 1536 columns
  *                        and 4096 64-height column chunks runs each global
- *                        relabel as one block with its
- *                        records in LDS (no launch or host poll per level);
- *                        0: always one launch per level
+ *                        relabel as one block with its records (and, when
+ *                        both fit in 160 KB, its bit masks) in LDS (no launch
+ *                        or host poll per level); 0: always one launch per level
  *   "hmax"            -- 1: every solve also reads out the highest optimal
  *                        surface (smf_surface_max) with one complete global
  *                        relabel after termination; the first 1 allocates

@@ -224,6 +224,7 @@ struct smf_handle {
     int64_t gap_every = 0;         // sweeps between gap searches (0: off)
     int64_t want_hmax = 0;         // 1: also read out the highest optimal surface
     int64_t push_phases = 3;       // push phases per sweep (one relabel phase)
+    int64_t search_quorum = 90;    // a batch search ends once this percentage of its volumes ended
     int cur_work = 0;              // work[cur_work] holds the columns of the next push phase
     bool hmax_ready = false;       // the last solve computed Hmax
 
@@ -636,7 +637,9 @@ struct Search {
         --inflight;
         bool ended = false;
         all = true;
+        int nlive = 0, npart = 0;
         for (int i = 0; i < n; ++i) {
+            npart += part[i] ? 1 : 0;
             if (!live[i]) continue;
             const InstScratch &r = h->is_host[i];
             const bool complete = !r.lvl_changed[(Lp - 1) % kLvlSlots];
@@ -648,8 +651,12 @@ struct Search {
                 fill_out[i] = complete ? kInf : L + 1;
             } else {
                 all = false;
+                ++nlive;
             }
         }
+        // the volumes still searching when the quorum has ended take the
+        // first level not run as their fill label, a valid lower bound
+        if (!all && 100 * (int64_t)(npart - nlive) >= h->search_quorum * npart) all = true;
         if (all) {
             // levels < L are complete now (the batches after the snapshot
             // included); a volume still covered takes the latest fill
@@ -1151,6 +1158,11 @@ extern "C" int smf_set_param(smf_handle *h, const char *key, int64_t value)
     else if (!strcmp(key, "count_work")) {
         if (value != 0 && value != 1) return fail(SMF_ERR_ARG, "smf_set_param: count_work is 0 or 1");
         h->g.count_work = (int)value;
+        return SMF_OK;
+    }
+    else if (!strcmp(key, "search_quorum")) {
+        if (value < 1 || value > 100) return fail(SMF_ERR_ARG, "smf_set_param: search_quorum lies in [1, 100]");
+        h->search_quorum = value;
         return SMF_OK;
     }
     else if (!strcmp(key, "push_phases")) {

@@ -131,6 +131,9 @@ def test_batch_per_volume_periods(smf):
     {"bfs_early_stop": 0},
     {"poll_every": 3, "bfs_poll_every": 2},
     {"relabel_period": 1},
+    {"search_quorum": 100},
+    {"search_quorum": 1},
+    {"search_quorum": 50, "bfs_early_stop": 0},
 ])
 def test_batch_parameter_variants(smf, params):
     vols = _volumes(SHAPES, seed0=1100)
@@ -219,3 +222,12 @@ def test_batch_many_volumes_scattered_searches(smf):
     g = _solve_batch(smf, shapes, vols, params={"bfs_poll_every": 2}, per_volume={"relabel_period": periods})
     _check_oracle(shapes, vols, g)
     assert max(g["relabels"]) > 1
+
+
+def test_search_quorum_checked(smf):
+    with smf.BatchSolver(SHAPES[:2]) as b:
+        for v in (0, 101, -5):
+            with pytest.raises(smf.SmfError):
+                b.set_param("search_quorum", v)
+        b.set_param("search_quorum", 1)
+        b.set_param("search_quorum", 100)
