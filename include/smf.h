@@ -298,11 +298,12 @@ int smf_batch_get_stat(const smf_handle *h, const char *key, int64_t *out);
  * cached; then every volume of `h` gets its class's period
  * (smf_batch_set_param) and `h` the push phases of its cached class holding
  * the most nodes (push phases are one value per handle).  For a batch of
- * more than one volume the tuner then times whole solves of `h` with every
- * volume's period scaled by 1, 1.5, 2 and 3 and keeps the fastest scale (the
- * volumes of a batch share their searches, which favours longer periods
- * than solving each volume alone); the cache keeps the unscaled class
- * periods.  `packed_cost_dev` and `offsets_host` are as for smf_batch_solve
+ * more than one volume the tuner then times whole solves of `h` (the faster
+ * of two each) with every volume's period scaled by 1, 1.5, 2 and 3 (with the
+ * class push phases) and with the uniform schedules (2,4), (3,3) and (1,6),
+ * and keeps the fastest (the volumes of a batch share their searches, which
+ * can favour other schedules than solving each volume alone); the cache
+ * keeps the unscaled class periods.  `packed_cost_dev` and `offsets_host` are as for smf_batch_solve
  * (a plain handle: the volume, NULL offsets).  Allocates and frees the
  * temporary handles; work runs on `stream`.  If the environment variable
  * SMF_TUNE_CACHE names a file, the cache is loaded from it on first use and

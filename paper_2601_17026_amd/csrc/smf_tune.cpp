@@ -54,6 +54,8 @@ bool g_env_loaded = false;
 const int64_t kCandidates[][2] = {{4, 1}, {2, 2}, {1, 3}, {2, 3}, {3, 3}, {1, 4}, {2, 4}};
 // scale factors 1, 1.5, 2 and 3 (doubled) of the whole-batch step
 const int kBatchScale2[] = {2, 3, 4, 6};
+// Uniform (period, push phases) schedules a batch also tries.
+const int64_t kBatchUniform[][2] = {{2, 4}, {3, 3}, {1, 6}};
 // Repeats per candidate: the run-to-run spread of a solve is a few
 // percent, as large as the differences between neighbouring periods, so
 // the fastest of three runs counts for solves under 0.25 s and the faster
@@ -232,33 +234,48 @@ extern "C" int smf_autotune(smf_handle *h, const int32_t *packed_cost_dev,
     rc = apply_locked(h, s);
     if (rc || n == 1) return rc;
     // The volumes of a batch share their searches (a level costs one launch
-    // however many volumes take part), which favours longer periods than
-    // solving each volume alone: whole-batch solves with every period
-    // scaled by each factor are timed, and the fastest scale is kept.
+    // however many volumes take part), which can favour other schedules than
+    // solving each volume alone: whole-batch solves are timed with every
+    // class period scaled by each factor (the class push phases), and with a
+    // few uniform schedules; each is timed twice and the fastest kept.
     std::vector<int64_t> eff(n), scaled(n);
     rc = smf_batch_get_stat(h, "relabel_period", eff.data());
     if (rc) return rc;
-    int64_t best_ns = -1;
-    std::vector<int64_t> best = eff;
+    int64_t phases0 = 0;
+    rc = smf_get_stat(h, "push_phases", &phases0);
+    if (rc) return rc;
+    struct Sched {
+        std::vector<int64_t> per;
+        int64_t phases;
+    };
+    std::vector<Sched> cands;
     for (int f2 : kBatchScale2) {   // twice the scale factor
         for (size_t i = 0; i < n; ++i) scaled[i] = std::max<int64_t>(1, (eff[i] * f2 + 1) / 2);
-        rc = smf_batch_set_param(h, "relabel_period", scaled.data());
-        if (rc) return rc;
-        if (best_ns < 0) {
-            rc = smf_batch_solve(h, packed_cost_dev, off.data(), stream);   // warm-up
-            if (rc) return rc;
+        cands.push_back({scaled, phases0});
+    }
+    for (const auto &u : kBatchUniform) cands.push_back({std::vector<int64_t>(n, u[0]), u[1]});
+    int64_t best_ns = -1;
+    size_t best = 0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+        rc = smf_batch_set_param(h, "relabel_period", cands[c].per.data());
+        if (!rc) rc = smf_set_param(h, "push_phases", cands[c].phases);
+        if (!rc && c == 0) rc = smf_batch_solve(h, packed_cost_dev, off.data(), stream);   // warm-up
+        int64_t ns = -1;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = smf_batch_solve(h, packed_cost_dev, off.data(), stream);
+            const auto t1 = std::chrono::steady_clock::now();
+            const int64_t d = std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count();
+            ns = ns < 0 ? d : std::min(ns, d);
         }
-        const auto t0 = std::chrono::steady_clock::now();
-        rc = smf_batch_solve(h, packed_cost_dev, off.data(), stream);
-        const auto t1 = std::chrono::steady_clock::now();
         if (rc) return rc;
-        const int64_t ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count();
         if (best_ns < 0 || ns < best_ns) {
             best_ns = ns;
-            best = scaled;
+            best = c;
         }
     }
-    return smf_batch_set_param(h, "relabel_period", best.data());
+    rc = smf_batch_set_param(h, "relabel_period", cands[best].per.data());
+    return rc ? rc : smf_set_param(h, "push_phases", cands[best].phases);
 }
 
 extern "C" int smf_tune_apply(smf_handle *h)
