@@ -212,7 +212,10 @@ def test_gap_heuristic_freezes_nodes(smf, case, every):
 def test_block_search_at_its_limit(smf, shape, delta):
     # 1536 columns (the most a one-block search takes, 60 KiB of LDS
     # records) with one and two 64-height chunks: the one-block search and
-    # the launch-per-level search give the oracle's exact result
+    # the launch-per-level search give the oracle's exact result.  With one
+    # chunk the bit masks (60 KiB more) are copied into LDS beside the
+    # records; with two (120 KiB more) they exceed the 160 KiB and stay in
+    # global memory, so both forms of the one-block search run here
     cost = synth.layered_cost(*shape, 2, 0.4, 255, 0.05, 47)
     print(f"case: block search limit {shape} delta {delta}", flush=True)
     r = oracle.solve(cost, delta)
