@@ -223,8 +223,8 @@ int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *exten
  *                        default 90); the nodes of the others that no level
  *                        reached get the first level not run as their label,
  *                        a valid lower bound of their distance to t
- *   "block_search"    -- 1 (default): a plain handle of at most 1536 columns
- *                        and 4096 64-height column chunks runs each global
+ *   "block_search"    -- 1 (default): a plain handle of at most 2048 columns
+ *                        and 16384 64-height column chunks runs each global
  *                        relabel as one block with its records (and, when
  *                        both fit in 160 KB, its bit masks) in LDS (no launch
  *                        or host poll per level); 0: always one launch per level

@@ -1523,7 +1523,7 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
 // block then writes those fill labels itself and adds its level count to
 // s->block_levels.  Every column step is the one of k_bfs_level, so the
 // labels are the same.
-constexpr int kBlockSearchCols = 1536;
+constexpr int kBlockSearchCols = 2048;
 
 constexpr int kBlockSearchSlots = 2;   // columns per thread
 static_assert(kBlockSearchCols <= kBlockSearchSlots * 1024, "a one-block search takes 2 columns a thread");
@@ -1977,10 +1977,12 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
 // LDS of a one-block search (gfx950: 160 KB per workgroup).
 constexpr size_t kBlockSearchLds = 160 * 1024;
 
-// Deep columns make a level of one block longer than a level launched
-// over the grid (measured: 32x48x500 5% slower, 24x64x256 even), so the
-// block search also needs few 64-height chunks.
-constexpr long long kBlockSearchChunks = 4096;
+// Chunks a one-block search takes (its masks then stay in global memory;
+// measured: 32x48x500 with 12288 chunks 0.51 s against 0.70 s for launched
+// levels).  Beyond 2048 columns a thread walks more than two columns per
+// level and the launched levels win (measured: even at 3072 columns, 10%
+// slower at 4032).
+constexpr long long kBlockSearchChunks = 16384;
 
 bool bfs_block_fits(const Geom &g)
 {
@@ -1993,7 +1995,8 @@ void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *
     // records, and the masks when they fit beside them
     const size_t rec = sizeof(int) * 10 * (size_t)g.Ptot;
     const size_t masks = sizeof(unsigned long long) * kMasks * (size_t)g.max_nch * g.Ptot;
-    const int stage = rec + masks <= kBlockSearchLds ? 1 : 0;
+    // (1 KB of the 160 KB stays free for the kernel's static LDS)
+    const int stage = rec + masks + 1024 <= kBlockSearchLds ? 1 : 0;
     const size_t lds = rec + (stage ? masks : 0);
     // gfx950 gives a workgroup up to 160 KB of LDS; the limit is raised once
     // per kernel (a runtime that refuses reports it at the launch)

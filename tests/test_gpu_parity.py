@@ -180,7 +180,7 @@ def test_error_paths(smf):
 ])
 def test_parameter_variants(smf, params):
     # every schedule knob leaves the exact result unchanged; both volumes
-    # have at most 1536 columns, so their searches run in one block unless
+    # have at most 2048 columns, so their searches run in one block unless
     # block_search is 0
     for cost, delta in (synth.config_small(),
                         (synth.layered_cost(37, 29, 70, 2, 0.4, 255, 0.05, 23), 1)):
@@ -208,14 +208,15 @@ def test_gap_heuristic_freezes_nodes(smf, case, every):
     assert g["cert"].ok, g["cert"]
 
 
-@pytest.mark.parametrize("shape,delta", [((32, 48, 64), 2), ((48, 32, 128), 1)])
+@pytest.mark.parametrize("shape,delta", [((32, 48, 64), 2), ((32, 64, 64), 1), ((16, 128, 384), 2), ((33, 64, 40), 1)])
 def test_block_search_at_its_limit(smf, shape, delta):
-    # 1536 columns (the most a one-block search takes, 60 KiB of LDS
-    # records) with one and two 64-height chunks: the one-block search and
-    # the launch-per-level search give the oracle's exact result.  With one
-    # chunk the bit masks (60 KiB more) are copied into LDS beside the
-    # records; with two (120 KiB more) they exceed the 160 KiB and stay in
-    # global memory, so both forms of the one-block search run here
+    # The one-block search and the launch-per-level search give the
+    # oracle's exact result at the block search's limits: 1536 columns with
+    # one 64-height chunk (records and bit masks, 120 KiB, both in LDS);
+    # 2048 columns, the most it takes (80 KiB of records, the masks too
+    # many for LDS and read from global memory); 2048 columns of six chunks
+    # (12288 column chunks); and 2112 columns, beyond the limit, where both
+    # settings launch every level
     cost = synth.layered_cost(*shape, 2, 0.4, 255, 0.05, 47)
     print(f"case: block search limit {shape} delta {delta}", flush=True)
     r = oracle.solve(cost, delta)
