@@ -223,11 +223,13 @@ int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *exten
  *                        default 90); the nodes of the others that no level
  *                        reached get the first level not run as their label,
  *                        a valid lower bound of their distance to t
- *   "block_search"    -- 1 (default): a plain handle of at most 2048 columns
- *                        and 16384 64-height column chunks runs each global
- *                        relabel as one block with its records (and, when
- *                        both fit in 160 KB, its bit masks) in LDS (no launch
- *                        or host poll per level); 0: always one launch per level
+ *   "block_search"    -- 1 (default): when every volume of the handle has at
+ *                        most 2048 columns and 16384 64-height column chunks,
+ *                        each global relabel runs as one block per volume
+ *                        with its records (and, when both fit in 160 KB, its
+ *                        bit masks) in LDS (no launch or host poll per level;
+ *                        in a batch the blocks also stop once search_quorum of
+ *                        the volumes have ended); 0: always one launch per level
  *   "hmax"            -- 1: every solve also reads out the highest optimal
  *                        surface (smf_surface_max) with one complete global
  *                        relabel after termination; the first 1 allocates

@@ -78,6 +78,10 @@ struct Geom {
     // flow), kMaskFd (down arc carries flow).
     unsigned long long *bits;
     int max_nch;
+    // the largest volume's columns and 64-height column chunks (whether every
+    // volume's search fits one block)
+    int max_cols;
+    long long max_chunks;
     // With soft smoothness (some volume has alpha > 0): four more masks,
     // bit set where the soft arc (p,z) -> (q_k,z) is residual, stored like
     // `bits` (sbits[(k * max_nch + w) * Ptot + p]); soft is 0 otherwise and
@@ -144,6 +148,7 @@ struct Scratch {
     int count[2];        // sizes of the two column work lists
     int short_count;     // size of the running global relabel's short-column list
     int block_levels;    // levels run by one-block searches since the solve began
+    int block_done;      // volumes whose one-block search has ended (the running search)
 };
 constexpr int kScratchHead = 64;
 static_assert(sizeof(Scratch) <= kScratchHead, "Scratch must fit its header");

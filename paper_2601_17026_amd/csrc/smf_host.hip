@@ -39,7 +39,7 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
 bool bfs_block_fits(const Geom &g);
 void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
-                      int max_level, Scratch *s, hipStream_t st);
+                      int max_level, int quorum, Scratch *s, hipStream_t st);
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
@@ -171,6 +171,7 @@ constexpr int64_t kMaxAlpha = 1LL << 29;   // soft residuals alpha - f + f' stay
 struct smf_handle {
     Geom g{};
     int device = 0;
+    int cus = 0;                  // compute units of the device
     int n = 0;
     std::vector<Inst> inst;       // host copy of the volume table
     long long max_inst_nodes = 0;
@@ -369,6 +370,10 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
         fail(SMF_ERR_HIP, std::string("smf_batch_create: no usable HIP device: ") + hipGetErrorString(dev_err));
         return nullptr;
     }
+    if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+        (void)hipGetLastError();
+        h->cus = 0;   // no quorum in block searches
+    }
     if (!dev_alloc(h->inst_dev, n) ||
         !dev_alloc(h->col_inst, P) || !dev_alloc(h->cnt_dev, counter_bytes(n)) || !dev_alloc(h->part_dev, n) ||
         !dev_alloc(h->fill_dev, n) || !dev_alloc(h->state, 8 * N) || !dev_alloc(h->H, P) ||
@@ -411,6 +416,12 @@ extern "C" smf_handle *smf_batch_create(int32_t n, const int32_t *nx, const int3
     g.hist_len = kHistLen;
     g.bits = h->bits;
     g.max_nch = max_nch;
+    g.max_cols = 0;
+    g.max_chunks = 0;
+    for (int i = 0; i < n; ++i) {
+        g.max_cols = std::max(g.max_cols, inst[i].P);
+        g.max_chunks = std::max(g.max_chunks, (long long)inst[i].P * inst[i].nch);
+    }
     g.level_block = 256;
     g.sweep_waves = 8192;
     g.soft = 0;
@@ -582,8 +593,18 @@ struct Search {
             // a small single volume: the whole search in one block, no polls
             {
                 TimedScope ts(h->timer, KC_BFS, s);
+                // the quorum rule of batch searches: the blocks stop once
+                // that many volumes' searches have ended
+                int npart = 0;
+                for (int i = 0; i < n; ++i) npart += part[i] ? 1 : 0;
+                // (only while every volume's block can be resident at once:
+                // a block that starts after the quorum would stop at once)
+                const int quorum = npart > 1 && npart <= h->cus
+                                       ? std::max<int>(1, (int)((h->search_quorum * npart + 99) / 100))
+                                       : INT_MAX;
+                launch_set_int(&h->scr->block_done, 0, s);
                 launch_bfs_block(h->g, h->st, T[1], LF[1], (int)early_stop,
-                                 (int)std::min<int64_t>(h->max_inst_nodes + 2, INT32_MAX), h->scr, s);
+                                 (int)std::min<int64_t>(h->max_inst_nodes + 2, INT32_MAX), quorum, h->scr, s);
             }
             HIP_TRY(hipGetLastError());
             whole = true;

@@ -424,6 +424,7 @@ __global__ void k_init_scratch(Geom g, Scratch *s)
         s->err = 0;
         s->changed = 0;
         s->block_levels = 0;
+        s->block_done = 0;
         s->count[0] = 0;
         s->count[1] = 0;
     }
@@ -1058,18 +1059,19 @@ constexpr int kFdAtT = 0x40000000;           // flow on the down arc into (p, T)
 constexpr int kTMask = 0x3fffffff;           // the threshold bits
 
 // Word w of bit mask m of column p.
-// Where a level reads the bit masks: word w of mask m of column p is
-// bits[(m * nch + w) * P + p] (the global masks, or a copy in LDS).
+// Where a level reads the bit masks: word w of mask m of global column p is
+// bits[(m * nch + w) * P + p - off] (the global masks, off 0, or a volume's
+// copy in LDS, off its first column).
 struct MaskSrc {
     const unsigned long long *bits;
-    int nch, P;
+    int nch, P, off;
     __device__ unsigned long long word(int m, int w, int p) const
     {
-        return bits[((size_t)m * nch + w) * P + p];
+        return bits[((size_t)m * nch + w) * P + (p - off)];
     }
 };
 
-__device__ __forceinline__ MaskSrc global_masks(const Geom &g) { return MaskSrc{g.bits, g.max_nch, g.Ptot}; }
+__device__ __forceinline__ MaskSrc global_masks(const Geom &g) { return MaskSrc{g.bits, g.max_nch, g.Ptot, 0}; }
 
 // Bits [lo, hi) of the heights 64w..64w+63 (lo < 64(w+1), hi > 64w).
 __device__ __forceinline__ unsigned long long range_bits(int w, int lo, int hi)
@@ -1513,10 +1515,11 @@ __global__ __launch_bounds__(1024) void k_bfs_level(Geom g, int *__restrict__ d,
     if (g.count_work) count_bytes(g, 0, bytes);
 }
 
-// A whole search of one small volume in one block (a plain handle of at
-// most kBlockSearchCols columns): the records live in LDS, double-buffered
-// as in global memory, and block barriers separate the levels instead of
-// launches and host polls.  Level 1 comes from k_bfs_init (records T1,
+// A whole search of small volumes, one block per volume (block i takes
+// volume i when it takes part; every volume of at most kBlockSearchCols
+// columns): the records live in LDS, double-buffered as in global memory,
+// and block barriers separate the levels instead of launches and host
+// polls.  Level 1 comes from k_bfs_init (records T1,
 // LF1).  The search ends when a level labels nothing (unreached nodes get
 // kInf) or, with early_stop, once no column's threshold lies above its
 // lowest active node (unreached nodes get the first level not run).  The
@@ -1531,20 +1534,23 @@ static_assert(kBlockSearchCols <= kBlockSearchSlots * 1024, "a one-block search 
 template <bool kSoft, bool kStage>
 __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d, const int *__restrict__ T1,
                                                    const int *__restrict__ LF1, int early_stop,
-                                                   int max_level, Scratch *s)
+                                                   int max_level, int quorum, Scratch *s)
 {
     extern __shared__ unsigned long long sml[];
     int *const sm = reinterpret_cast<int *>(sml);
-    const int P = g.Ptot;
+    const int ii = blockIdx.x;
+    if (!g.part[ii]) return;
+    const Inst I = g.inst[ii];
+    // local columns p of the volume are global columns c0 + p
+    const int P = I.P, c0 = I.col_base, Ptot = g.Ptot;
     // records of level L in buffer L & 1: thresholds at sm + (L & 1) P,
     // lowest-flow records at sm + 2P + 4P (L & 1); the buffers are picked by
     // arithmetic on the LDS base, so the compiler keeps LDS accesses
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        sm[P + i] = T1[i];
+        sm[P + i] = T1[c0 + i];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sm[6 * P + k * P + i] = LF1[(size_t)k * P + i];
+        for (int k = 0; k < 4; ++k) sm[6 * P + k * P + i] = LF1[(size_t)k * Ptot + c0 + i];
     }
-    const Inst I = g.inst[0];
     // kStage: the level-1 bit masks are copied into LDS after the records
     // (40 bytes per column and chunk), so that a level reads no global
     // memory and only writes its labels there
@@ -1553,26 +1559,29 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
         const int per = I.nch * P;
         for (int i = threadIdx.x; i < kMasks * per; i += blockDim.x) {
             const int m = i / per, r = i - m * per, w = r / P, p = r - w * P;
-            sb[i] = g.bits[((size_t)m * g.max_nch + w) * P + p];
+            sb[i] = g.bits[((size_t)m * g.max_nch + w) * Ptot + c0 + p];
         }
     }
-    const MaskSrc ms = kStage ? MaskSrc{sb, I.nch, P} : global_masks(g);
+    const MaskSrc ms = kStage ? MaskSrc{sb, I.nch, P, c0} : global_masks(g);
     // each thread's lowest active heights, for the early stop
     int la[kBlockSearchSlots];
 #pragma unroll
     for (int j = 0; j < kBlockSearchSlots; ++j) {
         const int p = j * (int)blockDim.x + (int)threadIdx.x;
-        la[j] = p < P ? g.low_act[p] : 0;
+        la[j] = p < P ? g.low_act[c0 + p] : 0;
     }
     __syncthreads();
     const int slots = (P + (int)blockDim.x - 1) / (int)blockDim.x;
     // per level L, red[L % 3] gathers bit 0: a column moved, bit 1: a column
-    // is still short of its lowest active node
+    // is still short of its lowest active node, bit 2: `quorum` volumes'
+    // searches have ended (s->block_done, read once per level by thread 0),
+    // which ends this one too
     __shared__ int red[3];
     if (threadIdx.x < 3) red[threadIdx.x] = 0;
     __syncthreads();
     // the geometry of the thread's columns, fixed for the whole search:
-    // node (p, 0), the neighbours and the band shifts
+    // node (p, 0), the neighbours (local columns, -1: none) and the band
+    // shifts
     long long cbase[kBlockSearchSlots];
     int cq[kBlockSearchSlots][4];
     BandCol cbc[kBlockSearchSlots];
@@ -1580,12 +1589,16 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
     for (int j = 0; j < kBlockSearchSlots; ++j) {
         // a slot past the last column takes column 0's geometry, unused
         const int pj = j * (int)blockDim.x + (int)threadIdx.x;
-        const int p = pj < P ? pj : 0;
-        const Col col = column_in(I, 0, p);
+        const int p = c0 + (pj < P ? pj : 0);
+        const Col col = column_in(I, ii, p);
         cbase[j] = (long long)col.base;
+        int qg[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) cq[j][k] = nbr(I.nx, I.ny, col.x, col.y, p, k);
-        band_col(g, p, cq[j], I.K, I.delta, cbc[j]);
+        for (int k = 0; k < 4; ++k) {
+            qg[k] = nbr(I.nx, I.ny, col.x, col.y, p, k);
+            cq[j][k] = qg[k] >= 0 ? qg[k] - c0 : -1;
+        }
+        band_col(g, p, qg, I.K, I.delta, cbc[j]);
     }
     long long bytes = 0;
     int L = 1, cur = 1, run = 0;
@@ -1627,8 +1640,8 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
                 b = 8;
                 if (near) {
                     bool fd_new = false;
-                    b += 16 + 8 * level_update<kSoft>(g, ms, p, I.K, cbc[j], I.alpha, T, (tw & kFdAtT) != 0, tq,
-                                                      lq, lf, cand, fd_new);
+                    b += 16 + 8 * level_update<kSoft>(g, ms, c0 + p, I.K, cbc[j], I.alpha, T, (tw & kFdAtT) != 0,
+                                                      tq, lq, lf, cand, fd_new);
                     need = cand < T;
                     if (need) tword = cand | (fd_new ? kFdAtT : 0) | kChanged;
                 }
@@ -1662,7 +1675,11 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
         // levels L - 2 and L - 1
         const int wf = (__ballot(moved) ? 1 : 0) | (__ballot(short_col) ? 2 : 0);
         if (lane_id() == 0 && wf) atomicOr(&red[L % 3], wf);
-        if (threadIdx.x == 0) red[(L + 1) % 3] = 0;
+        if (threadIdx.x == 0) {
+            red[(L + 1) % 3] = 0;
+            if (__hip_atomic_load(&s->block_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= quorum)
+                atomicOr(&red[L % 3], 4);
+        }
         __syncthreads();
         const int f = red[L % 3];
         const bool any_m = f & 1, any_s = f & 2;
@@ -1670,11 +1687,12 @@ __global__ __launch_bounds__(1024) void k_bfs_block(Geom g, int *__restrict__ d,
             complete = true;   // level L labelled nothing
             break;
         }
-        if (early_stop && !any_s) {
+        if ((early_stop && !any_s) || (f & 4)) {
             ++L;   // levels <= L are done: unreached nodes lie beyond L + 1
             break;
         }
     }
+    if (threadIdx.x == 0) atomicAdd(&s->block_done, 1);
     // fix-up: L is the first level whose labels were not all written
     const int fill = complete ? kInf : L + 1;
     for (long long v = threadIdx.x; v < (long long)I.N; v += blockDim.x)
@@ -1986,15 +2004,16 @@ constexpr long long kBlockSearchChunks = 16384;
 
 bool bfs_block_fits(const Geom &g)
 {
-    return g.n == 1 && g.Ptot <= kBlockSearchCols && (long long)g.Ptot * g.max_nch <= kBlockSearchChunks;
+    return g.max_cols <= kBlockSearchCols && g.max_chunks <= kBlockSearchChunks;
 }
 
 void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
-                      int max_level, Scratch *s, hipStream_t st)
+                      int max_level, int quorum, Scratch *s, hipStream_t st)
 {
     // records, and the masks when they fit beside them
-    const size_t rec = sizeof(int) * 10 * (size_t)g.Ptot;
-    const size_t masks = sizeof(unsigned long long) * kMasks * (size_t)g.max_nch * g.Ptot;
+    // LDS for the largest volume; one block per volume
+    const size_t rec = sizeof(int) * 10 * (size_t)g.max_cols;
+    const size_t masks = sizeof(unsigned long long) * kMasks * (size_t)g.max_chunks;
     // (1 KB of the 160 KB stays free for the kernel's static LDS)
     const int stage = rec + masks + 1024 <= kBlockSearchLds ? 1 : 0;
     const size_t lds = rec + (stage ? masks : 0);
@@ -2011,19 +2030,19 @@ void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *
     (void)raised;
     if (stage) {
         if (g.soft)
-            hipLaunchKernelGGL((k_bfs_block<true, true>), dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1,
-                               early_stop, max_level, s);
+            hipLaunchKernelGGL((k_bfs_block<true, true>), dim3(g.n), dim3(1024), lds, st, g, sv.d, T1, LF1,
+                               early_stop, max_level, quorum, s);
         else
-            hipLaunchKernelGGL((k_bfs_block<false, true>), dim3(1), dim3(1024), lds, st, g, sv.d, T1, LF1,
-                               early_stop, max_level, s);
+            hipLaunchKernelGGL((k_bfs_block<false, true>), dim3(g.n), dim3(1024), lds, st, g, sv.d, T1, LF1,
+                               early_stop, max_level, quorum, s);
         return;
     }
     if (g.soft)
-        hipLaunchKernelGGL((k_bfs_block<true, false>), dim3(1), dim3(1024), rec, st, g, sv.d, T1, LF1, early_stop,
-                           max_level, s);
+        hipLaunchKernelGGL((k_bfs_block<true, false>), dim3(g.n), dim3(1024), rec, st, g, sv.d, T1, LF1, early_stop,
+                           max_level, quorum, s);
     else
-        hipLaunchKernelGGL((k_bfs_block<false, false>), dim3(1), dim3(1024), rec, st, g, sv.d, T1, LF1,
-                           early_stop, max_level, s);
+        hipLaunchKernelGGL((k_bfs_block<false, false>), dim3(g.n), dim3(1024), rec, st, g, sv.d, T1, LF1,
+                           early_stop, max_level, quorum, s);
 }
 
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st)

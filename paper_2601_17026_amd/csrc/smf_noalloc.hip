@@ -19,6 +19,8 @@
 // written by the solve first.  Calls that overlap on one GPU race.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <atomic>
 #include <cstdio>
 #include <string>
@@ -39,7 +41,7 @@ void launch_bfs_level(const Geom &g, const State &sv, int L, const int *Tin, con
 void launch_bfs_fixup(const Geom &g, const State &sv, int c0, int c1, hipStream_t st);
 bool bfs_block_fits(const Geom &g);
 void launch_bfs_block(const Geom &g, const State &sv, const int *T1, const int *LF1, int early_stop,
-                      int max_level, Scratch *s, hipStream_t st);
+                      int max_level, int quorum, Scratch *s, hipStream_t st);
 void launch_bfs_count(const Geom &g, const int *T, int slot, hipStream_t st);
 void launch_push(const Geom &g, const State &sv, const Work &win, const Work &wout, Scratch *s,
                  bool down, hipStream_t st);
@@ -160,7 +162,7 @@ int search(Run &r)
     launch_set_int(g.short_count, 0, r.s);
     launch_bfs_init(g, r.st, r.T[1], r.LF[1], 0, P, r.s);   // level 1 lives in buffer 1
     if (bfs_block_fits(g)) {
-        launch_bfs_block(g, r.st, r.T[1], r.LF[1], 1, (int)(r.N + 2), r.scr, r.s);
+        launch_bfs_block(g, r.st, r.T[1], r.LF[1], 1, (int)(r.N + 2), INT_MAX, r.scr, r.s);   // one volume: no quorum
         NA_TRY(hipGetLastError());
         return SMF_OK;
     }
@@ -310,6 +312,8 @@ extern "C" int smf_solve_noalloc(const int32_t *cost_dev, int32_t nx, int32_t ny
     g.hist_len = 0;
     g.bits = reinterpret_cast<unsigned long long *>(base + l.bits);
     g.max_nch = nch;
+    g.max_cols = (int)P;
+    g.max_chunks = (long long)P * nch;
     g.sbits = nullptr;
     g.soft = 0;
     g.low_act = bfs + 10 * P;

@@ -128,12 +128,15 @@ def test_batch_per_volume_periods(smf):
 
 @pytest.mark.parametrize("params", [
     {"gap_every": 1},
-    {"bfs_early_stop": 0},
     {"poll_every": 3, "bfs_poll_every": 2},
     {"relabel_period": 1},
+    {"block_search": 0},
     {"search_quorum": 100},
-    {"search_quorum": 1},
-    {"search_quorum": 50, "bfs_early_stop": 0},
+    {"search_quorum": 50},
+    {"search_quorum": 100, "block_search": 0},
+    {"search_quorum": 1, "block_search": 0},
+    {"search_quorum": 50, "bfs_early_stop": 0, "block_search": 0},
+    {"bfs_early_stop": 0},
 ])
 def test_batch_parameter_variants(smf, params):
     vols = _volumes(SHAPES, seed0=1100)
