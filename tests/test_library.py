@@ -160,3 +160,13 @@ def test_device_memory_budget_refuses_before_allocating(monkeypatch):
     lib = smf._lib
     assert lib.smf_create(64, 64, 64, 1) is None
     assert b"more than SMF_DEVICE_MEM_LIMIT" in lib.smf_last_error()
+
+
+def test_every_parameter_key_is_documented():
+    # every key smf_set_param accepts is described in the header
+    host = open(os.path.join(ROOT, "paper_2601_17026_amd", "csrc", "smf_host.hip")).read()
+    body = host[host.index('extern "C" int smf_set_param('):host.index('extern "C" int smf_batch_set_param(')]
+    keys = set(re.findall(r'strcmp\(key, "([a-z_]+)"\)', body))
+    assert {"relabel_period", "push_phases", "search_quorum", "block_search"} <= keys
+    text = open(HEADER).read()
+    assert not [k for k in sorted(keys) if f'"{k}"' not in text]
