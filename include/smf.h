@@ -222,7 +222,9 @@ int smf_set_band(smf_handle *h, const int32_t *offset_host, const int32_t *exten
  *                        volumes once this percentage of them has ended (1..100,
  *                        default 90); the nodes of the others that no level
  *                        reached get the first level not run as their label,
- *                        a valid lower bound of their distance to t
+ *                        a valid lower bound of their distance to t (the
+ *                        complete global relabel of "hmax" always runs to its
+ *                        end)
  *   "block_search"    -- 1 (default): when every volume of the handle has at
  *                        most 2048 columns and 16384 64-height column chunks,
  *                        each global relabel runs as one block per volume

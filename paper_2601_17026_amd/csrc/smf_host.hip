@@ -532,6 +532,7 @@ struct Search {
     int L = 1, cur = 1, slot = 0, npoll = 0, inflight = 0;
     int Lsnap[2] = {0, 0}, Csnap[2] = {0, 0};
     bool whole = false;   // nothing to do, or the one-block search already ran
+    bool exact = false;   // a complete search: no early stop and no quorum
     int *T[2] = {}, *LF[2] = {};
 
     int begin(smf_handle *hh, hipStream_t ss, const std::vector<char> &p, bool complete)
@@ -542,6 +543,7 @@ struct Search {
         // a complete search runs until a level labels nothing, whatever
         // bfs_early_stop says
         early_stop = complete ? 0 : h->bfs_early_stop;
+        exact = complete;
         const size_t P = (size_t)h->g.Ptot;
         T[0] = h->bfs;
         T[1] = h->bfs + 5 * P;
@@ -599,7 +601,7 @@ struct Search {
                 for (int i = 0; i < n; ++i) npart += part[i] ? 1 : 0;
                 // (only while every volume's block can be resident at once:
                 // a block that starts after the quorum would stop at once)
-                const int quorum = npart > 1 && npart <= h->cus
+                const int quorum = !exact && npart > 1 && npart <= h->cus
                                        ? std::max<int>(1, (int)((h->search_quorum * npart + 99) / 100))
                                        : INT_MAX;
                 launch_set_int(&h->scr->block_done, 0, s);
@@ -676,8 +678,10 @@ struct Search {
             }
         }
         // the volumes still searching when the quorum has ended take the
-        // first level not run as their fill label, a valid lower bound
-        if (!all && 100 * (int64_t)(npart - nlive) >= h->search_quorum * npart) all = true;
+        // first level not run as their fill label, a valid lower bound (not
+        // in a complete search, whose unreached nodes must be exactly those
+        // that cannot reach t)
+        if (!exact && !all && 100 * (int64_t)(npart - nlive) >= h->search_quorum * npart) all = true;
         if (all) {
             // levels < L are complete now (the batches after the snapshot
             // included); a volume still covered takes the latest fill

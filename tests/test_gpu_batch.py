@@ -234,3 +234,27 @@ def test_search_quorum_checked(smf):
                 b.set_param("search_quorum", v)
         b.set_param("search_quorum", 1)
         b.set_param("search_quorum", 100)
+
+
+@pytest.mark.parametrize("block", [1, 0])
+def test_batch_hmax_matches_oracle(smf, block):
+    # the complete search of the h_max read-out runs to its end in every
+    # volume of a batch, whatever the search quorum: small cost ranges give
+    # columns whose optimal height is not unique
+    shapes = [(20, 24, 30, 1), (9, 11, 60, 3), (30, 30, 40, 2), (5, 7, 9, 0), (16, 12, 70, 2)]
+    vols = [synth.random_cost(nx, ny, K, 0, 4, seed=2600 + i) for i, (nx, ny, K, _) in enumerate(shapes)]
+    print(f"case: batch hmax, block_search {block}", flush=True)
+    with smf.BatchSolver(shapes) as b:
+        b.set_param("hmax", 1)
+        b.set_param("block_search", block)
+        b.set_param("search_quorum", 1)
+        b.solve(b.pack([torch.from_numpy(v).cuda() for v in vols]))
+        hmin = [s.cpu().numpy() for s in b.unpack_surfaces(b.surfaces())]
+        hmax = [s.cpu().numpy() for s in b.unpack_surfaces(b.surfaces_max())]
+    ties = 0
+    for i, ((nx, ny, K, dl), v) in enumerate(zip(shapes, vols)):
+        r = oracle.solve(v, dl)
+        np.testing.assert_array_equal(hmin[i], r.hmin, err_msg=f"volume {i}")
+        np.testing.assert_array_equal(hmax[i], r.hmax, err_msg=f"volume {i}")
+        ties += int((r.hmax > r.hmin).sum())
+    assert ties > 0
