@@ -592,7 +592,7 @@ struct Search {
             launch_bfs_init(h->g, h->st, T[1], LF[1], c0, c1, s);   // level 1 lives in buffer 1
         }
         if (h->block_search && bfs_block_fits(h->g)) {
-            // a small single volume: the whole search in one block, no polls
+            // small volumes: each volume's whole search in one block, no polls
             {
                 TimedScope ts(h->timer, KC_BFS, s);
                 // the quorum rule of batch searches: the blocks stop once
