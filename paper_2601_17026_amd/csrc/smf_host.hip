@@ -220,7 +220,7 @@ struct smf_handle {
     int64_t poll_every = 1;
     int64_t bfs_poll_every = 16;
     int64_t bfs_early_stop = 1;
-    int64_t block_search = 1;      // small single volumes: whole searches in one block
+    int64_t block_search = 1;      // small volumes: each whole search in one block per volume
     int64_t verbose = 0;           // 1: progress lines on stderr
     int64_t gap_every = 0;         // sweeps between gap searches (0: off)
     int64_t want_hmax = 0;         // 1: also read out the highest optimal surface
@@ -511,7 +511,7 @@ static bool shrink_cover(const smf_handle *h, const std::vector<char> &live, std
 
 // One global relabel (reverse breadth-first search from t) of the volumes
 // with part[i], as a resumable state on one stream: begin() enqueues level 1
-// (or, for a small single volume, the whole search in one block), step() the
+// (or, for small volumes, each whole search in one block), step() the
 // next batch of bfs_poll_every levels with the early-stop count and a
 // counter snapshot, examine() reads the oldest snapshot in flight and
 // decides which volumes' searches have ended, and finish() enqueues the
